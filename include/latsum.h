@@ -1,0 +1,216 @@
+/*
+ * latsum: assembled canonical-tensor lattice summation of Newton potentials
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: V. Khoromskaia, B. N. Khoromskij, "Grid-based lattice summation of
+ * electrostatic potentials by assembled rank-structured tensor approximation"
+ * (arXiv 1405.2270). Section, equation and theorem labels below are the
+ * paper's.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Unit cell [-b/2, b/2]^3, n cells of size h = b/n per edge (Sec. 2.1).
+ *    Box case: lattice shifts b*k, k_l = 0..L_l-1; the grid of axis l has
+ *    N_l = L_l * n cells, cell g spanning [-b/2 + g h, -b/2 + (g+1) h]
+ *    (Sec. 3.1, eq. N0grid). Periodic case: only the reference cell is
+ *    resolved (N_l = n) and the images are k = -p..p for L = 2p+1, and
+ *    -L/2..L/2-1 for even L (Sec. 3.2, eq. EwaldSumP, Lemma 3.2).
+ *  - Charges: M0 positions a_nu in physical coordinates inside the unit cell,
+ *    row-major [M0][3] FP64, and charges Z_nu [M0] FP64, both in device
+ *    memory. Positions need not be grid nodes: every cell integral is taken
+ *    at the continuous position.
+ *  - Canonical format (Appendix, eq. CP_form): rank index r = nu*R + q;
+ *    factor matrices f[l] are vector-contiguous [K][N_l] FP64 in device
+ *    memory, and coef[r] = Z_nu w_q is kept apart, FP64.
+ *  - Every pointer argument named *_dev is device memory owned by the caller;
+ *    struct descriptors and other pointers are host memory read during the
+ *    call only. The library allocates no device memory and keeps no pointer
+ *    after a call returns.
+ *  - Arguments are checked on the host before anything is enqueued; a
+ *    failing check returns a negative ls_status and enqueues nothing.
+ *    ls_last_error() then describes the failure (thread-local).
+ *  - Work is enqueued on `stream` (0 = the null stream) and runs
+ *    asynchronously; outputs are valid after the stream is synchronised.
+ *    A launch failure returns LS_EHIP.
+ */
+#ifndef LATSUM_H
+#define LATSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LS_OK = 0,
+  LS_EINVAL = -1,        /* invalid argument */
+  LS_EHIP = -2,          /* HIP runtime or launch error */
+  LS_EUNSUPPORTED = -3,  /* valid but not implemented combination */
+  LS_EWORKSPACE = -4     /* workspace missing or too small */
+} ls_status;
+
+typedef enum {
+  LS_F64 = 0,     /* FP64 operands, FP64 MFMA, FP64 output */
+  LS_F32 = 1,     /* operands rounded to FP32, FP32 MFMA, FP32 output */
+  LS_BF16X3 = 2,  /* operands split into 2 bf16 terms, 3 bf16 MFMA products, FP32 accumulate/output */
+  LS_BF16X6 = 3   /* operands split into 3 bf16 terms, 6 bf16 MFMA products, FP32 accumulate/output */
+} ls_precision;
+
+typedef enum {
+  LS_RULE_U = 0,  /* t_k = k h_M, w_k = h_M/sqrt(pi), k = -M..M (eqs. sinc_Newt, hM) */
+  LS_RULE_S = 1   /* t_q = s sinh(q h_M), q = 0..M, folded (R = M+1) */
+} ls_rule;
+
+typedef struct {
+  int32_t n;         /* grid cells per unit-cell edge, >= 1 */
+  int32_t L[3];      /* lattice cells per axis, >= 1 */
+  double b;          /* unit-cell edge length, > 0 */
+  int32_t periodic;  /* 0: box (Theorem 3.1), 1: periodic reference cell (Lemma 3.2) */
+} ls_lattice;
+
+typedef struct {
+  int32_t R;         /* number of quadrature terms = canonical rank of one kernel */
+  const double* t;   /* host [R], nodes t_q >= 0 (1/length) */
+  const double* w;   /* host [R], weights w_q (1/length) */
+} ls_quad;
+
+typedef struct {
+  int32_t K;            /* rank */
+  int32_t len[3];       /* vector length per axis */
+  const double* f[3];   /* device [K][len[l]] FP64 factor matrices */
+  const double* coef;   /* device [K] FP64 weights */
+} ls_canon;
+
+typedef struct {
+  int32_t o[3];  /* origin in cells */
+  int32_t e[3];  /* extent in cells, >= 1; o + e <= len per axis */
+} ls_box;
+
+/* Version string of the library. */
+const char* ls_version(void);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char* ls_last_error(void);
+
+/*
+ * Quadrature table (Sec. 2.1, eqs. laplace, sinc_Newt, hM) on the host.
+ * The printed weight h_M lacks the 1/sqrt(pi) of eq. laplace; it is included.
+ *   rule U: h_M = C0 log(M)/M, t_k = k h_M, w_k = h_M/sqrt(pi), k = -M..M, R = 2M+1.
+ *   rule S: h_M = C0 log(M)/M, t_q = s sinh(q h_M), w_0 = s h_M/sqrt(pi),
+ *           w_q = 2 s h_M cosh(q h_M)/sqrt(pi), q = 0..M, R = M+1
+ *           (the sinh-substituted sinc rule, folded over +-q).
+ * t, w: host arrays of `capacity` doubles; *R receives the term count.
+ * Errors: LS_EINVAL for M < 2, C0 <= 0, s <= 0 (rule S), unknown rule,
+ * capacity < R or null pointers.
+ */
+ls_status ls_quadrature(int32_t rule, int32_t M, double C0, double s,
+                        double* t, double* w, int32_t capacity, int32_t* R);
+
+/*
+ * Half-width X (cells) of the master grid (eq. master_pot generalised to the
+ * lattice): master index j in [-X, X) covers every offset g - p - k n that an
+ * assembled sum needs on any axis. Box: X = max_l N_l. Periodic:
+ * X = (max_l L_l div 2 + 1) n. Host only.
+ */
+ls_status ls_master_halfwidth(const ls_lattice* lat, int32_t* X);
+
+/*
+ * Kernel vectors (Sec. 2.1, eqs. C_nD_0, galten_int; eq. master_pot):
+ * for every atom nu, axis l and term q the master vector on 2X cells,
+ *   masters_dev[((nu*3 + l)*R + q)*2X + j + X]
+ *     = integral over [(j - delta) h, (j + 1 - delta) h] of exp(-t_q^2 y^2) dy,
+ * where (a_{nu,l} + b/2)/h = p + delta with integer p and 0 <= delta < 1.
+ * With derivative != 0 the entries are the derivatives of the same cell
+ * integrals with respect to the charge position,
+ *   exp(-t_q^2 ((j - delta) h)^2) - exp(-t_q^2 ((j + 1 - delta) h)^2).
+ * All arithmetic is FP64. X must be ls_master_halfwidth(lat).
+ * masters_dev: device, M0*3*R*2X doubles, written.
+ * Errors: LS_EINVAL (null pointers, M0 < 1, R < 1, t < 0, X mismatch).
+ */
+ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                            const double* pos_dev, int32_t X, int32_t derivative,
+                            double* masters_dev, hipStream_t stream);
+
+/*
+ * Assembled canonical vectors (Theorem 3.1, eq. EwaldTensorM0 for the box;
+ * Lemma 3.2 for the periodic cell): for r = nu*R + q and each axis l,
+ *   f_l[r][g] = sum over images k of b_{g - p - k n}(t_q; delta),
+ * i.e. the pointwise sum of shifted windows of the master vector, and
+ * coef[r] = Z_nu w_q.
+ * masters_dev: the output of ls_kernel_vectors for the same lattice and X, or
+ * NULL to generate every cell integral in registers (L integrals per entry).
+ * The periodic case always generates in registers, since each master entry is
+ * used exactly once there; masters_dev must be NULL for it. With
+ * derivative != 0 the vectors are position derivatives (masters must then be
+ * derivative masters or NULL) and coef_dev may be NULL.
+ * f0_dev, f1_dev, f2_dev: device [K][N_l] FP64, written. coef_dev: device [K].
+ * Errors: LS_EINVAL.
+ */
+ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                      const double* pos_dev, const double* Z_dev, const double* masters_dev,
+                      int32_t X, int32_t derivative, double* f0_dev, double* f1_dev,
+                      double* f2_dev, double* coef_dev, hipStream_t stream);
+
+/*
+ * Reconstruction of sub-boxes of a canonical tensor (Appendix, eq. CP_form):
+ *   out_b[i][j][k] = scale * sum_r coef[r] f0[r][o0+i] f1[r][o1+j] f2[r][o2+k]
+ * for each box b, as one GEMM per box with rows (i, j), columns k and the
+ * Khatri-Rao operand formed on the fly, on MFMA in the requested precision.
+ * scale = 1/h^3 gives cell averages of the potential; 1 gives the raw tensor.
+ * out_dev: device; boxes are stored one after another, each [e0][e1][e2]
+ * C-order; element type double for LS_F64, float otherwise.
+ * boxes: host [nbox]. tile: 0 = automatic, otherwise a tile id from
+ * ls_reconstruct_tiles (used by the autotuner).
+ * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
+ * LS_EUNSUPPORTED (tile id not valid for the precision).
+ */
+ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
+                         int32_t precision, int32_t tile, void* out_dev, hipStream_t stream);
+
+/* Number of reconstruction tile variants for a precision (for autotuning). */
+int32_t ls_reconstruct_tiles(int32_t precision);
+
+/*
+ * Energy as a canonical scalar product (Appendix, eq. scal) with a density
+ * rho in canonical form sampled at cell midpoints (Sec. 2.2, Example 2.1):
+ *   E = sum_r sum_s coef[r] d[s] prod_l G_l[r][s],  G_l = f_l rho_l^T.
+ * P and rho must have equal len[]. precision LS_F64 or LS_F32 (Gram products
+ * and per-lane sums in FP32; all reductions across lanes and the final sum in
+ * FP64). E_dev: device, one double. ws_dev: device workspace of at least
+ * ls_energy_workspace(P->K, rho->K) bytes; on return it holds the Grams
+ * G_l[r][s] at ((l*K + r)*Krho + s) as FP64.
+ * Errors: LS_EINVAL, LS_EWORKSPACE, LS_EUNSUPPORTED (bf16 precisions).
+ */
+size_t ls_energy_workspace(int32_t K, int32_t Krho);
+ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t precision,
+                    double* E_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Forces on the unit-cell atoms, F[nu][l] = -dE/da_{nu,l}, with the energy
+ * of the previous entry point, by the adjoint of the assembled vectors:
+ * moving a_nu moves all its lattice images, so
+ *   dE/da_{nu,l} = Z_nu sum_q w_q sum_s d_s G'_l[nu q][s] prod_{l' != l} G_l'[nu q][s],
+ * where G'_l pairs the position derivative of each master vector with the
+ * density folded back over the lattice shifts (the transpose of the shift
+ * sum). Value Grams use the same folded density, so E is produced as well.
+ * rho: density in canonical form with len[l] = N_l of the lattice.
+ * precision: LS_F64 or LS_F32 (FP32 products and per-lane sums in the Grams;
+ * cell integrals, folded density and every reduction across lanes in FP64).
+ * F_dev: device [M0][3]. E_dev: device scalar or NULL.
+ * ws_dev: at least ls_forces_workspace(lat, M0, R, rho->K) bytes.
+ * Errors: LS_EINVAL, LS_EWORKSPACE, LS_EUNSUPPORTED.
+ */
+size_t ls_forces_workspace(const ls_lattice* lat, int32_t M0, int32_t R, int32_t Krho);
+ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                    const double* pos_dev, const double* Z_dev, const ls_canon* rho,
+                    int32_t precision, double* F_dev, double* E_dev,
+                    void* ws_dev, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATSUM_H */

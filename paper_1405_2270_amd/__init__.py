@@ -1,0 +1,14 @@
+"""latsum for MI355X: assembled canonical-tensor lattice sums of Newton potentials.
+
+Hot path (Khoromskaia & Khoromskij, arXiv 1405.2270): quadrature table ->
+kernel vectors -> lattice assembly -> energy / reconstruction, plus forces by
+the adjoint. All arithmetic runs in the HIP library ``liblatsum.so``; this
+package only marshals torch tensors into its C ABI.
+"""
+from .api import (LatticeSpec, QuadTable, quadrature, master_halfwidth, kernel_vectors, assemble,
+                  reconstruct, reconstruct_into, reconstruct_tiles, energy, forces, LatticeEnergy,
+                  lattice_energy)
+
+__all__ = ["LatticeSpec", "QuadTable", "quadrature", "master_halfwidth", "kernel_vectors",
+           "assemble", "reconstruct", "reconstruct_into", "reconstruct_tiles", "energy", "forces",
+           "LatticeEnergy", "lattice_energy"]

@@ -1,0 +1,98 @@
+"""ctypes binding of liblatsum.so (argument marshalling only).
+
+The library is loaded from this package directory; there is no fallback: if
+it is missing or fails to load, every call raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblatsum.so")
+
+LS_OK, LS_EINVAL, LS_EHIP, LS_EUNSUPPORTED, LS_EWORKSPACE = 0, -1, -2, -3, -4
+LS_F64, LS_F32, LS_BF16X3, LS_BF16X6 = 0, 1, 2, 3
+LS_RULE_U, LS_RULE_S = 0, 1
+
+PRECISIONS = {"f64": LS_F64, "f32": LS_F32, "bf16x3": LS_BF16X3, "bf16x6": LS_BF16X6}
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("L", ctypes.c_int32 * 3), ("b", ctypes.c_double),
+                ("periodic", ctypes.c_int32)]
+
+
+class Quad(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("t", c_double_p), ("w", c_double_p)]
+
+
+class Canon(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("len", ctypes.c_int32 * 3),
+                ("f", ctypes.c_void_p * 3), ("coef", ctypes.c_void_p)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("o", ctypes.c_int32 * 3), ("e", ctypes.c_int32 * 3)]
+
+
+class LatsumError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+_SIGNATURES = {
+    "ls_version": (ctypes.c_char_p, []),
+    "ls_last_error": (ctypes.c_char_p, []),
+    "ls_quadrature": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     c_double_p, c_double_p, ctypes.c_int32, c_int32_p]),
+    "ls_master_halfwidth": (ctypes.c_int, [ctypes.POINTER(Lattice), c_int32_p]),
+    "ls_kernel_vectors": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.POINTER(Quad), ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_assemble": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.POINTER(Quad), ctypes.c_int32,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_reconstruct": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_reconstruct_tiles": (ctypes.c_int32, [ctypes.c_int32]),
+    "ls_energy_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "ls_energy": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Canon), ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "ls_forces_workspace": (ctypes.c_size_t, [ctypes.POINTER(Lattice), ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32]),
+    "ls_forces": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.POINTER(Quad), ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Canon),
+                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+EXPORTS = tuple(_SIGNATURES)
+
+
+def lib():
+    """The loaded library (raises if liblatsum.so is missing)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1405_2270_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = handle
+    return _LIB
+
+
+def check(fn_name, status):
+    if status != LS_OK:
+        msg = lib().ls_last_error().decode(errors="replace")
+        raise LatsumError(fn_name, status, msg)

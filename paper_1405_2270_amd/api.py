@@ -1,0 +1,214 @@
+"""Python surface of the latsum library: marshals torch tensors into the C ABI.
+
+PyTorch supplies device memory and the current stream; every arithmetic step
+runs in the HIP library. Inputs must be CUDA (HIP) tensors of dtype float64 and
+contiguous; outputs are allocated here with torch and filled by the library.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Lattice, Quad, Canon, Box, check, lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev_f64(x, name):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    return x
+
+
+@dataclass(frozen=True)
+class LatticeSpec:
+    """Grid and lattice: unit cell edge b, n cells per edge, L images per axis."""
+    b: float
+    n: int
+    L: tuple
+    periodic: bool = False
+
+    @property
+    def h(self):
+        return self.b / self.n
+
+    def N(self, l):
+        return self.n if self.periodic else self.L[l] * self.n
+
+    def c(self):
+        return Lattice(self.n, (ctypes.c_int32 * 3)(*self.L), self.b, int(self.periodic))
+
+
+class QuadTable:
+    """Quadrature nodes/weights held on the host (FP64) for the C ABI."""
+
+    def __init__(self, t, w):
+        self.t = np.ascontiguousarray(t, np.float64)
+        self.w = np.ascontiguousarray(w, np.float64)
+        self.R = int(self.t.size)
+
+    def c(self):
+        return Quad(self.R, self.t.ctypes.data_as(_lib.c_double_p),
+                    self.w.ctypes.data_as(_lib.c_double_p))
+
+
+def quadrature(rule, M, C0=1.0, s=1.0):
+    """Sinc quadrature table computed by the library (``rule`` 'U' or 'S')."""
+    code = {"U": _lib.LS_RULE_U, "S": _lib.LS_RULE_S}[rule]
+    cap = 2 * M + 1
+    t = np.zeros(cap)
+    w = np.zeros(cap)
+    R = ctypes.c_int32(0)
+    check("ls_quadrature", lib().ls_quadrature(code, M, C0, s, t.ctypes.data_as(_lib.c_double_p),
+                                               w.ctypes.data_as(_lib.c_double_p), cap,
+                                               ctypes.byref(R)))
+    return QuadTable(t[:R.value], w[:R.value])
+
+
+def master_halfwidth(lat):
+    X = ctypes.c_int32(0)
+    check("ls_master_halfwidth", lib().ls_master_halfwidth(ctypes.byref(lat.c()), ctypes.byref(X)))
+    return X.value
+
+
+def kernel_vectors(lat, quad, pos, derivative=False):
+    """Master vectors [M0*3][R][2X] (FP64) for every atom and axis."""
+    pos = _dev_f64(pos, "pos")
+    M0 = pos.shape[0]
+    X = master_halfwidth(lat)
+    out = torch.empty((M0 * 3, quad.R, 2 * X), dtype=torch.float64, device=pos.device)
+    check("ls_kernel_vectors", lib().ls_kernel_vectors(ctypes.byref(lat.c()), ctypes.byref(quad.c()),
+                                                       M0, _ptr(pos), X, int(derivative), _ptr(out),
+                                                       _stream()))
+    return out
+
+
+def assemble(lat, quad, pos, Z, masters=None, derivative=False):
+    """Assembled canonical factors [f0, f1, f2] ([K][N_l] FP64 each) and coef [K]."""
+    pos = _dev_f64(pos, "pos")
+    M0 = pos.shape[0]
+    K = M0 * quad.R
+    dev = pos.device
+    F = [torch.empty((K, lat.N(l)), dtype=torch.float64, device=dev) for l in range(3)]
+    coef = None if derivative else torch.empty(K, dtype=torch.float64, device=dev)
+    if not derivative:
+        Z = _dev_f64(Z, "Z")
+    if masters is not None:
+        masters = _dev_f64(masters, "masters")
+    X = master_halfwidth(lat)
+    check("ls_assemble", lib().ls_assemble(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0,
+                                           _ptr(pos), _ptr(None if derivative else Z),
+                                           _ptr(masters), X, int(derivative), _ptr(F[0]),
+                                           _ptr(F[1]), _ptr(F[2]), _ptr(coef), _stream()))
+    return F, coef
+
+
+def _canon(F, coef):
+    return Canon(int(F[0].shape[0]), (ctypes.c_int32 * 3)(*[int(f.shape[1]) for f in F]),
+                 (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F]), coef.data_ptr())
+
+
+def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0):
+    """Sub-boxes of the canonical tensor. ``boxes``: iterable of
+    (o0, o1, o2, e0, e1, e2). Returns one tensor [e0][e1][e2] per box
+    (views of a single allocation)."""
+    for f in F:
+        _dev_f64(f, "factor")
+    _dev_f64(coef, "coef")
+    boxes = [tuple(int(v) for v in b) for b in boxes]
+    prec = _lib.PRECISIONS[precision]
+    dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
+    sizes = [b[3] * b[4] * b[5] for b in boxes]
+    flat = torch.empty(sum(sizes), dtype=dtype, device=F[0].device)
+    cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
+                              for b in boxes])
+    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(_canon(F, coef)), cb, len(boxes),
+                                                 float(scale), prec, int(tile), _ptr(flat),
+                                                 _stream()))
+    out, off = [], 0
+    for b, s in zip(boxes, sizes):
+        out.append(flat[off:off + s].view(b[3], b[4], b[5]))
+        off += s
+    return out
+
+
+def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0):
+    """As ``reconstruct`` but into a caller-provided flat tensor."""
+    boxes = [tuple(int(v) for v in b) for b in boxes]
+    prec = _lib.PRECISIONS[precision]
+    cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
+                              for b in boxes])
+    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(_canon(F, coef)), cb, len(boxes),
+                                                 float(scale), prec, int(tile), _ptr(out),
+                                                 _stream()))
+    return out
+
+
+def reconstruct_tiles(precision):
+    return int(lib().ls_reconstruct_tiles(_lib.PRECISIONS[precision]))
+
+
+def energy(F, coef, D, d, precision="f64", ws=None):
+    """E = <P, rho> (eq. scal) as a device scalar tensor."""
+    for f in list(F) + list(D):
+        _dev_f64(f, "factor")
+    K, Krho = int(F[0].shape[0]), int(D[0].shape[0])
+    need = int(lib().ls_energy_workspace(K, Krho))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=F[0].device)
+    E = torch.empty((), dtype=torch.float64, device=F[0].device)
+    check("ls_energy", lib().ls_energy(ctypes.byref(_canon(F, coef)), ctypes.byref(_canon(D, d)),
+                                       _lib.PRECISIONS[precision], _ptr(E), _ptr(ws), ws.numel(),
+                                       _stream()))
+    return E
+
+
+def forces(lat, quad, pos, Z, D, d, precision="f64", ws=None):
+    """(F [M0][3], E) with F = -dE/dpos, by the adjoint of the assembled sums."""
+    pos = _dev_f64(pos, "pos")
+    Z = _dev_f64(Z, "Z")
+    M0 = pos.shape[0]
+    need = int(lib().ls_forces_workspace(ctypes.byref(lat.c()), M0, quad.R, int(D[0].shape[0])))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=pos.device)
+    F = torch.empty((M0, 3), dtype=torch.float64, device=pos.device)
+    E = torch.empty((), dtype=torch.float64, device=pos.device)
+    check("ls_forces", lib().ls_forces(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0, _ptr(pos),
+                                       _ptr(Z), ctypes.byref(_canon(D, d)),
+                                       _lib.PRECISIONS[precision], _ptr(F), _ptr(E), _ptr(ws),
+                                       ws.numel(), _stream()))
+    return F, E
+
+
+class LatticeEnergy(torch.autograd.Function):
+    """E(pos) = <P(pos), rho> with the hand-written adjoint as its gradient.
+
+    forward(pos, Z, D0, D1, D2, d, lat, quad, precision) -> E (0-d tensor).
+    The forward pass runs ls_forces, which yields E and -dE/dpos together;
+    backward returns grad_E * dE/dpos for ``pos`` and None elsewhere.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, Z, D0, D1, D2, d, lat, quad, precision):
+        F, E = forces(lat, quad, pos.detach().contiguous(), Z, [D0, D1, D2], d, precision)
+        ctx.save_for_backward(F)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        (F,) = ctx.saved_tensors
+        return (-F * gE, None, None, None, None, None, None, None, None)
+
+
+def lattice_energy(pos, Z, D, d, lat, quad, precision="f64"):
+    return LatticeEnergy.apply(pos, Z, D[0], D[1], D[2], d, lat, quad, precision)

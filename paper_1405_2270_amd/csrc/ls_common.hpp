@@ -1,0 +1,149 @@
+// Shared host/device helpers of the latsum library (internal header).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+
+#include "latsum.h"
+
+namespace ls {
+
+// Largest quadrature rank handled; the node table travels as a kernel
+// argument (no device allocation).
+constexpr int kMaxR = 160;
+// Largest density rank in the Gram kernels (per-lane accumulators).
+constexpr int kMaxRho = 16;
+
+struct QuadArg {
+  int R;
+  double tau[kMaxR];  // t_q * h: nodes in inverse cells
+  double w[kMaxR];
+};
+
+struct Lat {
+  int n;
+  int L[3];
+  int N[3];         // cells per axis of the summation grid
+  int kmin[3];      // first image index per axis
+  double b, h;
+  int periodic;
+};
+
+// thread-local error text
+void set_error(const char* fmt, ...);
+void clear_error();
+
+ls_status check_lattice(const ls_lattice* lat, Lat* out);
+ls_status check_quad(const ls_quad* quad, double h, QuadArg* out);
+int master_halfwidth(const Lat& L);
+ls_status launch_status(const char* what);
+
+#define LS_REQUIRE(cond, ...)            \
+  do {                                   \
+    if (!(cond)) {                       \
+      ::ls::set_error(__VA_ARGS__);      \
+      return LS_EINVAL;                  \
+    }                                    \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Cell integrals in grid units (cell size 1), FP64.
+// ---------------------------------------------------------------------------
+
+// Integral of exp(-tau^2 y^2) over [y0, y0 + 1].
+//
+// With u = tau*y, a = tau*(y0 + 1/2) and c = tau/2 the integral is
+// (1/tau) * integral over [a - c, a + c] of exp(-u^2) du. Two evaluations:
+//  * nearly flat integrand (tau <= 0.35 and |a| tau <= 0.25): expand around
+//    the cell centre, exp(-(a+s)^2) = exp(-a^2) exp(-2as - s^2), whose even
+//    part in s has the Hermite series sum_m H_2m(a) s^2m/(2m)!, so
+//    integral = exp(-a^2) * sum_m H_2m(a) c^2m / (2m+1)!   (8 terms);
+//    this avoids the cancelling difference of two nearly equal erf values.
+//  * otherwise the erfc difference on the tail side (or the erf sum across
+//    the origin); there erfc(far)/erfc(near) <= ~0.6, so nothing cancels.
+// Entries whose near edge is beyond |u| = 27 are below 1e-318 and return 0.
+__device__ __forceinline__ double cell_integral(double tau, double y0) {
+  if (tau == 0.0) return 1.0;
+  const double y1 = y0 + 1.0;
+  const double u0 = tau * y0;
+  const double u1 = tau * y1;
+  const double a = 0.5 * (u0 + u1);
+  const double aa = fabs(a);
+  if (tau <= 0.35 && aa * tau <= 0.25) {
+    const double c = 0.5 * tau;
+    const double c2 = c * c;
+    const double two_a = 2.0 * aa;
+    // H_0 = 1, H_1 = 2a, H_{k+1} = 2a H_k - 2k H_{k-1}
+    double hkm1 = 1.0, hk = two_a;
+    double sum = 1.0, cp = 1.0;
+    const double inv_fact[8] = {1.0,
+                                1.0 / 6.0,
+                                1.0 / 120.0,
+                                1.0 / 5040.0,
+                                1.0 / 362880.0,
+                                1.0 / 39916800.0,
+                                1.0 / 6227020800.0,
+                                1.0 / 1307674368000.0};
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+      // advance twice: k = 2m-1 -> 2m
+      double h2 = two_a * hk - 2.0 * (2 * m - 1) * hkm1;  // H_{2m}
+      double h3 = two_a * h2 - 2.0 * (2 * m) * hk;        // H_{2m+1}
+      hkm1 = h2;
+      hk = h3;
+      cp *= c2;
+      sum = fma(h2 * cp, inv_fact[m], sum);
+    }
+    return exp(-a * a) * sum;
+  }
+  const double k = 0.88622692545275801365 / tau;  // sqrt(pi)/(2 tau)
+  if (u0 >= 0.0) {
+    if (u0 > 27.0) return 0.0;
+    return k * (erfc(u0) - erfc(u1));
+  }
+  if (u1 <= 0.0) {
+    if (u1 < -27.0) return 0.0;
+    return k * (erfc(-u1) - erfc(-u0));
+  }
+  return k * (erf(u1) + erf(-u0));
+}
+
+// d/da of the integral of exp(-t^2 (x - a)^2) over a cell, in grid units:
+// exp(-tau^2 y0^2) - exp(-tau^2 y1^2) with y1 = y0 + 1, written as the
+// larger exponential times expm1 of the exponent difference
+// (y1^2 - y0^2 = 2 y0 + 1), which does not cancel.
+__device__ __forceinline__ double cell_derivative(double tau, double y0) {
+  const double y1 = y0 + 1.0;
+  const double t2 = tau * tau;
+  const double dsq = 2.0 * y0 + 1.0;
+  if (fabs(y0) <= fabs(y1)) {
+    const double e = t2 * y0 * y0;
+    if (e > 745.0) return 0.0;
+    return -exp(-e) * expm1(-t2 * dsq);
+  }
+  const double e = t2 * y1 * y1;
+  if (e > 745.0) return 0.0;
+  return exp(-e) * expm1(t2 * dsq);
+}
+
+// Node index p and offset delta of a coordinate, (a + b/2)/h = p + delta.
+// p = floor((a + b/2)/h) clamped to [0, n-1], so every memory index derived
+// from p stays inside its buffer for any input (a NaN position gives NaN
+// results, never an out-of-range access). The geometry stays exact after the
+// clamp: cell offsets are j - delta with j = g - p - k n, and only the split
+// between p and delta moves (delta = 1 when rounding puts a + b/2 at b).
+__device__ __forceinline__ void node_offset(double a, double b, double h, int n, int* p,
+                                            double* delta) {
+  const double s = (a + 0.5 * b) / h;
+  double f = floor(s);
+  f = fmin(fmax(f, 0.0), (double)(n - 1));  // fmax/fmin map NaN to the other operand
+  *p = (int)f;
+  *delta = s - f;
+}
+
+}  // namespace ls

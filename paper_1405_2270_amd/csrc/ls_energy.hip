@@ -1,0 +1,336 @@
+// Energy as a canonical scalar product (Appendix, eq. scal) and forces on the
+// unit-cell atoms by the adjoint of the assembled vectors.
+//
+// Energy from factors (HBM-bound): G_l[r][s] = <f_l[r], rho_l[s]> streams each
+// factor row once (one workgroup per row and axis, density rows from L2),
+// then E = sum_r coef[r] sum_s d[s] prod_l G_l[r][s] in one workgroup.
+//
+// Forces without factors: with Phi_l[s][i] = sum_k rho_l[s][i + k n] (the
+// density folded back over the lattice shifts, the transpose of the shift
+// sum), each Gram entry of an atom's assembled vector is a master-length dot
+// product <m_q, Phi_l[s](. + p)>, for the value masters and for their position
+// derivatives alike. One workgroup per (atom, axis, q) generates both master
+// vectors in registers and contracts them with Phi, so neither masters nor
+// factors touch HBM.
+//
+// All cross-lane reductions are fixed-order trees (bitwise reproducible).
+#include "ls_common.hpp"
+
+namespace ls {
+
+template <typename T>
+__device__ __forceinline__ double block_sum256(T v, double* sh) {
+  // deterministic: lanes write, tree in LDS
+  const int tid = threadIdx.x;
+  sh[tid] = (double)v;
+  __syncthreads();
+#pragma unroll
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// G[(l*K + r)*Krho + s] = sum_g f_l[r][g] * D_l[s][g]
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ f0,
+                                               const double* __restrict__ f1,
+                                               const double* __restrict__ f2,
+                                               const double* __restrict__ D0,
+                                               const double* __restrict__ D1,
+                                               const double* __restrict__ D2, int K, int Krho,
+                                               int N0, int N1, int N2, double* __restrict__ G) {
+  __shared__ double sh[256];
+  const int r = blockIdx.x;
+  const int l = blockIdx.y;
+  const double* f = (l == 0 ? f0 : (l == 1 ? f1 : f2));
+  const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2));
+  const int N = (l == 0 ? N0 : (l == 1 ? N1 : N2));
+  const double* fr = f + (size_t)r * N;
+  T acc[kMaxRho];
+#pragma unroll
+  for (int s = 0; s < kMaxRho; ++s) acc[s] = 0;
+  for (int g = threadIdx.x; g < N; g += 256) {
+    const T fv = (T)fr[g];
+#pragma unroll
+    for (int s = 0; s < kMaxRho; ++s)
+      if (s < Krho) acc[s] += fv * (T)D[(size_t)s * N + g];
+  }
+  for (int s = 0; s < Krho; ++s) {
+    const double tot = block_sum256(acc[s], sh);
+    if (threadIdx.x == 0) G[((size_t)l * K + r) * Krho + s] = tot;
+  }
+}
+
+// E = sum_r coef[r] sum_s d[s] G0[r][s] G1[r][s] G2[r][s]
+__global__ __launch_bounds__(256) void k_energy_reduce(const double* __restrict__ G,
+                                                        const double* __restrict__ coef,
+                                                        const double* __restrict__ d, int K,
+                                                        int Krho, double* __restrict__ E) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < K; r += 256) {
+    double v = 0.0;
+    for (int s = 0; s < Krho; ++s) {
+      const size_t i0 = (size_t)r * Krho + s;
+      v += d[s] * G[i0] * G[(size_t)K * Krho + i0] * G[2 * (size_t)K * Krho + i0];
+    }
+    acc += coef[r] * v;
+  }
+  const double tot = block_sum256(acc, sh);
+  if (threadIdx.x == 0) *E = tot;
+}
+
+// Phi[(l*Krho + s)*W + i + X] = sum_{k in images} D_l[s][i + k n],  i in [-X, X + n - 1)
+__global__ __launch_bounds__(256) void k_fold_density(const double* __restrict__ D0,
+                                                       const double* __restrict__ D1,
+                                                       const double* __restrict__ D2, Lat lat,
+                                                       int Krho, int X, int W,
+                                                       double* __restrict__ Phi) {
+  const int ii = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  const int l = blockIdx.z;
+  if (ii >= W) return;
+  const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2)) + (size_t)s * lat.N[l];
+  const int i = ii - X;
+  double acc = 0.0;
+  for (int k = lat.kmin[l]; k < lat.kmin[l] + lat.L[l]; ++k) {
+    const long long g = (long long)i + (long long)k * lat.n;
+    if (g >= 0 && g < lat.N[l]) acc += D[g];
+  }
+  Phi[((size_t)l * Krho + s) * W + ii] = acc;
+}
+
+// Value and derivative Grams of one (atom, axis, q) against the folded density:
+//   Gv[s] = sum_j h*B(j) Phi[s][j + p],  Gd[s] = sum_j dB(j) Phi[s][j + p]
+template <typename T>
+__global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
+                                                      Lat lat, const double* __restrict__ Phi,
+                                                      int Krho, int X, int W, int K,
+                                                      double* __restrict__ Gv,
+                                                      double* __restrict__ Gd) {
+  __shared__ double sh[256];
+  const int q = blockIdx.x;
+  const int c = blockIdx.y;  // nu*3 + l
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  int p;
+  double delta;
+  node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
+  const double tau = qa.tau[q];
+  const double* ph = Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
+  T av[kMaxRho], ad[kMaxRho];
+#pragma unroll
+  for (int s = 0; s < kMaxRho; ++s) {
+    av[s] = 0;
+    ad[s] = 0;
+  }
+  for (int jj = threadIdx.x; jj < 2 * X; jj += 256) {
+    const int j = jj - X;
+    const double y0 = (double)j - delta;
+    const double bv = lat.h * cell_integral(tau, y0);
+    const double bd = cell_derivative(tau, y0);
+    if (bv == 0.0 && bd == 0.0) continue;
+#pragma unroll
+    for (int s = 0; s < kMaxRho; ++s) {
+      if (s < Krho) {
+        const T f = (T)ph[(size_t)s * W + j];
+        av[s] += (T)bv * f;
+        ad[s] += (T)bd * f;
+      }
+    }
+  }
+  const int r = nu * qa.R + q;
+  for (int s = 0; s < Krho; ++s) {
+    const double tv = block_sum256(av[s], sh);
+    const double td = block_sum256(ad[s], sh);
+    if (threadIdx.x == 0) {
+      Gv[((size_t)l * K + r) * Krho + s] = tv;
+      Gd[((size_t)l * K + r) * Krho + s] = td;
+    }
+  }
+}
+
+// F[nu][l] = -Z_nu sum_q w_q sum_s d_s Gd_l[nu q][s] prod_{l' != l} Gv_l'[nu q][s]
+// Eatom[nu] = Z_nu sum_q w_q sum_s d_s prod_l Gv_l[nu q][s]
+__global__ __launch_bounds__(256) void k_force_combine(const double* __restrict__ Z, QuadArg qa,
+                                                        int M0, int Krho,
+                                                        const double* __restrict__ d,
+                                                        const double* __restrict__ Gv,
+                                                        const double* __restrict__ Gd,
+                                                        double* __restrict__ F,
+                                                        double* __restrict__ Eatom) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;  // nu*4 + (l or 3 = energy)
+  if (idx >= 4 * M0) return;
+  const int nu = idx >> 2, l = idx & 3;
+  const int K = M0 * qa.R;
+  const size_t stride = (size_t)K * Krho;
+  double acc = 0.0;
+  for (int q = 0; q < qa.R; ++q) {
+    const size_t base = ((size_t)nu * qa.R + q) * Krho;
+    double v = 0.0;
+    for (int s = 0; s < Krho; ++s) {
+      const double g0 = Gv[base + s], g1 = Gv[stride + base + s], g2 = Gv[2 * stride + base + s];
+      double t;
+      if (l == 0)
+        t = Gd[base + s] * g1 * g2;
+      else if (l == 1)
+        t = g0 * Gd[stride + base + s] * g2;
+      else if (l == 2)
+        t = g0 * g1 * Gd[2 * stride + base + s];
+      else
+        t = g0 * g1 * g2;
+      v += d[s] * t;
+    }
+    acc += qa.w[q] * v;
+  }
+  if (l < 3)
+    F[nu * 3 + l] = -Z[nu] * acc;
+  else
+    Eatom[nu] = Z[nu] * acc;
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double* __restrict__ x, int n,
+                                              double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += x[i];
+  const double tot = block_sum256(acc, sh);
+  if (threadIdx.x == 0) *out = tot;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace ls
+
+using namespace ls;
+
+extern "C" size_t ls_energy_workspace(int32_t K, int32_t Krho) {
+  if (K < 1 || Krho < 1) return 0;
+  return align256((size_t)3 * K * Krho * sizeof(double));
+}
+
+extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t precision,
+                               double* E_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  LS_REQUIRE(P != nullptr && rho != nullptr && E_dev != nullptr, "null pointer");
+  LS_REQUIRE(P->K >= 1 && rho->K >= 1, "ranks must be >= 1");
+  LS_REQUIRE(P->f[0] && P->f[1] && P->f[2] && P->coef, "null factor pointer");
+  LS_REQUIRE(rho->f[0] && rho->f[1] && rho->f[2] && rho->coef, "null density pointer");
+  if (rho->K > kMaxRho) {
+    set_error("density rank %d exceeds the supported %d", rho->K, kMaxRho);
+    return LS_EUNSUPPORTED;
+  }
+  for (int l = 0; l < 3; ++l)
+    LS_REQUIRE(P->len[l] == rho->len[l] && P->len[l] >= 1, "length mismatch on axis %d", l);
+  if (precision != LS_F64 && precision != LS_F32) {
+    set_error("energy supports LS_F64 and LS_F32 only");
+    return LS_EUNSUPPORTED;
+  }
+  const size_t need = ls_energy_workspace(P->K, rho->K);
+  if (ws_dev == nullptr || ws_bytes < need) {
+    set_error("workspace of %zu bytes required", need);
+    return LS_EWORKSPACE;
+  }
+  double* G = (double*)ws_dev;
+  dim3 grid(P->K, 3);
+  if (precision == LS_F64)
+    hipLaunchKernelGGL(k_gram<double>, grid, dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
+                       rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0], P->len[1],
+                       P->len[2], G);
+  else
+    hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
+                       rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0], P->len[1],
+                       P->len[2], G);
+  ls_status st = launch_status("ls_energy (gram)");
+  if (st != LS_OK) return st;
+  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, stream, G, P->coef, rho->coef, P->K,
+                     rho->K, E_dev);
+  return launch_status("ls_energy (reduce)");
+}
+
+// workspace: Phi [3][Krho][W] | Gv [3][K][Krho] | Gd [3][K][Krho] | Eatom [M0]
+static void forces_layout(const Lat& L, int M0, int R, int Krho, size_t* off_gv, size_t* off_gd,
+                          size_t* off_e, size_t* total, int* X, int* W) {
+  *X = master_halfwidth(L);
+  *W = 2 * (*X) + L.n;
+  const size_t K = (size_t)M0 * R;
+  size_t o = align256((size_t)3 * Krho * (*W) * sizeof(double));
+  *off_gv = o;
+  o += align256(3 * K * Krho * sizeof(double));
+  *off_gd = o;
+  o += align256(3 * K * Krho * sizeof(double));
+  *off_e = o;
+  o += align256((size_t)M0 * sizeof(double));
+  *total = o;
+}
+
+extern "C" size_t ls_forces_workspace(const ls_lattice* lat, int32_t M0, int32_t R, int32_t Krho) {
+  Lat L;
+  if (check_lattice(lat, &L) != LS_OK || M0 < 1 || R < 1 || Krho < 1) return 0;
+  size_t a, b, c, t;
+  int X, W;
+  forces_layout(L, M0, R, Krho, &a, &b, &c, &t, &X, &W);
+  return t;
+}
+
+extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                               const double* pos_dev, const double* Z_dev, const ls_canon* rho,
+                               int32_t precision, double* F_dev, double* E_dev, void* ws_dev,
+                               size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  Lat L;
+  ls_status st = check_lattice(lat, &L);
+  if (st != LS_OK) return st;
+  QuadArg qa;
+  st = check_quad(quad, L.h, &qa);
+  if (st != LS_OK) return st;
+  LS_REQUIRE(M0 >= 1 && M0 <= 20000, "M0 must be in [1, 20000] (got %d)", M0);
+  LS_REQUIRE(pos_dev != nullptr && Z_dev != nullptr && F_dev != nullptr, "null device pointer");
+  LS_REQUIRE(rho != nullptr && rho->K >= 1 && rho->f[0] && rho->f[1] && rho->f[2] && rho->coef,
+             "density is null or empty");
+  if (rho->K > kMaxRho) {
+    set_error("density rank %d exceeds the supported %d", rho->K, kMaxRho);
+    return LS_EUNSUPPORTED;
+  }
+  for (int l = 0; l < 3; ++l)
+    LS_REQUIRE(rho->len[l] == L.N[l], "density length %d != grid %d on axis %d", rho->len[l],
+               L.N[l], l);
+  if (precision != LS_F64 && precision != LS_F32) {
+    set_error("forces support LS_F64 and LS_F32 only");
+    return LS_EUNSUPPORTED;
+  }
+  size_t off_gv, off_gd, off_e, total;
+  int X, W;
+  forces_layout(L, M0, qa.R, rho->K, &off_gv, &off_gd, &off_e, &total, &X, &W);
+  if (ws_dev == nullptr || ws_bytes < total) {
+    set_error("workspace of %zu bytes required", total);
+    return LS_EWORKSPACE;
+  }
+  char* ws = (char*)ws_dev;
+  double* Phi = (double*)ws;
+  double* Gv = (double*)(ws + off_gv);
+  double* Gd = (double*)(ws + off_gd);
+  double* Eatom = (double*)(ws + off_e);
+  const int K = M0 * qa.R;
+  hipLaunchKernelGGL(k_fold_density, dim3((W + 255) / 256, rho->K, 3), dim3(256), 0, stream,
+                     rho->f[0], rho->f[1], rho->f[2], L, rho->K, X, W, Phi);
+  st = launch_status("ls_forces (fold)");
+  if (st != LS_OK) return st;
+  if (precision == LS_F64)
+    hipLaunchKernelGGL(k_force_grams<double>, dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev,
+                       qa, L, Phi, rho->K, X, W, K, Gv, Gd);
+  else
+    hipLaunchKernelGGL(k_force_grams<float>, dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev,
+                       qa, L, Phi, rho->K, X, W, K, Gv, Gd);
+  st = launch_status("ls_forces (grams)");
+  if (st != LS_OK) return st;
+  hipLaunchKernelGGL(k_force_combine, dim3((4 * M0 + 255) / 256), dim3(256), 0, stream, Z_dev, qa,
+                     M0, rho->K, rho->coef, Gv, Gd, F_dev, Eatom);
+  st = launch_status("ls_forces (combine)");
+  if (st != LS_OK || E_dev == nullptr) return st;
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, stream, Eatom, M0, E_dev);
+  return launch_status("ls_forces (energy)");
+}

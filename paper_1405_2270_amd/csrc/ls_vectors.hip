@@ -1,0 +1,221 @@
+// Kernel vectors (Sec. 2.1, eqs. C_nD_0, galten_int, master_pot) and their
+// assembly over the lattice (Theorem 3.1 / eq. EwaldTensorM0, Lemma 3.2).
+//
+// Data layout in HBM
+//   masters  [M0*3][R][2X]  FP64, entry j + X = cell integral of master cell j
+//   factors  f_l [M0*R][N_l] FP64, r = nu*R + q, vector-contiguous
+//
+// Box assembly from masters (HBM-bound). For output g = rho + m n (residue
+// rho in [0, n), block m in [0, L)) the lattice sum over k = 0..L-1 is
+//   v[rho + m n] = sum_{d = m-L+1}^{m} beta[d],  beta[d] = master[rho - p + d n],
+// a window of length L sliding over the 2L-1 values of one residue class.
+// Every window is a suffix of the left half (d < 0) plus a prefix of the
+// right half (d >= 0), so one lane per residue computes the left suffix sums
+// once (held in registers), then streams the outputs with a running prefix
+// sum: each master entry is read once, each output written once, and all
+// partial sums add like-signed terms only (no subtraction).
+#include "ls_common.hpp"
+
+namespace ls {
+
+// ---------------------------------------------------------------------------
+// masters
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_masters(const double* __restrict__ pos, QuadArg qa,
+                                                  double b, double h, int n, int X, int deriv,
+                                                  double* __restrict__ out) {
+  const int jj = blockIdx.x * 256 + threadIdx.x;
+  const int q = blockIdx.y;
+  const int c = blockIdx.z;  // nu*3 + l
+  if (jj >= 2 * X) return;
+  int p;
+  double delta;
+  node_offset(pos[c], b, h, n, &p, &delta);
+  const double y0 = (double)(jj - X) - delta;
+  const double tau = qa.tau[q];
+  const double v = deriv ? cell_derivative(tau, y0) : h * cell_integral(tau, y0);
+  out[((size_t)c * qa.R + q) * (size_t)(2 * X) + jj] = v;
+}
+
+// ---------------------------------------------------------------------------
+// box assembly from masters: one lane per residue class, LMAX >= L
+// ---------------------------------------------------------------------------
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__ masters,
+                                                       const double* __restrict__ pos, int R, int n,
+                                                       int L0, int L1, int L2, double b, double h,
+                                                       int X, double* __restrict__ f0,
+                                                       double* __restrict__ f1,
+                                                       double* __restrict__ f2) {
+  const int rho = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int c = blockIdx.z;
+  if (rho >= n || q >= R) return;
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int L = (l == 0) ? L0 : (l == 1 ? L1 : L2);
+  const size_t N = (size_t)L * n;
+  int p;
+  double delta;
+  node_offset(pos[c], b, h, n, &p, &delta);
+  // beta[d] = mrow[d * n], d in [-(L-1), L-1]
+  const double* mrow = masters + ((size_t)c * R + q) * (size_t)(2 * X) + X + rho - p;
+  double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * R + q) * N + rho;
+  // suf[e] = sum_{i=e}^{L-2} beta[i - (L-1)] for e in [0, L-2]
+  double suf[LMAX > 1 ? LMAX - 1 : 1];
+  const double* left = mrow - (ptrdiff_t)(L - 1) * n;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = LMAX - 2; e >= 0; --e) {
+    if (e <= L - 2) acc += left[(ptrdiff_t)e * n];
+    suf[e] = acc;
+  }
+  double pre = 0.0;
+#pragma unroll
+  for (int m = 0; m < LMAX; ++m) {
+    if (m < L) {
+      pre += mrow[(ptrdiff_t)m * n];
+      const double s = (m <= L - 2) ? suf[m] : 0.0;
+      out[(ptrdiff_t)m * n] = s + pre;
+    }
+  }
+}
+
+// Box assembly from masters for any L: one lane per output, L reads.
+__global__ __launch_bounds__(256) void k_assemble_box_direct(const double* __restrict__ masters,
+                                                              const double* __restrict__ pos, int R,
+                                                              int n, int L0, int L1, int L2,
+                                                              double b, double h, int X,
+                                                              double* __restrict__ f0,
+                                                              double* __restrict__ f1,
+                                                              double* __restrict__ f2) {
+  const int q = blockIdx.y;
+  const int c = blockIdx.z;
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int L = (l == 0) ? L0 : (l == 1 ? L1 : L2);
+  const int N = L * n;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= N) return;
+  int p;
+  double delta;
+  node_offset(pos[c], b, h, n, &p, &delta);
+  const double* m = masters + ((size_t)c * R + q) * (size_t)(2 * X) + X;
+  // ascending k: d = m_blk - k; sum in order of increasing k
+  double acc = 0.0;
+  for (int k = 0; k < L; ++k) acc += m[g - p - k * n];
+  double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * R + q) * (size_t)N;
+  out[g] = acc;
+}
+
+// Assembly with every cell integral generated in registers (periodic cell,
+// or box without stored masters): one lane per output, one integral per image.
+__global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict__ pos, QuadArg qa,
+                                                         Lat lat, int deriv, double* __restrict__ f0,
+                                                         double* __restrict__ f1,
+                                                         double* __restrict__ f2) {
+  const int q = blockIdx.y;
+  const int c = blockIdx.z;
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int N = lat.N[l];
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= N) return;
+  int p;
+  double delta;
+  node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
+  const double tau = qa.tau[q];
+  const int k0 = lat.kmin[l], k1 = lat.kmin[l] + lat.L[l];
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const double y0 = (double)(g - p - k * lat.n) - delta;
+    acc += deriv ? cell_derivative(tau, y0) : cell_integral(tau, y0);
+  }
+  double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * qa.R + q) * (size_t)N;
+  out[g] = deriv ? acc : lat.h * acc;
+}
+
+__global__ void k_coef(const double* __restrict__ Z, QuadArg qa, int M0, double* __restrict__ coef) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M0 * qa.R) return;
+  coef[r] = Z[r / qa.R] * qa.w[r % qa.R];
+}
+
+}  // namespace ls
+
+using namespace ls;
+
+extern "C" ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                                       const double* pos_dev, int32_t X, int32_t derivative,
+                                       double* masters_dev, hipStream_t stream) {
+  clear_error();
+  Lat L;
+  ls_status st = check_lattice(lat, &L);
+  if (st != LS_OK) return st;
+  QuadArg qa;
+  st = check_quad(quad, L.h, &qa);
+  if (st != LS_OK) return st;
+  LS_REQUIRE(M0 >= 1 && M0 <= 20000, "M0 must be in [1, 20000] (got %d)", M0);
+  LS_REQUIRE(pos_dev != nullptr && masters_dev != nullptr, "null device pointer");
+  LS_REQUIRE(X == master_halfwidth(L), "X = %d does not match the lattice (%d)", X,
+             master_halfwidth(L));
+  dim3 grid((2 * X + 255) / 256, qa.R, 3 * M0);
+  hipLaunchKernelGGL(k_masters, grid, dim3(256), 0, stream, pos_dev, qa, L.b, L.h, L.n, X,
+                     derivative ? 1 : 0, masters_dev);
+  return launch_status("ls_kernel_vectors");
+}
+
+extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                                 const double* pos_dev, const double* Z_dev,
+                                 const double* masters_dev, int32_t X, int32_t derivative,
+                                 double* f0_dev, double* f1_dev, double* f2_dev, double* coef_dev,
+                                 hipStream_t stream) {
+  clear_error();
+  Lat L;
+  ls_status st = check_lattice(lat, &L);
+  if (st != LS_OK) return st;
+  QuadArg qa;
+  st = check_quad(quad, L.h, &qa);
+  if (st != LS_OK) return st;
+  LS_REQUIRE(M0 >= 1 && M0 <= 20000, "M0 must be in [1, 20000] (got %d)", M0);
+  LS_REQUIRE(pos_dev != nullptr && f0_dev != nullptr && f1_dev != nullptr && f2_dev != nullptr,
+             "null device pointer");
+  LS_REQUIRE(derivative || (Z_dev != nullptr && coef_dev != nullptr),
+             "Z and coef are required for value vectors");
+  LS_REQUIRE(!(L.periodic && masters_dev != nullptr),
+             "the periodic cell generates its cell integrals in registers; pass masters = NULL");
+  if (masters_dev != nullptr)
+    LS_REQUIRE(X == master_halfwidth(L), "X = %d does not match the lattice (%d)", X,
+               master_halfwidth(L));
+  if (masters_dev == nullptr) {
+    const int Nmax = L.N[0] > L.N[1] ? (L.N[0] > L.N[2] ? L.N[0] : L.N[2])
+                                     : (L.N[1] > L.N[2] ? L.N[1] : L.N[2]);
+    dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
+    hipLaunchKernelGGL(k_assemble_fused, grid, dim3(256), 0, stream, pos_dev, qa, L,
+                       derivative ? 1 : 0, f0_dev, f1_dev, f2_dev);
+  } else {
+    const int Lmax = L.L[0] > L.L[1] ? (L.L[0] > L.L[2] ? L.L[0] : L.L[2])
+                                     : (L.L[1] > L.L[2] ? L.L[1] : L.L[2]);
+    dim3 grid((L.n + 63) / 64, (qa.R + 3) / 4, 3 * M0);
+#define LS_ASM(LM)                                                                            \
+  hipLaunchKernelGGL(k_assemble_box<LM>, grid, dim3(256), 0, stream, masters_dev, pos_dev,    \
+                     qa.R, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev, f2_dev)
+    if (Lmax <= 8)
+      LS_ASM(8);
+    else if (Lmax <= 16)
+      LS_ASM(16);
+    else if (Lmax <= 32)
+      LS_ASM(32);
+    else if (Lmax <= 64)
+      LS_ASM(64);
+    else {
+      const int Nmax = Lmax * L.n;
+      dim3 g2((Nmax + 255) / 256, qa.R, 3 * M0);
+      hipLaunchKernelGGL(k_assemble_box_direct, g2, dim3(256), 0, stream, masters_dev, pos_dev,
+                         qa.R, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev, f2_dev);
+    }
+#undef LS_ASM
+  }
+  st = launch_status("ls_assemble");
+  if (st != LS_OK || derivative) return st;
+  const int K = M0 * qa.R;
+  hipLaunchKernelGGL(k_coef, dim3((K + 255) / 256), dim3(256), 0, stream, Z_dev, qa, M0, coef_dev);
+  return launch_status("ls_assemble (coef)");
+}

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Error measures (both stated for every potential/energy check):
+  rel_inf = max|x - x_o| / max|x_o|
+  rel_mag = max|x - x_o| / max|x_o^{|Z|}|, the oracle rerun with |Z_nu|, which
+            is the scale rounding errors follow when charges cancel.
+Gates: FP64 path 1e-12 (rel_mag, and rel_inf where charges do not cancel),
+mixed FP32 / split-bf16x6 1e-6 (rel_mag), split-bf16x3 3e-5 (rel_mag, two bf16
+terms carry ~16 bits), forces 1e-5 normwise for the FP32 Grams.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.lattice import Geometry, direct_factors, master_vectors, node_and_offset, factor_entries
+from oracle.canonical import reconstruct as o_reconstruct, sample_columns
+from oracle.physics import energy as o_energy, forces_adjoint
+from oracle.quadrature import rule_u, rule_s
+from workloads import small_box, small_periodic, config1, config2
+
+pytestmark = pytest.mark.gpu
+
+dev = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1405_2270_amd as lib
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return lib
+
+
+def _quads(sysm, L):
+    q = sysm.quad
+    if q["rule"] == "U":
+        t, w = rule_u(q["M"], q["C0"])
+        qt = L.quadrature("U", q["M"], q["C0"])
+    else:
+        t, w = rule_s(q["M"], q["C0"], q["s"])
+        qt = L.quadrature("S", q["M"], q["C0"], q["s"])
+    return t, w, qt
+
+
+def _spec(sysm, L):
+    return L.LatticeSpec(sysm.b, sysm.n, tuple(sysm.L), sysm.periodic)
+
+
+def _geom(sysm):
+    return Geometry(sysm.b, sysm.n, tuple(sysm.L), sysm.periodic)
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def _gpu_factors(L, sysm, qt, fused=False):
+    spec = _spec(sysm, L)
+    pos, Z = _t(sysm.pos), _t(sysm.Z)
+    masters = None if (fused or sysm.periodic) else L.kernel_vectors(spec, qt, pos)
+    F, coef = L.assemble(spec, qt, pos, Z, masters)
+    torch.cuda.synchronize()
+    return F, coef
+
+
+def _close_rows(a, b, rtol):
+    # elementwise relative, with a floor at rtol * (row maximum) for deep tails
+    scale = np.maximum(np.abs(b), np.max(np.abs(b), axis=1, keepdims=True) * 1e-3)
+    return np.max(np.abs(a - b) / scale) < rtol
+
+
+SMALL = [
+    ("box_offgrid", lambda: small_box(101, n=12, L=(3, 2, 4), M0=3)),
+    ("box_ongrid_U", lambda: small_box(102, n=10, L=(2, 3, 2), M0=2, rule="U", M=12, on_grid=True)),
+    ("box_single", lambda: small_box(103, n=9, L=(1, 1, 1), M0=1, neutral=False)),
+    ("box_L17", lambda: small_box(104, n=6, L=(17, 3, 9), M0=2)),
+    ("periodic_odd", lambda: small_periodic(105, n=12, L=(5, 5, 3), M0=4)),
+    ("periodic_even", lambda: small_periodic(106, n=10, L=(4, 6, 2), M0=3)),
+]
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+def test_quadrature_and_masters(L, name, maker):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    assert np.allclose(qt.t, t, rtol=1e-15, atol=0) and np.allclose(qt.w, w, rtol=1e-15, atol=0)
+    if sysm.periodic:
+        return
+    spec = _spec(sysm, L)
+    geom = _geom(sysm)
+    X = L.master_halfwidth(spec)
+    for deriv in (False, True):
+        m = L.kernel_vectors(spec, qt, _t(sysm.pos), derivative=deriv).cpu().numpy()
+        for nu in range(sysm.M0):
+            for l in range(3):
+                _, d = node_and_offset(geom, sysm.pos[nu, l])
+                ref = master_vectors(geom, t, d, X, derivative=deriv)
+                assert _close_rows(m[nu * 3 + l], ref, 1e-13), (name, deriv, nu, l)
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("fused", [False, True])
+def test_assembled_factors(L, name, maker, fused):
+    sysm = maker()
+    if sysm.periodic and not fused:
+        pytest.skip("periodic cell always generates in registers")
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt, fused)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z)
+    for l in range(3):
+        assert _close_rows(F[l].cpu().numpy(), Fo[l], 2e-13), (name, l)
+    assert np.allclose(coef.cpu().numpy(), co, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+def test_derivative_factors(L, name, maker):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    pos = _t(sysm.pos)
+    Fo, _ = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z, derivative=True)
+    variants = [None] if sysm.periodic else [None, L.kernel_vectors(spec, qt, pos, derivative=True)]
+    for masters in variants:
+        F, _ = L.assemble(spec, qt, pos, None, masters, derivative=True)
+        for l in range(3):
+            a, b = F[l].cpu().numpy(), Fo[l]
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b)), (name, l)
+
+
+def _errors(got, ref, ref_abs):
+    err = np.max(np.abs(got - ref))
+    return err / np.max(np.abs(ref)), err / np.max(np.abs(ref_abs))
+
+
+PREC_GATES = {"f64": 1e-12, "f32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5}
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3"])
+def test_reconstruct(L, name, maker, precision):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z)
+    h3 = sysm.h ** 3
+    boxes = [tuple(b) for b in sysm.boxes]
+    full = (0, 0, 0, F[0].shape[1], F[1].shape[1], F[2].shape[1])
+    boxes.append(full)
+    tiles = [0] + list(range(1, L.reconstruct_tiles(precision) + 1))
+    for tile in tiles:
+        outs = L.reconstruct(F, coef, boxes, 1.0 / h3, precision, tile)
+        torch.cuda.synchronize()
+        for b, out in zip(boxes, outs):
+            ref = o_reconstruct(Fo, co, b[:3], b[3:]) / h3
+            ref_abs = o_reconstruct(Fo, np.abs(co), b[:3], b[3:]) / h3
+            rel_inf, rel_mag = _errors(out.double().cpu().numpy(), ref, ref_abs)
+            assert rel_mag < PREC_GATES[precision], (name, precision, tile, b, rel_inf, rel_mag)
+            if precision == "f64" and np.all(sysm.Z > 0):
+                assert rel_inf < 1e-12
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_energy(L, name, maker, precision):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    E = float(L.energy(F, coef, D, d, precision).cpu())
+    geom = _geom(sysm)
+    Eo = o_energy(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
+    Eabs = o_energy(geom, t, w, sysm.pos, np.abs(sysm.Z), sysm.density.D, sysm.density.d)
+    gate = 1e-12 if precision == "f64" else 1e-6
+    assert abs(E - Eo) / abs(Eabs) < gate, (name, E, Eo, Eabs)
+
+
+@pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_forces_and_energy_by_adjoint(L, name, maker, precision):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    Fg, Eg = L.forces(spec, qt, _t(sysm.pos), _t(sysm.Z), D, d, precision)
+    geom = _geom(sysm)
+    Fo = forces_adjoint(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
+    Eo = o_energy(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
+    Eabs = o_energy(geom, t, w, sysm.pos, np.abs(sysm.Z), sysm.density.D, sysm.density.d)
+    gate = 1e-11 if precision == "f64" else 1e-5
+    assert np.max(np.abs(Fg.cpu().numpy() - Fo)) / np.max(np.abs(Fo)) < gate, name
+    assert abs(float(Eg.cpu()) - Eo) / abs(Eabs) < (1e-12 if precision == "f64" else 1e-6)
+
+
+def test_autograd_matches_finite_differences(L):
+    sysm = small_box(111, n=10, L=(3, 3, 3), M0=3)
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    pos = _t(sysm.pos).requires_grad_(True)
+    E = L.lattice_energy(pos, _t(sysm.Z), D, d, spec, qt, "f64")
+    E.backward()
+    g = pos.grad.cpu().numpy()
+    step = 1e-4 * sysm.b
+    fd = np.zeros_like(g)
+    for nu in range(sysm.M0):
+        for l in range(3):
+            pp, pm = sysm.pos.copy(), sysm.pos.copy()
+            pp[nu, l] += step
+            pm[nu, l] -= step
+            Ep = float(L.forces(spec, qt, _t(pp), _t(sysm.Z), D, d, "f64")[1].cpu())
+            Em = float(L.forces(spec, qt, _t(pm), _t(sysm.Z), D, d, "f64")[1].cpu())
+            fd[nu, l] = (Ep - Em) / (2 * step)
+    assert np.max(np.abs(g - fd)) < 1e-6 * np.max(np.abs(fd))
+
+
+def test_reproducible_bitwise(L):
+    sysm = small_box(121, n=12, L=(4, 4, 4), M0=4)
+    t, w, qt = _quads(sysm, L)
+    outs = []
+    for _ in range(2):
+        F, coef = _gpu_factors(L, sysm, qt)
+        V = L.reconstruct(F, coef, [(0, 0, 0, 48, 48, 48)], 1.0, "f64")[0]
+        E = L.energy(F, coef, [_t(x) for x in sysm.density.D], _t(sysm.density.d), "f64")
+        outs.append((F[0].cpu().numpy(), V.cpu().numpy(), float(E.cpu())))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_invalid_arguments_raise(L):
+    from paper_1405_2270_amd._lib import LatsumError
+    sysm = small_box(131, n=8, L=(2, 2, 2), M0=2)
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    with pytest.raises(LatsumError):
+        L.reconstruct(F, coef, [(0, 0, 10, 8, 8, 8)], 1.0, "f64")   # outside the factors
+    with pytest.raises(LatsumError):
+        L.reconstruct(F, coef, [(0, 0, 0, 0, 8, 8)], 1.0, "f64")    # empty extent
+    with pytest.raises(LatsumError):
+        L.reconstruct(F, coef, [(0, 0, 0, 4, 4, 4)], 1.0, "f64", tile=99)
+    with pytest.raises(LatsumError):
+        L.energy(F, coef, [_t(x) for x in sysm.density.D], _t(sysm.density.d), "bf16x3")
+    bad = L.LatticeSpec(sysm.b, 0, (2, 2, 2))
+    with pytest.raises(LatsumError):
+        L.kernel_vectors(bad, qt, _t(sysm.pos))
+    with pytest.raises(LatsumError):
+        L.assemble(L.LatticeSpec(sysm.b, 8, (2, 2, 2), True), qt, _t(sysm.pos), _t(sysm.Z),
+                   torch.zeros(1, dtype=torch.float64, device=dev))
+
+
+def test_positions_outside_the_cell_stay_exact(L):
+    # a charge at the upper cell edge or slightly outside: the node index is
+    # clamped, the geometry is not
+    b, n = 10.0, 8
+    pos = np.array([[0.5 * b, -0.5 * b, 0.3], [0.5 * b + 0.7, 0.1, -0.5 * b - 0.2]])
+    Z = np.array([1.0, -1.0])
+    t, w = rule_s(29, 3.4, 2.45e-3 * n / b)
+    qt = L.quadrature("S", 29, 3.4, 2.45e-3 * n / b)
+    spec = L.LatticeSpec(b, n, (3, 3, 3))
+    F, coef = L.assemble(spec, qt, _t(pos), _t(Z), L.kernel_vectors(spec, qt, _t(pos)))
+    Fo, _ = direct_factors(Geometry(b, n, (3, 3, 3)), t, w, pos, Z)
+    for l in range(3):
+        assert _close_rows(F[l].cpu().numpy(), Fo[l], 2e-13)
+
+
+def test_config1_full_potential(L):
+    # small benchmark case: full 128^3 potential of 8 unit charges (L = 2)
+    sysm = config1()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z)
+    h3 = sysm.h ** 3
+    ref = o_reconstruct(Fo, co) / h3
+    for precision in ("f64", "f32", "bf16x6"):
+        V = L.reconstruct(F, coef, [tuple(sysm.boxes[0])], 1.0 / h3, precision)[0]
+        rel_inf, _ = _errors(V.double().cpu().numpy(), ref, ref)
+        assert rel_inf < PREC_GATES[precision], (precision, rel_inf)
+
+
+@pytest.mark.slow
+def test_config2_sampled(L):
+    # headline workload at full size: factors sampled column by column against
+    # the oracle, and potential values at sampled points of two 256^3 boxes
+    sysm = config2()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    geom = _geom(sysm)
+    rng = np.random.default_rng(7)
+    boxes = [tuple(b) for b in sysm.boxes[:2]]
+    h3 = sysm.h ** 3
+    for bi, b in enumerate(boxes):
+        sel_local = [np.sort(rng.choice(b[3 + l], 6, replace=False)) for l in range(3)]
+        cols = [factor_entries(geom, t, sysm.pos, l, b[l] + sel_local[l]) for l in range(3)]
+        for l in range(3):
+            got = F[l][:, b[l] + sel_local[l]].cpu().numpy()
+            assert _close_rows(got, cols[l], 2e-13)
+        sel = np.array(np.meshgrid(np.arange(6), np.arange(6), np.arange(6), indexing="ij")).reshape(3, -1).T
+        coef_o = (sysm.Z[:, None] * w[None, :]).ravel()
+        ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
+        ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
+        for precision in ("f64", "f32", "bf16x6"):
+            V = L.reconstruct(F, coef, [b], 1.0 / h3, precision)[0]
+            got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
+            rel_inf, rel_mag = _errors(got.double().cpu().numpy(), ref, ref_abs)
+            assert rel_mag < PREC_GATES[precision], (precision, rel_inf, rel_mag)
+            del V
+            torch.cuda.empty_cache()
