@@ -12,7 +12,10 @@ L = 2p+1, and {-L/2 .. L/2-1} for even L (reading G8).
 
 Charges sit anywhere in the unit cell (reading G6): the cell integrals are taken
 at the continuous positions a_nu + b k, which reduces to the paper's
-node-centred windows when a_nu is a grid node.
+node-centred windows when a_nu is a grid node. The offset of cell g from image
+k is evaluated as (g - k n) h - (a_nu + b/2), which equals
+(-b/2 + g h) - (a_nu + b k) because b = n h, but does not subtract two
+coordinates of lattice size (that would cost log10(L n) digits far out).
 
 The canonical rank index is r = nu*R + q (atom-major); coef[r] = Z_nu w_q is kept
 apart from the vectors (reading G4, eq. CP_form).
@@ -75,13 +78,15 @@ def direct_factors(geom, t, w, pos, Z, derivative=False):
     cell = gauss_cell_integral_dpos if derivative else gauss_cell_integral
     F = []
     for l in range(3):
-        x = geom.edges(l)
+        g = np.arange(geom.N(l))
         out = np.zeros((M0 * R, geom.N(l)))
         for nu in range(M0):
             acc = np.zeros((R, geom.N(l)))
+            a = pos[nu, l] + 0.5 * geom.b
             for k in geom.images(l):
-                c = pos[nu, l] + geom.b * k
-                acc += cell(t[:, None], (x[:-1] - c)[None, :], (x[1:] - c)[None, :])
+                y0 = (g - k * geom.n) * geom.h - a
+                y1 = (g + 1 - k * geom.n) * geom.h - a
+                acc += cell(t[:, None], y0[None, :], y1[None, :])
             out[nu * R:(nu + 1) * R] = acc
         F.append(out)
     coef = (np.asarray(Z, np.float64)[:, None] * np.asarray(w, np.float64)[None, :]).ravel()
@@ -174,15 +179,15 @@ def factor_entries(geom, t, pos, l, g, derivative=False):
     t = np.asarray(t, np.float64)
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     g = np.asarray(g)
-    x0 = -0.5 * geom.b + geom.h * g
-    x1 = -0.5 * geom.b + geom.h * (g + 1)
     cell = gauss_cell_integral_dpos if derivative else gauss_cell_integral
     out = np.zeros((pos.shape[0] * t.size, g.size))
     for nu in range(pos.shape[0]):
         acc = np.zeros((t.size, g.size))
+        a = pos[nu, l] + 0.5 * geom.b
         for k in geom.images(l):
-            c = pos[nu, l] + geom.b * k
-            acc += cell(t[:, None], (x0 - c)[None, :], (x1 - c)[None, :])
+            y0 = (g - k * geom.n) * geom.h - a
+            y1 = (g + 1 - k * geom.n) * geom.h - a
+            acc += cell(t[:, None], y0[None, :], y1[None, :])
         out[nu * t.size:(nu + 1) * t.size] = acc
     return out
 
