@@ -73,7 +73,7 @@ typedef struct {
 
 typedef struct {
   int32_t R;         /* number of quadrature terms = canonical rank of one kernel */
-  const double* t;   /* host [R], nodes t_q >= 0 (1/length) */
+  const double* t;   /* host [R], nodes t_q (1/length); only t_q^2 is used */
   const double* w;   /* host [R], weights w_q (1/length) */
 } ls_quad;
 
@@ -128,7 +128,7 @@ ls_status ls_master_halfwidth(const ls_lattice* lat, int32_t* X);
  *   exp(-t_q^2 ((j - delta) h)^2) - exp(-t_q^2 ((j + 1 - delta) h)^2).
  * All arithmetic is FP64. X must be ls_master_halfwidth(lat).
  * masters_dev: device, M0*3*R*2X doubles, written.
- * Errors: LS_EINVAL (null pointers, M0 < 1, R < 1, t < 0, X mismatch).
+ * Errors: LS_EINVAL (null pointers, M0 < 1, R < 1, non-finite t or w, X mismatch).
  */
 ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                             const double* pos_dev, int32_t X, int32_t derivative,

@@ -48,9 +48,10 @@ ls_status check_quad(const ls_quad* quad, double h, QuadArg* out) {
   }
   out->R = quad->R;
   for (int q = 0; q < quad->R; ++q) {
-    LS_REQUIRE(std::isfinite(quad->t[q]) && quad->t[q] >= 0.0, "t[%d] must be finite and >= 0", q);
+    LS_REQUIRE(std::isfinite(quad->t[q]), "t[%d] must be finite", q);
     LS_REQUIRE(std::isfinite(quad->w[q]), "w[%d] must be finite", q);
-    out->tau[q] = quad->t[q] * h;
+    // only t^2 enters the Gaussians (rule U has nodes of both signs)
+    out->tau[q] = std::fabs(quad->t[q]) * h;
     out->w[q] = quad->w[q];
   }
   return LS_OK;

@@ -19,8 +19,9 @@
 //          v_mfma_f32_16x16x32_bf16 with FP32 accumulation, FP32 out.
 //
 // MFMA operand layout (16x16 blocks, wave of 64 lanes): lane l supplies
-// A[l%16][k-group l/16] and B[k-group l/16][l%16] and receives
-// D[4*(l/16) + v][l%16], v = 0..3.
+// A[l%16][k-group l/16] and B[k-group l/16][l%16]. It receives D[4*(l/16) + v][l%16]
+// (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
+// f64 one (checked on gfx950).
 #include "ls_common.hpp"
 
 namespace ls {
@@ -123,13 +124,14 @@ __global__ __launch_bounds__(256) void k_recon(BoxArg a, T* __restrict__ out) {
   }
 
   const T sc = (T)a.scale;
+  constexpr bool f64_layout = sizeof(T) == 8;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = row0 + wr + i * 16 + 4 * lk + v;
+        const int row = row0 + wr + i * 16 + (f64_layout ? lk + 4 * v : 4 * lk + v);
         const int col = col0 + wc + j * 16 + lr;
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
       }
