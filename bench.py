@@ -1,0 +1,213 @@
+"""Benchmark: assembled lattice-potential values/s (+ forces/s), mixed vs FP64.
+
+One step is one pass of the whole hot path over the headline workload (box
+lattice L=32, n=128, N=4096, 8 charges per cell, rule S with R=48, 16 random
+256^3 sub-boxes, rank-8 density):
+  quadrature table (host) -> kernel vectors -> lattice assembly -> energy ->
+  reconstruction of the 16 sub-boxes.
+Inputs are resident in HBM before timing starts. The FP64 path and each mixed
+reconstruction precision are timed; `value` is the fastest mixed variant whose
+potential error against the FP64 path stays within 1e-6 (rel_mag), and the
+FP64 rate is reported beside it. Forces/s is timed on the forces workload
+(M0=64 charges, L=32, n=128) as M0 / time of one forces call (which also
+yields the energy).
+
+Prints ONE JSON line (rank 0). Runs on one GPU; --gpus > 1 is refused.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--precisions", default="f64,f32,bf16x6,bf16x3")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-forces", action="store_true")
+    p.add_argument("--cpu-sample-edge", type=int, default=160)
+    return p.parse_args()
+
+
+def cpu_baseline(sysm, edge):
+    """The oracle, as it stands, on a bounded sample of the same workload: the
+    factor columns of one edge^3 sub-box of the first box (every image of every
+    atom, FP64) and its reconstruction by einsum. Rate in values/s."""
+    import numpy as np
+    from oracle.lattice import Geometry, factor_entries
+    from oracle.quadrature import rule_s
+    from oracle.canonical import reconstruct
+    q = sysm.quad
+    t0 = time.perf_counter()
+    t, w = rule_s(q["M"], q["C0"], q["s"])
+    geom = Geometry(sysm.b, sysm.n, sysm.L, False)
+    o = sysm.boxes[0][:3]
+    cols = [factor_entries(geom, t, sysm.pos, l, o[l] + np.arange(edge)) for l in range(3)]
+    coef = (sysm.Z[:, None] * w[None, :]).ravel()
+    V = reconstruct(cols, coef) / sysm.h ** 3
+    dt = time.perf_counter() - t0
+    assert V.shape == (edge, edge, edge)
+    return {"value": edge ** 3 / dt, "unit": "potential values/s", "cores": 1, "kind": "oracle",
+            "sample": f"factor columns (all {sysm.L[0]}^3 images, {sysm.K} rank terms) and einsum "
+                      f"reconstruction of one {edge}^3 sub-box of box 0; {dt:.1f} s single-threaded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1405_2270_amd as L
+    from workloads import config2, config5
+
+    dev = torch.device("cuda:0")
+    T = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    sysm = config2()
+    q = sysm.quad
+    spec = L.LatticeSpec(sysm.b, sysm.n, sysm.L, False)
+    pos, Z = T(sysm.pos), T(sysm.Z)
+    D = [T(x) for x in sysm.density.D]
+    d = T(sysm.density.d)
+    boxes = [tuple(int(v) for v in b) for b in sysm.boxes]
+    nvals = sum(b[3] * b[4] * b[5] for b in boxes)
+    scale = 1.0 / sysm.h ** 3
+    K = sysm.K
+    ws = torch.empty(L.api.lib().ls_energy_workspace(K, 8), dtype=torch.uint8, device=dev)
+    outs = {"f64": torch.empty(nvals, dtype=torch.float64, device=dev)}
+    precs = [p for p in args.precisions.split(",") if p]
+    for p in precs:
+        if p != "f64":
+            outs[p] = torch.empty(nvals, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(prec, ev=None):
+        qt = L.quadrature("S", q["M"], q["C0"], q["s"])                 # a1 (host)
+        masters = L.kernel_vectors(spec, qt, pos)                          # a2
+        F, coef = L.assemble(spec, qt, pos, Z, masters)                    # a3
+        E = L.energy(F, coef, D, d, "f64", ws)                             # a6
+        if ev is not None:
+            ev[0].record(stream)
+        L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec)        # a5
+        if ev is not None:
+            ev[1].record(stream)
+        return F, coef, E
+
+    results = {}
+    for prec in ["f64"] + [p for p in precs if p != "f64"]:
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(prec, evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        recon_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+        results[prec] = {"ms_per_step": 1e3 * wall / args.steps, "recon_ms": recon_ms}
+
+    # errors of the mixed variants against the FP64 path (not timed)
+    F, coef, E = step("f64")
+    absout = torch.empty(nvals, dtype=torch.float64, device=dev)
+    L.reconstruct_into(F, coef.abs(), boxes, absout, scale, "f64")
+    vmax = float(outs["f64"].abs().max())
+    vabs = float(absout.abs().max())
+    for prec in precs:
+        if prec == "f64":
+            continue
+        step(prec)
+        err = float((outs[prec].double() - outs["f64"]).abs().max())
+        results[prec]["rel_inf"] = err / vmax
+        results[prec]["rel_mag"] = err / vabs
+
+    flops = 2.0 * nvals * K
+    for prec, r in results.items():
+        r["values_per_s"] = nvals / (r["ms_per_step"] / 1e3)
+        r["recon_tflops"] = flops / (r["recon_ms"] / 1e3) / 1e12
+
+    gated = [p for p in precs if p != "f64" and results[p].get("rel_mag", 1.0) <= 1e-6]
+    best = min(gated, key=lambda p: results[p]["ms_per_step"]) if gated else "f64"
+    rb = results[best]
+    per_launch_ms = rb["recon_ms"] / len(boxes)
+    achieved = flops / len(boxes) / (per_launch_ms / 1e3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAKS_TFLOPS[best],
+                "unit": "TFLOP/s", "frac": round(achieved / PEAKS_TFLOPS[best], 4),
+                "traffic": None, "kernel": f"k_recon ({best})",
+                "per_launch_ms": round(per_launch_ms, 4),
+                "algorithmic_flops_per_launch": flops / len(boxes)}
+
+    forces = None
+    if not args.no_forces:
+        c5 = config5()
+        q5 = c5.quad
+        spec5 = L.LatticeSpec(c5.b, c5.n, c5.L, False)
+        qt5 = L.quadrature("S", q5["M"], q5["C0"], q5["s"])
+        pos5, Z5 = T(c5.pos), T(c5.Z)
+        D5 = [T(x) for x in c5.density.D]
+        d5 = T(c5.density.d)
+        forces = {}
+        for prec in ("f64", "f32"):
+            for _ in range(args.warmup):
+                L.forces(spec5, qt5, pos5, Z5, D5, d5, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                L.forces(spec5, qt5, pos5, Z5, D5, d5, prec)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            forces[prec] = {"ms": round(ms, 4), "forces_per_s": c5.M0 / (ms / 1e3)}
+        F64, _ = L.forces(spec5, qt5, pos5, Z5, D5, d5, "f64")
+        F32, _ = L.forces(spec5, qt5, pos5, Z5, D5, d5, "f32")
+        forces["f32"]["rel_err"] = float((F32 - F64).abs().max() / F64.abs().max())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sysm, args.cpu_sample_edge)
+
+    line = {
+        "metric": "assembled lattice-potential values/s + forces/s, mixed vs FP64 at 1e-6 rel",
+        "value": rb["values_per_s"],
+        "unit": "potential values/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rb["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": best,
+        "data": "synthetic",
+        "config": {"workload": "box lattice L=32, n=128 (N=4096), 8 charges/cell rock-salt +-1 "
+                               "with jitter, rule S R=48 (K=384), 16 sub-boxes 256^3, rank-8 density",
+                   "global_batch": len(boxes), "seq_len": None, "parallelism": "none"},
+        "values_per_step": nvals,
+        "fp64": {"values_per_s": results["f64"]["values_per_s"],
+                 "ms_per_step": results["f64"]["ms_per_step"],
+                 "recon_tflops": results["f64"]["recon_tflops"]},
+        "mixed_speedup_vs_fp64": results["f64"]["ms_per_step"] / rb["ms_per_step"],
+        "variants": {p: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                     for p, r in results.items()},
+        "energy": float(E.cpu()),
+        "forces": forces,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
