@@ -61,15 +61,94 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// FP64 / FP32 tile kernel. T = operand type.
+// Operand staging shared by all precisions. One rank chunk of BK rows is
+// staged per step; lane t of the workgroup owns rank row kk = t / TPR and
+// rows m = q + TPR*e (q = t % TPR, e = 0..EPT-1) of the W operand, so every
+// load instruction of a 16-lane group reads 16 consecutive doubles.
+// Fast path (uniform per workgroup): the BM rows of the tile share one i,
+// so W[r][m] = alpha_r * f1[r][o1 + j0 + m - row0] with alpha_r = coef[r] f0[r][o0 + i]
+// (two scalar loads per rank row); otherwise every element does its own
+// index arithmetic.
+template <int BM, int BN, int BK>
+struct Stager {
+  static constexpr int EPT_W = BK * BM / 256;
+  static constexpr int TPR_W = BM / EPT_W;
+  static constexpr int EPT_Y = BK * BN / 256;
+  static constexpr int TPR_Y = BN / EPT_Y;
+  static_assert(EPT_W >= 1 && EPT_Y >= 1 && TPR_W * BK == 256 && TPR_Y * BK == 256, "staging map");
+
+  int wk, wq, yk, yq;
+  int row0, col0, M, i0, j0;
+  bool wfast, yfast;
+  double w[EPT_W];
+  double y[EPT_Y];
+
+  __device__ __forceinline__ void init(const BoxArg& a, int r0, int c0) {
+    const int tid = threadIdx.x;
+    wk = tid / TPR_W;
+    wq = tid - wk * TPR_W;
+    yk = tid / TPR_Y;
+    yq = tid - yk * TPR_Y;
+    row0 = r0;
+    col0 = c0;
+    M = a.e0 * a.e1;
+    i0 = row0 / a.e1;
+    j0 = row0 - i0 * a.e1;
+    wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
+    yfast = col0 + BN <= a.e2;
+  }
+
+  __device__ __forceinline__ void load(const BoxArg& a, int k0) {
+    const int r = k0 + wk;
+    if (r < a.K) {
+      if (wfast) {
+        const double alpha = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i0];
+        const double* src = a.A2 + (size_t)r * a.len1 + a.o1 + j0 + wq;
+#pragma unroll
+        for (int e = 0; e < EPT_W; ++e) w[e] = alpha * src[e * TPR_W];
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT_W; ++e) {
+          const int m = row0 + wq + e * TPR_W;
+          double v = 0.0;
+          if (m < M) {
+            const int i = m / a.e1, j = m - i * a.e1;
+            v = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i] * a.A2[(size_t)r * a.len1 + a.o1 + j];
+          }
+          w[e] = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT_W; ++e) w[e] = 0.0;
+    }
+    const int ry = k0 + yk;
+    if (ry < a.K) {
+      const double* src = a.A3 + (size_t)ry * a.len2 + a.o2 + col0 + yq;
+      if (yfast) {
+#pragma unroll
+        for (int e = 0; e < EPT_Y; ++e) y[e] = src[e * TPR_Y];
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT_Y; ++e) y[e] = (col0 + yq + e * TPR_Y < a.e2) ? src[e * TPR_Y] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT_Y; ++e) y[e] = 0.0;
+    }
+  }
+};
+
+// FP64 / FP32 tile kernel. T = operand type. Two LDS buffers: the global
+// loads of chunk c+1 are in flight while the MFMAs consume chunk c.
 template <typename T, int BM, int BN, int WM, int WN, int BK>
 __global__ __launch_bounds__(256) void k_recon(BoxArg a, T* __restrict__ out) {
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   typedef typename Acc<T>::type acc_t;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
-  __shared__ T Ws[BK][BM + PAD];
-  __shared__ T Ys[BK][BN + PAD];
+  constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
+  __shared__ T Ws[2][BK][BM + PAD];
+  __shared__ T Ys[2][BK][BN + PAD];
 
   const int M = a.e0 * a.e1;
   const int row0 = blockIdx.x * BM;
@@ -88,39 +167,32 @@ __global__ __launch_bounds__(256) void k_recon(BoxArg a, T* __restrict__ out) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
-    // stage W (Khatri-Rao of f0, f1 with coef) and Y
+  Stager<BM, BN, BK> st;
+  st.init(a, row0, col0);
+  st.load(a, 0);
+  const int nchunk = (a.K + BK - 1) / BK;
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
 #pragma unroll
-    for (int e = tid; e < BK * BM; e += 256) {
-      const int kk = e / BM, mm = e - kk * BM;
-      const int r = k0 + kk, m = row0 + mm;
-      double v = 0.0;
-      if (r < a.K && m < M) {
-        const int i = m / a.e1, j = m - i * a.e1;
-        v = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i] * a.A2[(size_t)r * a.len1 + a.o1 + j];
-      }
-      Ws[kk][mm] = (T)v;
-    }
+    for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
+      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (T)st.w[e];
 #pragma unroll
-    for (int e = tid; e < BK * BN; e += 256) {
-      const int kk = e / BN, nn = e - kk * BN;
-      const int r = k0 + kk, cc = col0 + nn;
-      Ys[kk][nn] = (r < a.K && cc < a.e2) ? (T)a.A3[(size_t)r * a.len2 + a.o2 + cc] : (T)0;
-    }
+    for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
+      Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (T)st.y[e];
     __syncthreads();
+    if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[FM], bv[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) av[i] = Ws[kk + lk][wr + i * 16 + lr];
+      for (int i = 0; i < FM; ++i) av[i] = Ws[buf][kk + lk][wr + i * 16 + lr];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j] = Ys[kk + lk][wc + j * 16 + lr];
+      for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kk + lk][wc + j * 16 + lr];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
     }
-    __syncthreads();
   }
 
   const T sc = (T)a.scale;
@@ -149,15 +221,29 @@ __device__ __forceinline__ float bf16_val(unsigned short u) {
 }
 
 // NT terms: 2 (x3 products) or 3 (x6 products). Operands in LDS as
-// [term][row][BK] bf16 with the rank contiguous (16-byte MFMA loads).
+// [term][row][BK] bf16 with the rank contiguous (16-byte MFMA operand loads);
+// the staging writes transpose the rank-major global layout. Two LDS buffers
+// as in the FP kernels.
+template <int NT>
+__device__ __forceinline__ void split_store(double v, unsigned short* dst, int plane) {
+  double rem = v;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const unsigned short u = bf16_bits((float)rem);
+    dst[t * plane] = u;
+    rem -= (double)bf16_val(u);
+  }
+}
+
 template <int NT, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict__ out) {
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   constexpr int BK = 32;
   constexpr int FM = WM / 16, FN = WN / 16;
   constexpr int KP = BK + 8;  // padded row (elements)
-  __shared__ __attribute__((aligned(16))) unsigned short Ws[NT][BM][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short Ys[NT][BN][KP];
+  typedef Stager<BM, BN, BK> S;
+  __shared__ __attribute__((aligned(16))) unsigned short Ws[2][NT][BM][KP];
+  __shared__ __attribute__((aligned(16))) unsigned short Ys[2][NT][BN][KP];
 
   const int M = a.e0 * a.e1;
   const int row0 = blockIdx.x * BM;
@@ -176,44 +262,29 @@ __global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict_
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
-    for (int e = tid; e < BK * BM; e += 256) {
-      const int kk = e / BM, mm = e - kk * BM;  // consecutive lanes: consecutive rows
-      const int r = k0 + kk, m = row0 + mm;
-      double v = 0.0;
-      if (r < a.K && m < M) {
-        const int i = m / a.e1, j = m - i * a.e1;
-        v = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i] * a.A2[(size_t)r * a.len1 + a.o1 + j];
-      }
-      double rem = v;
+  S st;
+  st.init(a, row0, col0);
+  st.load(a, 0);
+  const int nchunk = (a.K + BK - 1) / BK;
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const unsigned short u = bf16_bits((float)rem);
-        Ws[t][mm][kk] = u;
-        rem -= (double)bf16_val(u);
-      }
-    }
-    for (int e = tid; e < BK * BN; e += 256) {
-      const int kk = e / BN, nn = e - kk * BN;
-      const int r = k0 + kk, cc = col0 + nn;
-      double rem = (r < a.K && cc < a.e2) ? a.A3[(size_t)r * a.len2 + a.o2 + cc] : 0.0;
+    for (int e = 0; e < S::EPT_W; ++e)
+      split_store<NT>(st.w[e], &Ws[buf][0][st.wq + e * S::TPR_W][st.wk], BM * KP);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const unsigned short u = bf16_bits((float)rem);
-        Ys[t][nn][kk] = u;
-        rem -= (double)bf16_val(u);
-      }
-    }
+    for (int e = 0; e < S::EPT_Y; ++e)
+      split_store<NT>(st.y[e], &Ys[buf][0][st.yq + e * S::TPR_Y][st.yk], BN * KP);
     __syncthreads();
+    if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
     s8_t av[NT][FM], bv[NT][FN];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        av[t][i] = *reinterpret_cast<const s8_t*>(&Ws[t][wr + i * 16 + lr][lk * 8]);
+        av[t][i] = *reinterpret_cast<const s8_t*>(&Ws[buf][t][wr + i * 16 + lr][lk * 8]);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
-        bv[t][j] = *reinterpret_cast<const s8_t*>(&Ys[t][wc + j * 16 + lr][lk * 8]);
+        bv[t][j] = *reinterpret_cast<const s8_t*>(&Ys[buf][t][wc + j * 16 + lr][lk * 8]);
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -235,7 +306,6 @@ __global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict_
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
             __builtin_bit_cast(bf8_t, av[0][i]), __builtin_bit_cast(bf8_t, bv[0][j]), acc[i][j], 0, 0, 0);
       }
-    __syncthreads();
   }
 
   const float sc = (float)a.scale;
