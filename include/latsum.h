@@ -209,6 +209,55 @@ ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                     int32_t precision, double* F_dev, double* E_dev,
                     void* ws_dev, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Batched lattice systems (project addition; per system Sec. 3.1 box
+ * assembly, Appendix eq. scal energy and eq. CP_form reconstruction).
+ * Each system gives a box lattice, its quadrature, charges, a density in
+ * canonical form and one sub-box of at most min(n, 256) cells per axis to
+ * reconstruct (cell averages, scale 1/h^3). All systems run in one
+ * persistent kernel that drains a device work queue (density folding, then
+ * per-(atom, axis) vector tasks that form the energy Grams against the folded
+ * density and the sub-box factor columns, then MFMA reconstruction tiles),
+ * launched through a hipGraph built on first use. The library allocates the
+ * host-side plan object only; device memory is the caller's workspace.
+ */
+typedef struct {
+  ls_lattice lat;        /* periodic must be 0 */
+  ls_quad quad;          /* host nodes/weights, read during ls_batch_create */
+  int32_t M0;
+  const double* pos_dev; /* [M0][3] */
+  const double* Z_dev;   /* [M0] */
+  ls_canon rho;          /* density, rho.len[l] = N_l, rho.K <= 8 */
+  ls_box box;            /* sub-box, e[l] <= min(n, 256) */
+  void* out_dev;         /* [e0][e1][e2]: double (LS_F64) or float (LS_F32) */
+  double* E_dev;         /* energy <P, rho> */
+} ls_system;
+
+typedef struct ls_batch* ls_batch_t;
+
+/* Plan a batch; *ws_bytes receives the device workspace size.
+ * precision: LS_F64 or LS_F32 (reconstruction; everything else is FP64).
+ * Errors: LS_EINVAL (system index in the message), LS_EUNSUPPORTED. */
+ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
+                          ls_batch_t* batch, size_t* ws_bytes);
+/* Number of tile variants of the batch kernel (tile ids 1..n). */
+int32_t ls_batch_tiles(void);
+/* Enqueue one run on `stream` (graph replay). tile 0 = the autotuned tile
+ * (or a default before autotuning). The first run with a given workspace and
+ * tile uploads the descriptors (synchronously) and builds the graph. */
+ls_status ls_batch_run(ls_batch_t batch, void* ws_dev, size_t ws_bytes, int32_t tile,
+                       hipStream_t stream);
+/* Times every tile variant on this batch (two runs each, synchronous) and
+ * keeps the fastest for tile = 0. *best_ms (nullable) receives its time. */
+ls_status ls_batch_autotune(ls_batch_t batch, void* ws_dev, size_t ws_bytes, hipStream_t stream,
+                            int32_t* best_tile, double* best_ms);
+/* After the last run has completed: per-system device time in seconds
+ * (first task start to last task end, device wall clock) into seconds[count]
+ * (nullable), and the error flag (non-zero if a dependency wait timed out). */
+ls_status ls_batch_report(ls_batch_t batch, const void* ws_dev, double* seconds,
+                          int32_t* error_flag);
+void ls_batch_destroy(ls_batch_t batch);
+
 #ifdef __cplusplus
 }
 #endif

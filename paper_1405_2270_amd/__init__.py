@@ -7,8 +7,8 @@ package only marshals torch tensors into its C ABI.
 """
 from .api import (LatticeSpec, QuadTable, quadrature, master_halfwidth, kernel_vectors, assemble,
                   reconstruct, reconstruct_into, reconstruct_tiles, energy, forces, LatticeEnergy,
-                  lattice_energy)
+                  lattice_energy, Batch)
 
 __all__ = ["LatticeSpec", "QuadTable", "quadrature", "master_halfwidth", "kernel_vectors",
            "assemble", "reconstruct", "reconstruct_into", "reconstruct_tiles", "energy", "forces",
-           "LatticeEnergy", "lattice_energy"]
+           "LatticeEnergy", "lattice_energy", "Batch"]

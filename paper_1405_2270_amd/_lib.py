@@ -37,6 +37,12 @@ class Box(ctypes.Structure):
     _fields_ = [("o", ctypes.c_int32 * 3), ("e", ctypes.c_int32 * 3)]
 
 
+class System(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("quad", Quad), ("M0", ctypes.c_int32),
+                ("pos", ctypes.c_void_p), ("Z", ctypes.c_void_p), ("rho", Canon), ("box", Box),
+                ("out", ctypes.c_void_p), ("E", ctypes.c_void_p)]
+
+
 class LatsumError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__(f"{fn} failed with status {status}: {msg}")
@@ -71,6 +77,15 @@ _SIGNATURES = {
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Canon),
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_size_t, ctypes.c_void_p]),
+    "ls_batch_create": (ctypes.c_int, [ctypes.POINTER(System), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t)]),
+    "ls_batch_tiles": (ctypes.c_int32, []),
+    "ls_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                    ctypes.c_void_p]),
+    "ls_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p, c_int32_p, c_double_p]),
+    "ls_batch_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_int32_p]),
+    "ls_batch_destroy": (None, [ctypes.c_void_p]),
 }
 
 EXPORTS = tuple(_SIGNATURES)

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Lattice, Quad, Canon, Box, check, lib
+from ._lib import Lattice, Quad, Canon, Box, System, check, lib
 
 
 def _stream():
@@ -212,3 +212,79 @@ class LatticeEnergy(torch.autograd.Function):
 
 def lattice_energy(pos, Z, D, d, lat, quad, precision="f64"):
     return LatticeEnergy.apply(pos, Z, D[0], D[1], D[2], d, lat, quad, precision)
+
+
+class Batch:
+    """Many box lattice systems in one persistent launch (graph replay).
+
+    ``systems``: list of dicts with keys lat (LatticeSpec), quad (QuadTable),
+    pos, Z (device float64), D (three device tensors [R_rho][N_l]), d (device
+    [R_rho]) and box (o0, o1, o2, e0, e1, e2), extent at most one unit cell per
+    axis. Outputs: ``self.out[i]`` ([e0][e1][e2] cell averages) and
+    ``self.E[i]`` (energy), both device tensors filled by ``run``.
+    """
+
+    def __init__(self, systems, precision="f32"):
+        self.precision = precision
+        prec = _lib.PRECISIONS[precision]
+        dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
+        dev = systems[0]["pos"].device
+        self._keep = []
+        self.out, self.E = [], []
+        arr = (System * len(systems))()
+        for i, sy in enumerate(systems):
+            b = [int(v) for v in sy["box"]]
+            out = torch.empty((b[3], b[4], b[5]), dtype=dtype, device=dev)
+            E = torch.empty((), dtype=torch.float64, device=dev)
+            self.out.append(out)
+            self.E.append(E)
+            q = sy["quad"]
+            self._keep.append((q, sy["pos"], sy["Z"], sy["D"], sy["d"]))
+            arr[i].lat = sy["lat"].c()
+            arr[i].quad = q.c()
+            arr[i].M0 = int(sy["pos"].shape[0])
+            arr[i].pos = _dev_f64(sy["pos"], "pos").data_ptr()
+            arr[i].Z = _dev_f64(sy["Z"], "Z").data_ptr()
+            arr[i].rho = _canon(sy["D"], sy["d"])
+            arr[i].box = Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
+            arr[i].out = out.data_ptr()
+            arr[i].E = E.data_ptr()
+        self._handle = ctypes.c_void_p(0)
+        ws = ctypes.c_size_t(0)
+        check("ls_batch_create", lib().ls_batch_create(arr, len(systems), prec,
+                                                       ctypes.byref(self._handle), ctypes.byref(ws)))
+        self.ws = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+        self.count = len(systems)
+
+    def run(self, tile=0):
+        check("ls_batch_run", lib().ls_batch_run(self._handle, _ptr(self.ws), self.ws.numel(),
+                                                 int(tile), _stream()))
+
+    def autotune(self):
+        t = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        check("ls_batch_autotune", lib().ls_batch_autotune(self._handle, _ptr(self.ws), self.ws.numel(),
+                                                           _stream(), ctypes.byref(t), ctypes.byref(ms)))
+        return t.value, ms.value
+
+    def report(self):
+        """(per-system seconds, error flag) of the last completed run."""
+        torch.cuda.synchronize()
+        sec = np.zeros(self.count)
+        err = ctypes.c_int32(0)
+        check("ls_batch_report", lib().ls_batch_report(self._handle, _ptr(self.ws),
+                                                       sec.ctypes.data_as(_lib.c_double_p),
+                                                       ctypes.byref(err)))
+        return sec, int(err.value)
+
+    def close(self):
+        if self._handle:
+            torch.cuda.synchronize()
+            lib().ls_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

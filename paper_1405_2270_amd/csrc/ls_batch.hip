@@ -1,0 +1,706 @@
+// Batched lattice systems in one persistent launch (per system: Sec. 3.1,
+// Theorem 3.1 assembly, the canonical scalar product of the Appendix,
+// eq. scal, for the energy, and the reconstruction of one sub-box of at most
+// one unit cell per axis).
+//
+// One kernel, k_batch, drains a device work queue. Workgroups take task
+// indices from a global counter; the queue is ordered by phase, and within a
+// phase by decreasing system cost:
+//   FOLD (system, axis)  Phi_l[s][i] = sum_k rho_l[s][i + k n], the density
+//                        folded back over the lattice shifts (one lane per
+//                        residue class, suffix/prefix sums, no subtraction).
+//   VEC  (system, atom, axis)  for every q: the master cells j in [-X, X) are
+//                        generated in registers; their dot products with Phi
+//                        are the Gram entries G_l[nu q][s] (the assembled
+//                        vector's scalar product with the density), and the
+//                        cells that fall on the requested sub-box are summed
+//                        per residue into its factor columns. The system's
+//                        last VEC task forms E = sum_r coef_r sum_s d_s prod_l G.
+//   TILE (system, tile)  one MFMA tile of the sub-box reconstruction.
+// A VEC task waits until its system's FOLD tasks are done, a TILE until its
+// VEC tasks are done. Every awaited task was dequeued earlier by a running
+// workgroup and never waits on a later one, so every wait ends; each wait is
+// also bounded (a spin limit sets an error flag and skips the task).
+// Producer: all lanes fence (agent scope), barrier, one lane increments the
+// system's counter. Consumer: one lane polls with acquire loads, barrier, all
+// lanes fence (acquire) before reading.
+//
+// Per-system device clock stamps (first task start, last task end) give the
+// per-system latency distribution.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "ls_recon_tile.hpp"
+
+namespace ls {
+
+enum { TASK_FOLD = 0, TASK_VEC = 1, TASK_TILE = 2 };
+
+struct Task {
+  int type, sys, a, pad;
+};
+
+struct SysDev {
+  double b, h;
+  int n, L[3], N[3];
+  int M0, R, K, Krho;
+  int qoff, X, W;
+  int o[3], e[3];
+  int nvec, tiles_n;
+  const double* pos;
+  const double* Z;
+  const double* D[3];
+  const double* d;
+  void* out;
+  double* E;
+  double* Phi;    // [3][Krho][W]
+  double* G;      // [3][K][Krho]
+  double* Fc[3];  // [K][e_l]
+  double* coef;   // [K]
+};
+
+struct BatchArg {
+  const SysDev* sys;
+  const Task* tasks;
+  const double* tau;
+  const double* w;
+  int* head;
+  int* err;
+  int* fold_done;
+  int* vec_done;
+  unsigned long long* t_start;
+  unsigned long long* t_end;
+  int ntasks;
+  int nsys;
+};
+
+constexpr int kSpinLimit = 1 << 22;
+// density rank handled by the batch kernel (per-lane accumulators)
+constexpr int kBatchRho = 8;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Wait until *counter >= target. Returns false (and flags the error) if the
+// spin limit is reached.
+__device__ bool wait_counter(int* counter, int target, int* err, int* s_flag) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    bool ok = true;
+    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(4);
+      ++spins;
+      // after any timed-out wait every later wait fails at once, so a broken
+      // dependency cannot turn into a long series of timeouts
+      if (spins > kSpinLimit ||
+          ((spins & 1023) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+        atomicOr(err, 1);
+        ok = false;
+        break;
+      }
+    }
+    *s_flag = ok ? 1 : 0;
+  }
+  __syncthreads();
+  const bool ok = *s_flag != 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+  return ok;
+}
+
+// Returns the counter value before the increment (in lane 0; -1 elsewhere).
+__device__ int signal_counter(int* counter) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  int prev = -1;
+  if (threadIdx.x == 0) prev = __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return prev;
+}
+
+// Phi_l[s][i + X] = sum_{k=0}^{L-1} D_l[s][i + k n], i in [-X, X + n), D = 0 outside [0, N).
+// For i = rho + c n: c >= 0 -> suffix sum of the residue column from c, c < 0 ->
+// prefix sum up to c + L - 1.
+__device__ void fold_task(const SysDev& S, int l) {
+  const int n = S.n, L = S.L[l], N = S.N[l], X = S.X, W = S.W;
+  for (int s = 0; s < S.Krho; ++s) {
+    const double* D = S.D[l] + (size_t)s * N;
+    double* P = S.Phi + ((size_t)l * S.Krho + s) * W;
+    for (int rho = threadIdx.x; rho < n; rho += 256) {
+      // zero the whole residue column first (c outside [-(L-1), L-1])
+      for (int i = rho; i < W; i += n) P[i] = 0.0;
+      double acc = 0.0;
+      for (int c = L - 1; c >= 0; --c) {
+        acc += D[rho + (size_t)c * n];
+        const long long i = (long long)rho + (long long)c * n + X;
+        if (i >= 0 && i < W) P[i] = acc;
+      }
+      acc = 0.0;
+      for (int cp = 0; cp <= L - 2; ++cp) {
+        acc += D[rho + (size_t)cp * n];
+        const long long i = (long long)rho + (long long)(cp - L + 1) * n + X;
+        if (i >= 0 && i < W) P[i] = acc;
+      }
+    }
+  }
+}
+
+// Vector task: atom nu, axis l, all q.
+__device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbuf) {
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = S.n, L = S.L[l], X = S.X, W = S.W, Krho = S.Krho;
+  const int o = S.o[l], e = S.e[l];
+  int p;
+  double delta;
+  node_offset(S.pos[c], S.b, S.h, n, &p, &delta);
+  const double* ph = S.Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
+  // master cells that land on the sub-box: g = j + p + k n in [o, o+e), k in [0, L)
+  const int jlo = o - p - (L - 1) * n, jhi = o + e - 1 - p;
+  double* cbuf = sbuf;            // 256 cell values
+  double* red = sbuf + 256;       // [4][kBatchRho] wave partials
+#pragma unroll 1
+  for (int q = 0; q < S.R; ++q) {
+    const double tau = ba.tau[S.qoff + q];
+    double acc[kBatchRho];
+#pragma unroll
+    for (int s = 0; s < kBatchRho; ++s) acc[s] = 0.0;
+    double v = 0.0;
+#pragma unroll 1
+    for (int j0 = -X; j0 < X; j0 += 256) {
+      const int j = j0 + tid;
+      double bv = 0.0;
+      if (j < X) {
+        bv = S.h * cell_integral(tau, (double)j - delta);
+        if (bv != 0.0) {
+#pragma unroll
+          for (int s = 0; s < kBatchRho; ++s)
+            if (s < Krho) acc[s] += bv * ph[(size_t)s * W + j];
+        }
+      }
+      if (j0 + 255 >= jlo && j0 <= jhi) {  // uniform per chunk
+        cbuf[tid] = bv;
+        __syncthreads();
+        if (tid < e) {
+          // cells i of this chunk with (j0 + i + p - o) == tid (mod n)
+          int i0 = (tid + o - p - j0) % n;
+          if (i0 < 0) i0 += n;
+#pragma unroll 1
+          for (int i = i0; i < 256; i += n) {
+            const int jj = j0 + i;
+            if (jj >= jlo && jj <= jhi) {
+              const int k = (o + tid - jj - p) / n;  // exact
+              if (k >= 0 && k < L) v += cbuf[i];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // Gram entries: fixed-order wave then cross-wave sums
+    const int r = nu * S.R + q;
+#pragma unroll
+    for (int s = 0; s < kBatchRho; ++s) {
+      if (s < Krho) {
+        const double t = wave_sum(acc[s]);
+        if (lane == 0) red[wv * kBatchRho + s] = t;
+      }
+    }
+    __syncthreads();
+    if (tid < Krho)
+      S.G[((size_t)l * S.K + r) * Krho + tid] =
+          ((red[tid] + red[kBatchRho + tid]) + red[2 * kBatchRho + tid]) + red[3 * kBatchRho + tid];
+    if (tid < e) S.Fc[l][(size_t)r * e + tid] = v;
+    if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q];
+    __syncthreads();
+  }
+}
+
+__device__ void energy_task(const SysDev& S, double* sbuf) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const size_t st = (size_t)S.K * S.Krho;
+  double acc = 0.0;
+  for (int r = tid; r < S.K; r += 256) {
+    double v = 0.0;
+    for (int s = 0; s < S.Krho; ++s) {
+      const size_t i0 = (size_t)r * S.Krho + s;
+      v += S.d[s] * S.G[i0] * S.G[st + i0] * S.G[2 * st + i0];
+    }
+    acc += S.coef[r] * v;
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) sbuf[wv] = acc;
+  __syncthreads();
+  if (tid == 0) *S.E = ((sbuf[0] + sbuf[1]) + sbuf[2]) + sbuf[3];
+  __syncthreads();
+}
+
+template <typename T, int BM, int BN, int WM, int WN, int BK>
+__global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
+  constexpr int RB = recon_smem_bytes<T, BM, BN, BK>();
+  constexpr int VB = (256 + 4 * kBatchRho) * 8;
+  __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
+  __shared__ int s_task, s_flag;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(ba.head, 1);
+    __syncthreads();
+    // wave-uniform task index: descriptor loads become scalar loads
+    const int t = __builtin_amdgcn_readfirstlane(s_task);
+    __syncthreads();
+    if (t >= ba.ntasks) return;
+    const Task tk = ba.tasks[t];
+    const SysDev& S = ba.sys[tk.sys];
+    if (threadIdx.x == 0) atomicMin(&ba.t_start[tk.sys], (unsigned long long)wall_clock64());
+    if (tk.type == TASK_FOLD) {
+      fold_task(S, tk.a);
+      signal_counter(&ba.fold_done[tk.sys]);
+    } else if (tk.type == TASK_VEC) {
+      if (!wait_counter(&ba.fold_done[tk.sys], 3, ba.err, &s_flag)) continue;
+      vec_task(S, ba, tk.a, reinterpret_cast<double*>(smem));
+      const int prev = signal_counter(&ba.vec_done[tk.sys]);
+      if (threadIdx.x == 0) s_flag = (prev == S.nvec - 1) ? 1 : 0;
+      __syncthreads();
+      if (s_flag) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        energy_task(S, reinterpret_cast<double*>(smem));
+        if (threadIdx.x == 0) atomicMax(&ba.t_end[tk.sys], (unsigned long long)wall_clock64());
+      }
+    } else {
+      if (!wait_counter(&ba.vec_done[tk.sys], S.nvec, ba.err, &s_flag)) continue;
+      BoxArg a;
+      a.A1 = S.Fc[0];
+      a.A2 = S.Fc[1];
+      a.A3 = S.Fc[2];
+      a.coef = S.coef;
+      a.K = S.K;
+      a.len0 = S.e[0];
+      a.len1 = S.e[1];
+      a.len2 = S.e[2];
+      a.o0 = a.o1 = a.o2 = 0;
+      a.e0 = S.e[0];
+      a.e1 = S.e[1];
+      a.e2 = S.e[2];
+      a.scale = 1.0 / (S.h * S.h * S.h);
+      const int tm = tk.a / S.tiles_n, tn = tk.a - tm * S.tiles_n;
+      recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
+      __syncthreads();
+      if (threadIdx.x == 0) atomicMax(&ba.t_end[tk.sys], (unsigned long long)wall_clock64());
+    }
+  }
+}
+
+__global__ void k_batch_reset(BatchArg ba) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *ba.head = 0;
+    *ba.err = 0;
+  }
+  if (i < ba.nsys) {
+    ba.fold_done[i] = 0;
+    ba.vec_done[i] = 0;
+    ba.t_start[i] = ~0ull;
+    ba.t_end[i] = 0ull;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct TileCfg {
+  int bm, bn;
+  const void* fn;
+};
+
+template <typename T>
+static bool batch_tile(int tile, TileCfg* c) {
+#define LS_BT(ID, BM_, BN_, WM_, WN_, BK_)                                \
+  if (tile == ID) {                                                      \
+    c->bm = BM_;                                                         \
+    c->bn = BN_;                                                         \
+    c->fn = (const void*)&k_batch<T, BM_, BN_, WM_, WN_, BK_>;           \
+    return true;                                                         \
+  }
+  LS_BT(1, 128, 128, 64, 64, 16)
+  LS_BT(2, 64, 64, 32, 32, 16)
+  LS_BT(3, 128, 64, 64, 32, 16)
+  LS_BT(4, 64, 128, 32, 64, 16)
+#undef LS_BT
+  return false;
+}
+
+static bool get_tile(int precision, int tile, TileCfg* c) {
+  if (precision == LS_F64) return batch_tile<double>(tile, c);
+  if (precision == LS_F32) return batch_tile<float>(tile, c);
+  return false;
+}
+constexpr int kBatchTiles = 4;
+
+struct SysHost {
+  SysDev d;             // pointers into ws are offsets until bound
+  size_t off_phi, off_g, off_fc[3], off_coef;
+  double cost;
+};
+
+}  // namespace ls
+
+struct ls_batch {
+  int precision;
+  int count;
+  std::vector<ls::SysHost> sys;
+  std::vector<double> tau, w;
+  size_t off_ctrl, off_fold, off_vec, off_ts, off_te, off_sys, off_tau, off_w, off_tasks, ws_bytes;
+  // per bound tile: tasks differ only in the tile split of TILE tasks
+  int bound_tile = -1;
+  void* bound_ws = nullptr;
+  int ntasks = 0;
+  int best_tile = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<ls::Task> tasks;
+  std::vector<ls::SysDev> devsys;
+  ls::BatchArg arg;  // kernel-node arguments (kept alive with the graph)
+};
+
+namespace ls {
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static ls_status build_tasks(ls_batch* B, int tile, TileCfg* cfg) {
+  if (!get_tile(B->precision, tile, cfg)) {
+    set_error("tile %d not available for the batch precision", tile);
+    return LS_EUNSUPPORTED;
+  }
+  // LPT order within each phase
+  std::vector<int> order(B->count);
+  for (int i = 0; i < B->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return B->sys[a].cost > B->sys[b].cost; });
+  B->tasks.clear();
+  for (int i : order)
+    for (int l = 0; l < 3; ++l) B->tasks.push_back({TASK_FOLD, i, l, 0});
+  for (int i : order)
+    for (int c = 0; c < 3 * B->sys[i].d.M0; ++c) B->tasks.push_back({TASK_VEC, i, c, 0});
+  for (int i : order) {
+    SysDev& d = B->sys[i].d;
+    const long long M = (long long)d.e[0] * d.e[1];
+    const int tm = (int)((M + cfg->bm - 1) / cfg->bm);
+    d.tiles_n = (d.e[2] + cfg->bn - 1) / cfg->bn;
+    for (int t = 0; t < tm * d.tiles_n; ++t) B->tasks.push_back({TASK_TILE, i, t, 0});
+  }
+  B->ntasks = (int)B->tasks.size();
+  return LS_OK;
+}
+
+static BatchArg make_arg(ls_batch* B, char* ws) {
+  BatchArg a;
+  a.sys = (const SysDev*)(ws + B->off_sys);
+  a.tasks = (const Task*)(ws + B->off_tasks);
+  a.tau = (const double*)(ws + B->off_tau);
+  a.w = (const double*)(ws + B->off_w);
+  a.head = (int*)(ws + B->off_ctrl);
+  a.err = (int*)(ws + B->off_ctrl) + 1;
+  a.fold_done = (int*)(ws + B->off_fold);
+  a.vec_done = (int*)(ws + B->off_vec);
+  a.t_start = (unsigned long long*)(ws + B->off_ts);
+  a.t_end = (unsigned long long*)(ws + B->off_te);
+  a.ntasks = B->ntasks;
+  a.nsys = B->count;
+  return a;
+}
+
+// Upload descriptors for (ws, tile) and build the graph [reset -> k_batch].
+static ls_status bind(ls_batch* B, void* ws_dev, int tile, hipStream_t stream) {
+  if (B->bound_ws == ws_dev && B->bound_tile == tile && B->exec) return LS_OK;
+  TileCfg cfg;
+  ls_status st = build_tasks(B, tile, &cfg);
+  if (st != LS_OK) return st;
+  const size_t task_bytes = sizeof(Task) * B->tasks.size();
+  if (B->off_tasks + task_bytes > B->ws_bytes) {
+    set_error("internal: task list exceeds the planned workspace");
+    return LS_EWORKSPACE;
+  }
+  char* ws = (char*)ws_dev;
+  B->devsys.resize(B->count);
+  for (int i = 0; i < B->count; ++i) {
+    SysDev d = B->sys[i].d;
+    d.Phi = (double*)(ws + B->sys[i].off_phi);
+    d.G = (double*)(ws + B->sys[i].off_g);
+    for (int l = 0; l < 3; ++l) d.Fc[l] = (double*)(ws + B->sys[i].off_fc[l]);
+    d.coef = (double*)(ws + B->sys[i].off_coef);
+    B->devsys[i] = d;
+  }
+  hipError_t e = hipMemcpyAsync(ws + B->off_sys, B->devsys.data(), sizeof(SysDev) * B->count,
+                                hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + B->off_tasks, B->tasks.data(), task_bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + B->off_tau, B->tau.data(), sizeof(double) * B->tau.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + B->off_w, B->w.data(), sizeof(double) * B->w.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    set_error("batch descriptor upload: %s", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  if (B->exec) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+  }
+  if (B->graph) {
+    (void)hipGraphDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  int dev = 0, ncu = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, cfg.fn, 256, 0);
+  if (e != hipSuccess || ncu <= 0) {
+    set_error("device query: %s", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  if (per_cu < 1) per_cu = 1;
+  B->arg = make_arg(B, ws);
+  void* params[] = {&B->arg};
+  e = hipGraphCreate(&B->graph, 0);
+  hipGraphNode_t n_reset = nullptr, n_main = nullptr;
+  if (e == hipSuccess) {
+    hipKernelNodeParams kp = {};
+    kp.func = (void*)&k_batch_reset;
+    kp.gridDim = dim3((B->count + 255) / 256);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    e = hipGraphAddKernelNode(&n_reset, B->graph, nullptr, 0, &kp);
+  }
+  if (e == hipSuccess) {
+    hipKernelNodeParams kp = {};
+    kp.func = (void*)cfg.fn;
+    kp.gridDim = dim3(ncu * per_cu);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    e = hipGraphAddKernelNode(&n_main, B->graph, &n_reset, 1, &kp);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    set_error("batch graph: %s", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  B->bound_ws = ws_dev;
+  B->bound_tile = tile;
+  return LS_OK;
+}
+
+}  // namespace ls
+
+using namespace ls;
+
+extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
+                                     ls_batch_t* batch, size_t* ws_bytes) {
+  clear_error();
+  LS_REQUIRE(systems != nullptr && batch != nullptr && ws_bytes != nullptr, "null pointer");
+  LS_REQUIRE(count >= 1 && count <= (1 << 20), "count must be in [1, 2^20]");
+  if (precision != LS_F64 && precision != LS_F32) {
+    set_error("batches support LS_F64 and LS_F32 reconstruction");
+    return LS_EUNSUPPORTED;
+  }
+  ls_batch* B = new ls_batch();
+  B->precision = precision;
+  B->count = count;
+  B->sys.resize(count);
+  size_t off = 0;
+  B->off_ctrl = off;
+  off += al(64);
+  B->off_fold = off;
+  off += al(sizeof(int) * count);
+  B->off_vec = off;
+  off += al(sizeof(int) * count);
+  B->off_ts = off;
+  off += al(8 * (size_t)count);
+  B->off_te = off;
+  off += al(8 * (size_t)count);
+  B->off_sys = off;
+  off += al(sizeof(SysDev) * (size_t)count);
+  size_t nq = 0, max_tasks = 0;
+  for (int i = 0; i < count; ++i) {
+    const ls_system& S = systems[i];
+    Lat L;
+    ls_status st = check_lattice(&S.lat, &L);
+    QuadArg qa;
+    if (st == LS_OK) st = check_quad(&S.quad, L.h, &qa);
+    if (st != LS_OK) {
+      delete B;
+      return st;
+    }
+    auto fail = [&](const char* msg) {
+      set_error("system %d: %s", i, msg);
+      delete B;
+      return LS_EINVAL;
+    };
+    if (L.periodic) return fail("batches hold box lattices");
+    if (S.M0 < 1 || S.M0 > 20000) return fail("M0 out of range");
+    if (!S.pos_dev || !S.Z_dev || !S.out_dev || !S.E_dev) return fail("null device pointer");
+    if (S.rho.K < 1 || S.rho.K > kBatchRho || !S.rho.coef) return fail("density rank not in [1, 8]");
+    for (int l = 0; l < 3; ++l) {
+      if (!S.rho.f[l] || S.rho.len[l] != L.N[l]) return fail("density length != grid");
+      if (S.box.e[l] < 1 || S.box.e[l] > L.n || S.box.e[l] > 256 || S.box.o[l] < 0 ||
+          S.box.o[l] + S.box.e[l] > L.N[l])
+        return fail("sub-box must lie in the grid with extent in [1, min(n, 256)] per axis");
+    }
+    SysHost& h = B->sys[i];
+    SysDev& d = h.d;
+    memset(&d, 0, sizeof(d));
+    d.b = L.b;
+    d.h = L.h;
+    d.n = L.n;
+    for (int l = 0; l < 3; ++l) {
+      d.L[l] = L.L[l];
+      d.N[l] = L.N[l];
+      d.o[l] = S.box.o[l];
+      d.e[l] = S.box.e[l];
+      d.D[l] = S.rho.f[l];
+    }
+    d.M0 = S.M0;
+    d.R = qa.R;
+    d.K = S.M0 * qa.R;
+    d.Krho = S.rho.K;
+    d.qoff = (int)nq;
+    d.X = master_halfwidth(L);
+    d.W = 2 * d.X + L.n;
+    d.nvec = 3 * S.M0;
+    d.pos = S.pos_dev;
+    d.Z = S.Z_dev;
+    d.d = S.rho.coef;
+    d.out = S.out_dev;
+    d.E = S.E_dev;
+    for (int q = 0; q < qa.R; ++q) {
+      B->tau.push_back(qa.tau[q]);
+      B->w.push_back(qa.w[q]);
+    }
+    nq += qa.R;
+    h.off_phi = off;
+    off += al(sizeof(double) * 3 * (size_t)d.Krho * d.W);
+    h.off_g = off;
+    off += al(sizeof(double) * 3 * (size_t)d.K * d.Krho);
+    for (int l = 0; l < 3; ++l) {
+      h.off_fc[l] = off;
+      off += al(sizeof(double) * (size_t)d.K * d.e[l]);
+    }
+    h.off_coef = off;
+    off += al(sizeof(double) * (size_t)d.K);
+    h.cost = (double)d.K * (2.0 * d.X) + 2.0 * d.K * (double)d.e[0] * d.e[1] * d.e[2] / 64.0;
+    // task count bound: smallest tile 64x64
+    max_tasks += 3 + 3 * (size_t)S.M0 +
+                 (size_t)(((long long)d.e[0] * d.e[1] + 63) / 64) * ((d.e[2] + 63) / 64);
+  }
+  B->off_tau = off;
+  off += al(sizeof(double) * nq);
+  B->off_w = off;
+  off += al(sizeof(double) * nq);
+  B->off_tasks = off;
+  off += al(sizeof(Task) * max_tasks);
+  B->ws_bytes = off;
+  *ws_bytes = off;
+  *batch = B;
+  return LS_OK;
+}
+
+extern "C" int32_t ls_batch_tiles(void) { return kBatchTiles; }
+
+extern "C" ls_status ls_batch_run(ls_batch_t B, void* ws_dev, size_t ws_bytes, int32_t tile,
+                                  hipStream_t stream) {
+  clear_error();
+  LS_REQUIRE(B != nullptr, "null batch");
+  if (ws_dev == nullptr || ws_bytes < B->ws_bytes) {
+    set_error("workspace of %zu bytes required", B->ws_bytes);
+    return LS_EWORKSPACE;
+  }
+  if (tile == 0) tile = B->best_tile ? B->best_tile : 2;
+  ls_status st = bind(B, ws_dev, tile, stream);
+  if (st != LS_OK) return st;
+  hipError_t e = hipGraphLaunch(B->exec, stream);
+  if (e != hipSuccess) {
+    set_error("batch graph launch: %s", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  return LS_OK;
+}
+
+extern "C" ls_status ls_batch_autotune(ls_batch_t B, void* ws_dev, size_t ws_bytes,
+                                       hipStream_t stream, int32_t* best, double* best_ms) {
+  clear_error();
+  LS_REQUIRE(B != nullptr && best != nullptr, "null pointer");
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("event creation failed");
+    return LS_EHIP;
+  }
+  float best_t = 1e30f;
+  int best_id = 0;
+  ls_status st = LS_OK;
+  for (int t = 1; t <= kBatchTiles && st == LS_OK; ++t) {
+    st = ls_batch_run(B, ws_dev, ws_bytes, t, stream);  // warm (binds the graph)
+    if (st != LS_OK) break;
+    (void)hipEventRecord(e0, stream);
+    st = ls_batch_run(B, ws_dev, ws_bytes, t, stream);
+    (void)hipEventRecord(e1, stream);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      set_error("autotune synchronisation failed");
+      st = LS_EHIP;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_t) {
+      best_t = ms;
+      best_id = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LS_OK) return st;
+  B->best_tile = best_id;
+  *best = best_id;
+  if (best_ms) *best_ms = best_t;
+  return LS_OK;
+}
+
+extern "C" ls_status ls_batch_report(ls_batch_t B, const void* ws_dev, double* seconds,
+                                     int32_t* error_flag) {
+  clear_error();
+  LS_REQUIRE(B != nullptr && ws_dev != nullptr, "null pointer");
+  const char* ws = (const char*)ws_dev;
+  std::vector<unsigned long long> ts(B->count), te(B->count);
+  int ctrl[2] = {0, 0};
+  hipError_t e = hipMemcpy(ts.data(), ws + B->off_ts, 8 * (size_t)B->count, hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(te.data(), ws + B->off_te, 8 * (size_t)B->count, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(ctrl, ws + B->off_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+  int dev = 0, khz = 0;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess || khz <= 0) {
+    set_error("batch report: %s", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  if (seconds)
+    for (int i = 0; i < B->count; ++i)
+      seconds[i] = (te[i] >= ts[i] && ts[i] != ~0ull) ? (double)(te[i] - ts[i]) / (khz * 1e3) : -1.0;
+  if (error_flag) *error_flag = ctrl[1];
+  return LS_OK;
+}
+
+extern "C" void ls_batch_destroy(ls_batch_t B) {
+  if (!B) return;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  delete B;
+}

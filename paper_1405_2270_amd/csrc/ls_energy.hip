@@ -59,9 +59,12 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ f0,
     for (int s = 0; s < kMaxRho; ++s)
       if (s < Krho) acc[s] += fv * (T)D[(size_t)s * N + g];
   }
-  for (int s = 0; s < Krho; ++s) {
-    const double tot = block_sum256(acc[s], sh);
-    if (threadIdx.x == 0) G[((size_t)l * K + r) * Krho + s] = tot;
+#pragma unroll
+  for (int s = 0; s < kMaxRho; ++s) {
+    if (s < Krho) {
+      const double tot = block_sum256(acc[s], sh);
+      if (threadIdx.x == 0) G[((size_t)l * K + r) * Krho + s] = tot;
+    }
   }
 }
 
@@ -143,12 +146,15 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
     }
   }
   const int r = nu * qa.R + q;
-  for (int s = 0; s < Krho; ++s) {
-    const double tv = block_sum256(av[s], sh);
-    const double td = block_sum256(ad[s], sh);
-    if (threadIdx.x == 0) {
-      Gv[((size_t)l * K + r) * Krho + s] = tv;
-      Gd[((size_t)l * K + r) * Krho + s] = td;
+#pragma unroll
+  for (int s = 0; s < kMaxRho; ++s) {
+    if (s < Krho) {
+      const double tv = block_sum256(av[s], sh);
+      const double td = block_sum256(ad[s], sh);
+      if (threadIdx.x == 0) {
+        Gv[((size_t)l * K + r) * Krho + s] = tv;
+        Gd[((size_t)l * K + r) * Krho + s] = td;
+      }
     }
   }
 }

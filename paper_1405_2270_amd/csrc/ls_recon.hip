@@ -22,191 +22,14 @@
 // A[l%16][k-group l/16] and B[k-group l/16][l%16]. It receives D[4*(l/16) + v][l%16]
 // (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
 // f64 one (checked on gfx950).
-#include "ls_common.hpp"
+#include "ls_recon_tile.hpp"
 
 namespace ls {
 
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-typedef short s8_t __attribute__((ext_vector_type(8)));
-
-struct BoxArg {
-  const double* A1;
-  const double* A2;
-  const double* A3;
-  const double* coef;
-  int K;
-  int len0, len1, len2;
-  int o0, o1, o2;
-  int e0, e1, e2;
-  double scale;
-};
-
-template <typename T>
-struct Acc;
-template <>
-struct Acc<double> {
-  typedef d4_t type;
-};
-template <>
-struct Acc<float> {
-  typedef f4_t type;
-};
-
-__device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Operand staging shared by all precisions. One rank chunk of BK rows is
-// staged per step; lane t of the workgroup owns rank row kk = t / TPR and
-// rows m = q + TPR*e (q = t % TPR, e = 0..EPT-1) of the W operand, so every
-// load instruction of a 16-lane group reads 16 consecutive doubles.
-// Fast path (uniform per workgroup): the BM rows of the tile share one i,
-// so W[r][m] = alpha_r * f1[r][o1 + j0 + m - row0] with alpha_r = coef[r] f0[r][o0 + i]
-// (two scalar loads per rank row); otherwise every element does its own
-// index arithmetic.
-template <int BM, int BN, int BK>
-struct Stager {
-  static constexpr int EPT_W = BK * BM / 256;
-  static constexpr int TPR_W = BM / EPT_W;
-  static constexpr int EPT_Y = BK * BN / 256;
-  static constexpr int TPR_Y = BN / EPT_Y;
-  static_assert(EPT_W >= 1 && EPT_Y >= 1 && TPR_W * BK == 256 && TPR_Y * BK == 256, "staging map");
-
-  int wk, wq, yk, yq;
-  int row0, col0, M, i0, j0;
-  bool wfast, yfast;
-  double w[EPT_W];
-  double y[EPT_Y];
-
-  __device__ __forceinline__ void init(const BoxArg& a, int r0, int c0) {
-    const int tid = threadIdx.x;
-    wk = tid / TPR_W;
-    wq = tid - wk * TPR_W;
-    yk = tid / TPR_Y;
-    yq = tid - yk * TPR_Y;
-    row0 = r0;
-    col0 = c0;
-    M = a.e0 * a.e1;
-    i0 = row0 / a.e1;
-    j0 = row0 - i0 * a.e1;
-    wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
-    yfast = col0 + BN <= a.e2;
-  }
-
-  __device__ __forceinline__ void load(const BoxArg& a, int k0) {
-    const int r = k0 + wk;
-    if (r < a.K) {
-      if (wfast) {
-        const double alpha = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i0];
-        const double* src = a.A2 + (size_t)r * a.len1 + a.o1 + j0 + wq;
-#pragma unroll
-        for (int e = 0; e < EPT_W; ++e) w[e] = alpha * src[e * TPR_W];
-      } else {
-#pragma unroll
-        for (int e = 0; e < EPT_W; ++e) {
-          const int m = row0 + wq + e * TPR_W;
-          double v = 0.0;
-          if (m < M) {
-            const int i = m / a.e1, j = m - i * a.e1;
-            v = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i] * a.A2[(size_t)r * a.len1 + a.o1 + j];
-          }
-          w[e] = v;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < EPT_W; ++e) w[e] = 0.0;
-    }
-    const int ry = k0 + yk;
-    if (ry < a.K) {
-      const double* src = a.A3 + (size_t)ry * a.len2 + a.o2 + col0 + yq;
-      if (yfast) {
-#pragma unroll
-        for (int e = 0; e < EPT_Y; ++e) y[e] = src[e * TPR_Y];
-      } else {
-#pragma unroll
-        for (int e = 0; e < EPT_Y; ++e) y[e] = (col0 + yq + e * TPR_Y < a.e2) ? src[e * TPR_Y] : 0.0;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < EPT_Y; ++e) y[e] = 0.0;
-    }
-  }
-};
-
-// FP64 / FP32 tile kernel. T = operand type. Two LDS buffers: the global
-// loads of chunk c+1 are in flight while the MFMAs consume chunk c.
 template <typename T, int BM, int BN, int WM, int WN, int BK>
 __global__ __launch_bounds__(256) void k_recon(BoxArg a, T* __restrict__ out) {
-  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
-  typedef typename Acc<T>::type acc_t;
-  constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
-  __shared__ T Ws[2][BK][BM + PAD];
-  __shared__ T Ys[2][BK][BN + PAD];
-
-  const int M = a.e0 * a.e1;
-  const int row0 = blockIdx.x * BM;
-  const int col0 = blockIdx.y * BN;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = (wave / (BN / WN)) * WM;
-  const int wc = (wave % (BN / WN)) * WN;
-  const int lr = lane & 15;
-  const int lk = lane >> 4;
-
-  acc_t acc[FM][FN];
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
-  Stager<BM, BN, BK> st;
-  st.init(a, row0, col0);
-  st.load(a, 0);
-  const int nchunk = (a.K + BK - 1) / BK;
-  for (int c = 0; c < nchunk; ++c) {
-    const int buf = c & 1;
-#pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
-      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (T)st.w[e];
-#pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
-      Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (T)st.y[e];
-    __syncthreads();
-    if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T av[FM], bv[FN];
-#pragma unroll
-      for (int i = 0; i < FM; ++i) av[i] = Ws[buf][kk + lk][wr + i * 16 + lr];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kk + lk][wc + j * 16 + lr];
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
-    }
-  }
-
-  const T sc = (T)a.scale;
-  constexpr bool f64_layout = sizeof(T) == 8;
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + wr + i * 16 + (f64_layout ? lk + 4 * v : 4 * lk + v);
-        const int col = col0 + wc + j * 16 + lr;
-        if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
-      }
+  __shared__ __attribute__((aligned(16))) char smem[recon_smem_bytes<T, BM, BN, BK>()];
+  recon_tile<T, BM, BN, WM, WN, BK>(a, blockIdx.x * BM, blockIdx.y * BN, out, smem);
 }
 
 // ---------------------------------------------------------------------------

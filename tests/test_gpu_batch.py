@@ -1,0 +1,139 @@
+"""Batched systems in one persistent launch against the FP64 oracle.
+
+Each system's energy (FP64 throughout) and its reconstructed sub-box (FP64 or
+FP32 reconstruction) are compared with the oracle; graph replays must be
+bitwise identical; the autotuned tile must give the same results."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.lattice import Geometry, direct_factors, factor_entries
+from oracle.canonical import reconstruct as o_reconstruct, sample_columns
+from oracle.physics import energy as o_energy
+from oracle.quadrature import rule_s
+from workloads import small_box, config4
+
+pytestmark = pytest.mark.gpu
+dev = torch.device("cuda:0")
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def _systems():
+    out = []
+    specs = [dict(seed=201, n=8, L=(3, 3, 3), M0=2, box="cell"),
+             dict(seed=202, n=12, L=(2, 4, 3), M0=3, box="ragged"),
+             dict(seed=203, n=6, L=(5, 2, 2), M0=1, box="cell", neutral=False),
+             dict(seed=204, n=16, L=(2, 2, 2), M0=4, box="ragged"),
+             dict(seed=205, n=10, L=(4, 4, 1), M0=2, box="cell")]
+    for sp in specs:
+        s = small_box(sp["seed"], n=sp["n"], L=sp["L"], M0=sp["M0"], neutral=sp.get("neutral", True))
+        rng = np.random.default_rng(sp["seed"])
+        if sp["box"] == "cell":
+            o = [(s.L[l] // 2) * s.n for l in range(3)]
+            e = [s.n] * 3
+        else:
+            e = [int(rng.integers(1, s.n + 1)) for _ in range(3)]
+            o = [int(rng.integers(0, s.L[l] * s.n - e[l] + 1)) for l in range(3)]
+        out.append((s, tuple(o) + tuple(e)))
+    return out
+
+
+def _batch(L, systems, precision):
+    items = []
+    for s, box in systems:
+        q = s.quad
+        items.append(dict(lat=L.LatticeSpec(s.b, s.n, s.L, False),
+                          quad=L.quadrature("S", q["M"], q["C0"], q["s"]),
+                          pos=_t(s.pos), Z=_t(s.Z), D=[_t(x) for x in s.density.D],
+                          d=_t(s.density.d), box=box))
+    return L.Batch(items, precision)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_against_oracle(precision):
+    import paper_1405_2270_amd as L
+    systems = _systems()
+    B = _batch(L, systems, precision)
+    B.run(tile=2)
+    sec, err = B.report()
+    assert err == 0 and np.all(sec > 0)
+    first = [o.double().cpu().numpy().copy() for o in B.out]
+    E1 = [float(e.cpu()) for e in B.E]
+    for i, (s, box) in enumerate(systems):
+        q = s.quad
+        t, w = rule_s(q["M"], q["C0"], q["s"])
+        geom = Geometry(s.b, s.n, s.L, False)
+        Eo = o_energy(geom, t, w, s.pos, s.Z, s.density.D, s.density.d)
+        Eabs = o_energy(geom, t, w, s.pos, np.abs(s.Z), s.density.D, s.density.d)
+        assert abs(E1[i] - Eo) / abs(Eabs) < 1e-12, (i, E1[i], Eo)
+        Fo, co = direct_factors(geom, t, w, s.pos, s.Z)
+        ref = o_reconstruct(Fo, co, box[:3], box[3:]) / s.h ** 3
+        ref_abs = o_reconstruct(Fo, np.abs(co), box[:3], box[3:]) / s.h ** 3
+        err_v = np.max(np.abs(first[i] - ref)) / np.max(np.abs(ref_abs))
+        assert err_v < (1e-12 if precision == "f64" else 1e-6), (i, err_v)
+    # graph replay: bitwise identical
+    B.run(tile=2)
+    torch.cuda.synchronize()
+    for i in range(len(systems)):
+        assert np.array_equal(B.out[i].double().cpu().numpy(), first[i])
+        assert float(B.E[i].cpu()) == E1[i]
+    # every tile variant and the autotuned one give the same values
+    for tile in range(1, L.api.lib().ls_batch_tiles() + 1):
+        B.run(tile=tile)
+        torch.cuda.synchronize()
+        for i in range(len(systems)):
+            a = B.out[i].double().cpu().numpy()
+            assert np.max(np.abs(a - first[i])) <= 1e-12 * np.max(np.abs(first[i])) + 1e-300
+    best, ms = B.autotune()
+    assert 1 <= best <= L.api.lib().ls_batch_tiles() and ms > 0
+    B.run()
+    sec, err = B.report()
+    assert err == 0
+    B.close()
+
+
+def test_batch_rejects_bad_systems():
+    import paper_1405_2270_amd as L
+    from paper_1405_2270_amd._lib import LatsumError
+    (s, box), = _systems()[:1]
+    bad = (0, 0, 0, s.n + 1, 2, 2)   # extent beyond one unit cell
+    with pytest.raises(LatsumError):
+        _batch(L, [(s, bad)], "f64")
+    with pytest.raises(LatsumError):
+        _batch(L, [(s, box)], "bf16x3")
+
+
+@pytest.mark.slow
+def test_config4_smallest_systems_against_oracle():
+    # the batched workload's own systems: the six cheapest (oracle cost) in a
+    # batch with six mid-size ones; sampled sub-box values and energies
+    import paper_1405_2270_amd as L
+    systems = config4()
+    cost = [s.K * s.N(0) * s.L[0] for s in systems]
+    order = np.argsort(cost)
+    pick = list(order[:6]) + list(order[200:206])
+    chosen = [(systems[i], tuple(int(v) for v in systems[i].boxes[0])) for i in pick]
+    B = _batch(L, chosen, "f32")
+    B.run()
+    sec, err = B.report()
+    assert err == 0
+    rng = np.random.default_rng(9)
+    for k, (s, box) in enumerate(chosen[:6]):
+        q = s.quad
+        t, w = rule_s(q["M"], q["C0"], q["s"])
+        geom = Geometry(s.b, s.n, s.L, False)
+        Eo = o_energy(geom, t, w, s.pos, s.Z, s.density.D, s.density.d)
+        Eabs = o_energy(geom, t, w, s.pos, np.abs(s.Z), s.density.D, s.density.d)
+        assert abs(float(B.E[k].cpu()) - Eo) / abs(Eabs) < 1e-12
+        sel_local = [np.sort(rng.choice(box[3 + l], 5, replace=False)) for l in range(3)]
+        cols = [factor_entries(geom, t, s.pos, l, box[l] + sel_local[l]) for l in range(3)]
+        sel = np.array(np.meshgrid(np.arange(5), np.arange(5), np.arange(5), indexing="ij")).reshape(3, -1).T
+        coef = (s.Z[:, None] * w[None, :]).ravel()
+        ref = np.asarray(sample_columns(cols, coef, sel), np.float64) / s.h ** 3
+        ref_abs = np.asarray(sample_columns(cols, np.abs(coef), sel), np.float64) / s.h ** 3
+        got = B.out[k][sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
+        assert np.max(np.abs(got.double().cpu().numpy() - ref)) / np.max(np.abs(ref_abs)) < 1e-6
+    B.close()
