@@ -36,7 +36,123 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forces", action="store_true")
     p.add_argument("--cpu-sample-edge", type=int, default=160)
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--no-periodic", action="store_true")
+    p.add_argument("--batch-count", type=int, default=512)
+    p.add_argument("--mode", choices=["bench", "kernels"], default="bench",
+                   help="kernels: one launch of each hot-path kernel on the headline workload "
+                        "plus a 1 GiB device copy, for hardware-counter runs")
     return p.parse_args()
+
+
+def kernels_once():
+    """One launch of each hot-path kernel on the headline workload, preceded by
+    a plain 1 GiB device-to-device copy whose counters calibrate the traffic
+    counters (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    import numpy as np
+    import torch
+    import paper_1405_2270_amd as L
+    from workloads import config2
+    dev = torch.device("cuda:0")
+    T = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s = config2()
+    q = s.quad
+    spec = L.LatticeSpec(s.b, s.n, s.L, False)
+    qt = L.quadrature("S", q["M"], q["C0"], q["s"])
+    pos, Z = T(s.pos), T(s.Z)
+    masters = L.kernel_vectors(spec, qt, pos)
+    F, coef = L.assemble(spec, qt, pos, Z, masters)
+    E = L.energy(F, coef, [T(x) for x in s.density.D], T(s.density.d), "f64")
+    box = [tuple(int(v) for v in s.boxes[0])]
+    for prec in ("f64", "f32"):
+        L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))
+
+
+def bench_batch(L, T, count, steps, warmup):
+    """Batched workload: `count` box systems in one persistent launch (graph
+    replay), FP32 reconstruction of each system's central unit cell, FP64
+    energies. Tile picked by the library's autotuner."""
+    import numpy as np
+    import torch
+    from workloads import config4
+    systems = config4(count)
+    items = []
+    for s in systems:
+        q = s.quad
+        items.append(dict(lat=L.LatticeSpec(s.b, s.n, s.L, False),
+                          quad=L.quadrature("S", q["M"], q["C0"], q["s"]),
+                          pos=T(s.pos), Z=T(s.Z), D=[T(x) for x in s.density.D], d=T(s.density.d),
+                          box=tuple(int(v) for v in s.boxes[0])))
+    B = L.Batch(items, "f32")
+    tile, tune_ms = B.autotune()
+    for _ in range(warmup):
+        B.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        B.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sec, err = B.report()
+    nvals = sum(int(np.prod(s.boxes[0][3:])) for s in systems)
+    flops = sum(2.0 * int(np.prod(s.boxes[0][3:])) * s.K for s in systems)
+    B.close()
+    return {"systems": count, "precision": "f32", "tile": tile, "error_flag": err,
+            "ms_per_run": round(ms, 4), "values": nvals, "values_per_s": nvals / (ms / 1e3),
+            "recon_gflop": round(flops / 1e9, 1),
+            "p50_ms": round(float(np.percentile(sec, 50)) * 1e3, 4),
+            "p99_ms": round(float(np.percentile(sec, 99)) * 1e3, 4),
+            "max_ms": round(float(np.max(sec)) * 1e3, 4)}
+
+
+def bench_periodic(L, T, steps, warmup):
+    """Periodic workload: 64 charges, n=256, 64 images per axis, R=60 (K=3840):
+    fused periodic assembly -> energy -> reconstruction of the 256^3 cell."""
+    import torch
+    from workloads import config3
+    s = config3()
+    q = s.quad
+    spec = L.LatticeSpec(s.b, s.n, s.L, True)
+    pos, Z = T(s.pos), T(s.Z)
+    D = [T(x) for x in s.density.D]
+    d = T(s.density.d)
+    box = [tuple(int(v) for v in s.boxes[0])]
+    res = {}
+    outs = {}
+    for prec in ("f64", "f32"):
+        def step():
+            qt = L.quadrature("S", q["M"], q["C0"], q["s"])
+            F, coef = L.assemble(spec, qt, pos, Z)
+            E = L.energy(F, coef, D, d, "f64")
+            V = L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec)[0]
+            return F, coef, E, V
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            F, coef, E, V = step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        outs[prec] = V
+        res[prec] = {"ms_per_step": round(ms, 4), "values_per_s": s.n ** 3 / (ms / 1e3)}
+    Vabs = L.reconstruct(F, coef.abs(), box, 1.0 / s.h ** 3, "f64")[0]
+    err = float((outs["f32"].double() - outs["f64"]).abs().max())
+    res["f32"]["rel_inf"] = err / float(outs["f64"].abs().max())
+    res["f32"]["rel_mag"] = err / float(Vabs.abs().max())
+    res["energy"] = float(E.cpu())
+    res["K"] = s.K
+    return res
 
 
 def cpu_baseline(sysm, edge):
@@ -64,6 +180,9 @@ def cpu_baseline(sysm, edge):
 
 def main():
     args = parse()
+    if args.mode == "kernels":
+        kernels_once()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how the work would shard).", file=sys.stderr)
@@ -174,6 +293,9 @@ def main():
         F32, _ = L.forces(spec5, qt5, pos5, Z5, D5, d5, "f32")
         forces["f32"]["rel_err"] = float((F32 - F64).abs().max() / F64.abs().max())
 
+    batched = None if args.no_batch else bench_batch(L, T, args.batch_count, args.steps, 1)
+    periodic = None if args.no_periodic else bench_periodic(L, T, args.steps, 1)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sysm, args.cpu_sample_edge)
@@ -199,10 +321,12 @@ def main():
                  "ms_per_step": results["f64"]["ms_per_step"],
                  "recon_tflops": results["f64"]["recon_tflops"]},
         "mixed_speedup_vs_fp64": results["f64"]["ms_per_step"] / rb["ms_per_step"],
-        "variants": {p: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+        "variants": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()}
                      for p, r in results.items()},
         "energy": float(E.cpu()),
         "forces": forces,
+        "batched": batched,
+        "periodic": periodic,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -52,6 +52,17 @@ def forces_adjoint(geom, t, w, pos, Z, D, d):
     return out
 
 
+def forces_adjoint_atoms(geom, t, w, pos, Z, D, d, atoms):
+    """Rows ``atoms`` of ``forces_adjoint``, computing only those atoms'
+    vectors (the force on atom nu involves atom nu's Grams only)."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    Z = np.asarray(Z, np.float64)
+    out = np.zeros((len(atoms), 3))
+    for i, nu in enumerate(atoms):
+        out[i] = forces_adjoint(geom, t, w, pos[nu:nu + 1], Z[nu:nu + 1], D, d)[0]
+    return out
+
+
 def forces_fd(geom, t, w, pos, Z, D, d, step):
     """Central finite differences of the oracle energy (step in length units)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)

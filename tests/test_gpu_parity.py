@@ -15,9 +15,9 @@ import torch
 
 from oracle.lattice import Geometry, direct_factors, master_vectors, node_and_offset, factor_entries
 from oracle.canonical import reconstruct as o_reconstruct, sample_columns
-from oracle.physics import energy as o_energy, forces_adjoint
+from oracle.physics import energy as o_energy, forces_adjoint, forces_adjoint_atoms
 from oracle.quadrature import rule_u, rule_s
-from workloads import small_box, small_periodic, config1, config2
+from workloads import small_box, small_periodic, config1, config2, config3, config5
 
 pytestmark = pytest.mark.gpu
 
@@ -64,14 +64,16 @@ def _gpu_factors(L, sysm, qt, fused=False):
     return F, coef
 
 
-def _close_rows(a, b, rtol):
+def _close_rows(a, b, rtol, rowscale=None):
     """Row-wise normwise agreement: max_j |a_rj - b_rj| <= rtol * scale_r with
-    scale_r = max(max_j |b_rj|, 1e-12 * max |b|). Elementwise relative checks
+    scale_r = max(max_j |b_rj|, 1e-12 * max |b|), where max_j runs over the
+    whole vector when only some of its entries are compared (``rowscale``:
+    the vector maxima). Elementwise relative checks
     would be limited by input conditioning: in a Gaussian tail exp(-u^2)
     turns the rounding of the cell offset (~eps * n cells, from the position
     given in FP64) into a relative error of 2u * du on either side."""
-    rowmax = np.max(np.abs(b), axis=1)
-    scale = np.maximum(rowmax, 1e-12 * np.max(np.abs(b)))
+    rowmax = np.max(np.abs(b), axis=1) if rowscale is None else np.asarray(rowscale)
+    scale = np.maximum(rowmax, 1e-12 * np.max(rowmax))
     err = np.max(np.abs(a - b), axis=1)
     bad = err > rtol * scale
     if np.any(bad):
@@ -309,7 +311,7 @@ def test_config2_sampled(L):
         cols = [factor_entries(geom, t, sysm.pos, l, b[l] + sel_local[l]) for l in range(3)]
         for l in range(3):
             got = F[l][:, b[l] + sel_local[l]].cpu().numpy()
-            assert _close_rows(got, cols[l], 1e-12)
+            assert _close_rows(got, cols[l], 1e-12, F[l].abs().max(dim=1).values.cpu().numpy())
         sel = np.array(np.meshgrid(np.arange(6), np.arange(6), np.arange(6), indexing="ij")).reshape(3, -1).T
         coef_o = (sysm.Z[:, None] * w[None, :]).ravel()
         ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
@@ -321,3 +323,59 @@ def test_config2_sampled(L):
             assert rel_mag < PREC_GATES[precision], (precision, rel_inf, rel_mag)
             del V
             torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+def test_config3_periodic_sampled(L):
+    # periodic workload at full size: factor columns and sampled cell values
+    sysm = config3()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    geom = _geom(sysm)
+    rng = np.random.default_rng(11)
+    sel_local = [np.sort(rng.choice(sysm.n, 5, replace=False)) for l in range(3)]
+    cols = [factor_entries(geom, t, sysm.pos, l, sel_local[l]) for l in range(3)]
+    for l in range(3):
+        assert _close_rows(F[l][:, sel_local[l]].cpu().numpy(), cols[l], 1e-12,
+                           F[l].abs().max(dim=1).values.cpu().numpy())
+    sel = np.array(np.meshgrid(np.arange(5), np.arange(5), np.arange(5), indexing="ij")).reshape(3, -1).T
+    coef_o = (sysm.Z[:, None] * w[None, :]).ravel()
+    h3 = sysm.h ** 3
+    ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
+    ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
+    for precision in ("f64", "f32"):
+        V = L.reconstruct(F, coef, [tuple(sysm.boxes[0])], 1.0 / h3, precision)[0]
+        got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
+        rel_inf, rel_mag = _errors(got.double().cpu().numpy(), ref, ref_abs)
+        assert rel_mag < PREC_GATES[precision], (precision, rel_inf, rel_mag)
+
+
+@pytest.mark.slow
+def test_config5_forces_sampled(L):
+    # forces workload at full size: oracle adjoint on sampled atoms, and the
+    # GPU FP64 energy's central differences (step 1e-4 b) on the same atoms
+    sysm = config5()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    F64, E64 = L.forces(spec, qt, _t(sysm.pos), _t(sysm.Z), D, d, "f64")
+    F32, _ = L.forces(spec, qt, _t(sysm.pos), _t(sysm.Z), D, d, "f32")
+    F64 = F64.cpu().numpy()
+    F32 = F32.cpu().numpy()
+    atoms = [0, 17, 42]
+    geom = _geom(sysm)
+    Fo = forces_adjoint_atoms(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d, atoms)
+    scale = np.max(np.abs(Fo))
+    assert np.max(np.abs(F64[atoms] - Fo)) / scale < 1e-11
+    assert np.max(np.abs(F32[atoms] - Fo)) / scale < 1e-5
+    step = sysm.extra["fd_step"]
+    for nu in atoms:
+        for l in range(3):
+            pp, pm = sysm.pos.copy(), sysm.pos.copy()
+            pp[nu, l] += step
+            pm[nu, l] -= step
+            Ep = float(L.forces(spec, qt, _t(pp), _t(sysm.Z), D, d, "f64")[1].cpu())
+            Em = float(L.forces(spec, qt, _t(pm), _t(sysm.Z), D, d, "f64")[1].cpu())
+            fd = -(Ep - Em) / (2 * step)
+            assert abs(fd - F64[nu, l]) < 1e-5 * np.max(np.abs(F64)), (nu, l, fd, F64[nu, l])

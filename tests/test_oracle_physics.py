@@ -4,8 +4,8 @@ import pytest
 
 from oracle.lattice import Geometry, direct_factors, assembled_factors
 from oracle.canonical import reconstruct
-from oracle.physics import (energy, forces_adjoint, forces_fd, richardson_linear,
-                            richardson_quadratic)
+from oracle.physics import (energy, forces_adjoint, forces_adjoint_atoms, forces_fd,
+                            richardson_linear, richardson_quadratic)
 from workloads import small_box, small_periodic
 from oracle.quadrature import rule_s, rule_u
 
@@ -81,3 +81,12 @@ def test_neutral_periodic_sum_converges_in_L():
         F, c = assembled_factors(geom, t, w, pos, Z)
         vals.append(float(reconstruct(F, c, (1, 1, 1), (1, 1, 1))[0, 0, 0]) / geom.h ** 3)
     assert abs(vals[2] - vals[1]) < 0.5 * abs(vals[1] - vals[0])
+
+
+def test_forces_of_selected_atoms_match_full_adjoint():
+    sysm = small_box(51, n=8, M0=4)
+    t, w = _tw(sysm)
+    geom = _geom(sysm)
+    full = forces_adjoint(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
+    part = forces_adjoint_atoms(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d, [2, 0])
+    assert np.allclose(part, full[[2, 0]], rtol=1e-13, atol=1e-15 * np.abs(full).max())
