@@ -148,6 +148,12 @@ __device__ void fold_task(const SysDev& S, int l) {
   }
 }
 
+// Out-of-line cell integral: keeps the erfc/series evaluation's constants and
+// temporaries out of the persistent kernel's loop nests (register pressure).
+__device__ __attribute__((noinline)) double cell_integral_ool(double tau, double y0) {
+  return cell_integral(tau, y0);
+}
+
 // Vector task: atom nu, axis l, all q.
 __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbuf) {
   const int nu = c / 3, l = c - 3 * (c / 3);
@@ -169,12 +175,16 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
 #pragma unroll
     for (int s = 0; s < kBatchRho; ++s) acc[s] = 0.0;
     double v = 0.0;
+    // cells beyond the Gaussian's support contribute exactly 0
+    const double hw = support_halfwidth(tau);
+    const int jbeg = (int)fmax((double)-X, floor(delta - hw));
+    const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
 #pragma unroll 1
-    for (int j0 = -X; j0 < X; j0 += 256) {
+    for (int j0 = jbeg; j0 < jend; j0 += 256) {
       const int j = j0 + tid;
       double bv = 0.0;
-      if (j < X) {
-        bv = S.h * cell_integral(tau, (double)j - delta);
+      if (j < jend) {
+        bv = S.h * cell_integral_ool(tau, (double)j - delta);
         if (bv != 0.0) {
 #pragma unroll
           for (int s = 0; s < kBatchRho; ++s)

@@ -131,6 +131,13 @@ __device__ __forceinline__ double cell_derivative(double tau, double y0) {
   return exp(-e) * expm1(t2 * dsq);
 }
 
+// Cells whose offset from the charge satisfies |y| > support_halfwidth(tau)
+// (grid units) have |tau*y| > 28 at both edges: cell_integral and
+// cell_derivative return exactly 0 there, so loops may skip them.
+__device__ __forceinline__ double support_halfwidth(double tau) {
+  return tau > 0.0 ? 28.0 / tau + 2.0 : 1e300;
+}
+
 // Node index p and offset delta of a coordinate, (a + b/2)/h = p + delta.
 // p = floor((a + b/2)/h) clamped to [0, n-1], so every memory index derived
 // from p stays inside its buffer for any input (a NaN position gives NaN

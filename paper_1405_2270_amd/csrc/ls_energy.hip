@@ -130,8 +130,11 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
     av[s] = 0;
     ad[s] = 0;
   }
-  for (int jj = threadIdx.x; jj < 2 * X; jj += 256) {
-    const int j = jj - X;
+  // cells beyond the Gaussian's support contribute exactly 0
+  const double hw = support_halfwidth(tau);
+  const int jbeg = (int)fmax((double)-X, floor(delta - hw));
+  const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
+  for (int j = jbeg + (int)threadIdx.x; j < jend; j += 256) {
     const double y0 = (double)j - delta;
     const double bv = lat.h * cell_integral(tau, y0);
     const double bd = cell_derivative(tau, y0);

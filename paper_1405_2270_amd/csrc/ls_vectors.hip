@@ -122,7 +122,13 @@ __global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict
   double delta;
   node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
   const double tau = qa.tau[q];
-  const int k0 = lat.kmin[l], k1 = lat.kmin[l] + lat.L[l];
+  int k0 = lat.kmin[l], k1 = lat.kmin[l] + lat.L[l];
+  // images whose cell lies beyond the Gaussian's support contribute exactly 0:
+  // |g - p - k n - delta| <= hw  <=>  k in [(g - p - delta - hw)/n, (g - p - delta + hw)/n]
+  const double hw = support_halfwidth(tau);
+  const double base = (double)(g - p) - delta;
+  k0 = (int)fmax((double)k0, floor((base - hw) / lat.n));
+  k1 = (int)fmin((double)k1, ceil((base + hw) / lat.n) + 1.0);
   double acc = 0.0;
   for (int k = k0; k < k1; ++k) {
     const double y0 = (double)(g - p - k * lat.n) - delta;
