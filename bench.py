@@ -101,7 +101,7 @@ def bench_batch(L, T, count, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    sec, err = B.report()
+    sec, err, ph = B.report(phases=True)
     nvals = sum(int(np.prod(s.boxes[0][3:])) for s in systems)
     flops = sum(2.0 * int(np.prod(s.boxes[0][3:])) * s.K for s in systems)
     B.close()
@@ -110,7 +110,9 @@ def bench_batch(L, T, count, steps, warmup):
             "recon_gflop": round(flops / 1e9, 1),
             "p50_ms": round(float(np.percentile(sec, 50)) * 1e3, 4),
             "p99_ms": round(float(np.percentile(sec, 99)) * 1e3, 4),
-            "max_ms": round(float(np.max(sec)) * 1e3, 4)}
+            "max_ms": round(float(np.max(sec)) * 1e3, 4),
+            "phase_ms": {"fold": round(ph[0] * 1e3, 4), "vectors": round(ph[1] * 1e3, 4),
+                         "tiles": round(ph[2] * 1e3, 4)}}
 
 
 def bench_periodic(L, T, steps, warmup):

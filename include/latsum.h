@@ -253,9 +253,11 @@ ls_status ls_batch_autotune(ls_batch_t batch, void* ws_dev, size_t ws_bytes, hip
                             int32_t* best_tile, double* best_ms);
 /* After the last run has completed: per-system device time in seconds
  * (first task start to last task end, device wall clock) into seconds[count]
- * (nullable), and the error flag (non-zero if a dependency wait timed out). */
+ * (nullable), the span of each phase (folding, vector tasks, tiles: first
+ * start to last end) into phase_seconds[3] (nullable), and the error flag
+ * (non-zero if a dependency wait timed out). */
 ls_status ls_batch_report(ls_batch_t batch, const void* ws_dev, double* seconds,
-                          int32_t* error_flag);
+                          double* phase_seconds, int32_t* error_flag);
 void ls_batch_destroy(ls_batch_t batch);
 
 #ifdef __cplusplus

@@ -267,14 +267,19 @@ class Batch:
                                                            _stream(), ctypes.byref(t), ctypes.byref(ms)))
         return t.value, ms.value
 
-    def report(self):
-        """(per-system seconds, error flag) of the last completed run."""
+    def report(self, phases=False):
+        """(per-system seconds, error flag) of the last completed run; with
+        ``phases`` also the spans of the folding, vector and tile phases."""
         torch.cuda.synchronize()
         sec = np.zeros(self.count)
+        ph = np.zeros(3)
         err = ctypes.c_int32(0)
         check("ls_batch_report", lib().ls_batch_report(self._handle, _ptr(self.ws),
                                                        sec.ctypes.data_as(_lib.c_double_p),
+                                                       ph.ctypes.data_as(_lib.c_double_p),
                                                        ctypes.byref(err)))
+        if phases:
+            return sec, int(err.value), ph
         return sec, int(err.value)
 
     def close(self):

@@ -71,6 +71,7 @@ struct BatchArg {
   int* vec_done;
   unsigned long long* t_start;
   unsigned long long* t_end;
+  unsigned long long* t_phase;  // [3][2]: first start, last end per task type
   int ntasks;
   int nsys;
 };
@@ -263,10 +264,15 @@ __global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
     if (t >= ba.ntasks) return;
     const Task tk = ba.tasks[t];
     const SysDev& S = ba.sys[tk.sys];
-    if (threadIdx.x == 0) atomicMin(&ba.t_start[tk.sys], (unsigned long long)wall_clock64());
+    if (threadIdx.x == 0) {
+      const unsigned long long now = wall_clock64();
+      atomicMin(&ba.t_start[tk.sys], now);
+      atomicMin(&ba.t_phase[2 * tk.type], now);
+    }
     if (tk.type == TASK_FOLD) {
       fold_task(S, tk.a);
       signal_counter(&ba.fold_done[tk.sys]);
+      if (threadIdx.x == 0) atomicMax(&ba.t_phase[1], (unsigned long long)wall_clock64());
     } else if (tk.type == TASK_VEC) {
       if (!wait_counter(&ba.fold_done[tk.sys], 3, ba.err, &s_flag)) continue;
       vec_task(S, ba, tk.a, reinterpret_cast<double*>(smem));
@@ -278,6 +284,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
         energy_task(S, reinterpret_cast<double*>(smem));
         if (threadIdx.x == 0) atomicMax(&ba.t_end[tk.sys], (unsigned long long)wall_clock64());
       }
+      if (threadIdx.x == 0) atomicMax(&ba.t_phase[3], (unsigned long long)wall_clock64());
     } else {
       if (!wait_counter(&ba.vec_done[tk.sys], S.nvec, ba.err, &s_flag)) continue;
       BoxArg a;
@@ -297,7 +304,11 @@ __global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
       const int tm = tk.a / S.tiles_n, tn = tk.a - tm * S.tiles_n;
       recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
       __syncthreads();
-      if (threadIdx.x == 0) atomicMax(&ba.t_end[tk.sys], (unsigned long long)wall_clock64());
+      if (threadIdx.x == 0) {
+        const unsigned long long now = wall_clock64();
+        atomicMax(&ba.t_end[tk.sys], now);
+        atomicMax(&ba.t_phase[5], now);
+      }
     }
   }
 }
@@ -307,6 +318,10 @@ __global__ void k_batch_reset(BatchArg ba) {
   if (i == 0) {
     *ba.head = 0;
     *ba.err = 0;
+  }
+  if (i < 3) {
+    ba.t_phase[2 * i] = ~0ull;
+    ba.t_phase[2 * i + 1] = 0ull;
   }
   if (i < ba.nsys) {
     ba.fold_done[i] = 0;
@@ -416,6 +431,7 @@ static BatchArg make_arg(ls_batch* B, char* ws) {
   a.vec_done = (int*)(ws + B->off_vec);
   a.t_start = (unsigned long long*)(ws + B->off_ts);
   a.t_end = (unsigned long long*)(ws + B->off_te);
+  a.t_phase = (unsigned long long*)(ws + B->off_ctrl + 64);
   a.ntasks = B->ntasks;
   a.nsys = B->count;
   return a;
@@ -527,8 +543,8 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   B->count = count;
   B->sys.resize(count);
   size_t off = 0;
-  B->off_ctrl = off;
-  off += al(64);
+  B->off_ctrl = off;  // head, err at +0; phase stamps [6] u64 at +64
+  off += al(128);
   B->off_fold = off;
   off += al(sizeof(int) * count);
   B->off_vec = off;
@@ -684,7 +700,7 @@ extern "C" ls_status ls_batch_autotune(ls_batch_t B, void* ws_dev, size_t ws_byt
 }
 
 extern "C" ls_status ls_batch_report(ls_batch_t B, const void* ws_dev, double* seconds,
-                                     int32_t* error_flag) {
+                                     double* phase_seconds, int32_t* error_flag) {
   clear_error();
   LS_REQUIRE(B != nullptr && ws_dev != nullptr, "null pointer");
   const char* ws = (const char*)ws_dev;
@@ -694,6 +710,8 @@ extern "C" ls_status ls_batch_report(ls_batch_t B, const void* ws_dev, double* s
   if (e == hipSuccess)
     e = hipMemcpy(te.data(), ws + B->off_te, 8 * (size_t)B->count, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(ctrl, ws + B->off_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+  unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpy(ph, ws + B->off_ctrl + 64, sizeof(ph), hipMemcpyDeviceToHost);
   int dev = 0, khz = 0;
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
@@ -704,6 +722,11 @@ extern "C" ls_status ls_batch_report(ls_batch_t B, const void* ws_dev, double* s
   if (seconds)
     for (int i = 0; i < B->count; ++i)
       seconds[i] = (te[i] >= ts[i] && ts[i] != ~0ull) ? (double)(te[i] - ts[i]) / (khz * 1e3) : -1.0;
+  if (phase_seconds)
+    for (int k = 0; k < 3; ++k)
+      phase_seconds[k] = (ph[2 * k + 1] >= ph[2 * k] && ph[2 * k] != ~0ull)
+                             ? (double)(ph[2 * k + 1] - ph[2 * k]) / (khz * 1e3)
+                             : 0.0;
   if (error_flag) *error_flag = ctrl[1];
   return LS_OK;
 }
