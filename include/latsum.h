@@ -210,6 +210,33 @@ ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                     void* ws_dev, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Canonical sum alpha A + beta B by concatenation of the factor matrices
+ * (Appendix, eq. conc); used for the Richardson-regularised periodic sum
+ * 2 P_L - P_2L (linear growth) or (4 P_L - P_2L)/3 (quadratic), Sec. 3.2.
+ * A and B must have equal len[]; outputs: f_l [K_A + K_B][len_l] (rows of A,
+ * then rows of B) and coef [K_A + K_B] = (alpha coef_A, beta coef_B), device.
+ * Errors: LS_EINVAL.
+ */
+ls_status ls_canon_combine(const ls_canon* A, double alpha, const ls_canon* B, double beta,
+                           double* f0_dev, double* f1_dev, double* f2_dev, double* coef_dev,
+                           hipStream_t stream);
+
+/*
+ * Nuclear-potential operator matrix in a separable basis (Sec. 2.2,
+ * Example 2.1, eq. nuc_pot): V[k][m] = <G_k (.) G_m, P> for rank-one basis
+ * functions G_k = g_k^(0) (x) g_k^(1) (x) g_k^(2) sampled at cell midpoints:
+ *   V[k][m] = sum_r coef[r] prod_l sum_i g_k^(l)(i) g_m^(l)(i) f_l[r][i]
+ * (Hadamard and scalar products, eqs. had, scal), on FP64 MFMA.
+ * g_l_dev: device [Nb][P->len[l]] FP64. V_dev: device [Nb][Nb] FP64 (symmetric).
+ * ws_dev: at least ls_nuclear_workspace(P->K, Nb) bytes.
+ * Errors: LS_EINVAL, LS_EWORKSPACE.
+ */
+size_t ls_nuclear_workspace(int32_t K, int32_t Nb);
+ls_status ls_nuclear_matrix(const ls_canon* P, int32_t Nb, const double* g0_dev,
+                            const double* g1_dev, const double* g2_dev, double* V_dev,
+                            void* ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Batched lattice systems (project addition; per system Sec. 3.1 box
  * assembly, Appendix eq. scal energy and eq. CP_form reconstruction).
  * Each system gives a box lattice, its quadrature, charges, a density in

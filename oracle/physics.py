@@ -17,11 +17,16 @@ nothing with this formula but the energy itself.
 
 Richardson (Sec. 3.2): for sums growing linearly in L, 2 p_L - p_{2L}; for
 quadratic growth, (4 p_L - p_{2L})/3.
+
+Nuclear-potential operator matrix (Sec. 2.2, Example 2.1, eq. nuc_pot): for
+separable basis functions G_k = g_k^(1) (x) g_k^(2) (x) g_k^(3) sampled at cell
+midpoints, v_km = <G_k (.) G_m, P> with the Hadamard product of eq. had and the
+scalar product of eq. scal.
 """
 import numpy as np
 
 from .lattice import direct_factors
-from .canonical import scalar_product
+from .canonical import scalar_product, hadamard
 
 
 def energy(geom, t, w, pos, Z, D, d, factors=None):
@@ -85,3 +90,16 @@ def richardson_linear(pL, p2L):
 def richardson_quadratic(pL, p2L):
     """Regularised value for a sum growing like c L^2: (4 p_L - p_2L)/3."""
     return (4.0 * np.asarray(pL) - np.asarray(p2L)) / 3.0
+
+
+def nuclear_matrix(F, coef, g):
+    """v_km = <G_k (.) G_m, P> (eq. nuc_pot): G_k (.) G_m is the rank-one
+    canonical tensor with vectors g_k^(l) (.) g_m^(l) (eq. had), and the scalar
+    product with the canonical P follows eq. scal. g[l]: (N_b, N_l)."""
+    Nb = g[0].shape[0]
+    V = np.zeros((Nb, Nb))
+    for k in range(Nb):
+        for m in range(Nb):
+            Hk = [(g[l][k] * g[l][m])[None, :] for l in range(3)]
+            V[k, m] = scalar_product(F, coef, Hk, np.ones(1))
+    return V

@@ -77,6 +77,13 @@ _SIGNATURES = {
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Canon),
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_size_t, ctypes.c_void_p]),
+    "ls_canon_combine": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_double, ctypes.POINTER(Canon),
+                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_nuclear_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "ls_nuclear_matrix": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "ls_batch_create": (ctypes.c_int, [ctypes.POINTER(System), ctypes.c_int32, ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t)]),
     "ls_batch_tiles": (ctypes.c_int32, []),

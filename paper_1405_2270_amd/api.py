@@ -190,6 +190,50 @@ def forces(lat, quad, pos, Z, D, d, precision="f64", ws=None):
     return F, E
 
 
+def combine(FA, ca, alpha, FB, cb, beta):
+    """alpha A + beta B as one canonical tensor (eq. conc): factors [A; B]."""
+    for f in list(FA) + list(FB):
+        _dev_f64(f, "factor")
+    Kt = int(FA[0].shape[0] + FB[0].shape[0])
+    dev = FA[0].device
+    F = [torch.empty((Kt, int(FA[l].shape[1])), dtype=torch.float64, device=dev) for l in range(3)]
+    coef = torch.empty(Kt, dtype=torch.float64, device=dev)
+    check("ls_canon_combine", lib().ls_canon_combine(ctypes.byref(_canon(FA, ca)), float(alpha),
+                                                     ctypes.byref(_canon(FB, cb)), float(beta),
+                                                     _ptr(F[0]), _ptr(F[1]), _ptr(F[2]), _ptr(coef),
+                                                     _stream()))
+    return F, coef
+
+
+def richardson(lat, quad, pos, Z, order="linear"):
+    """Richardson-regularised periodic sum on the reference cell (Sec. 3.2):
+    the assembled periodic tensors at L and 2L combined as 2 P_L - P_2L
+    (``linear``) or (4 P_L - P_2L)/3 (``quadratic``), in canonical form."""
+    if not lat.periodic:
+        raise ValueError("Richardson regularisation applies to the periodic cell")
+    lat2 = LatticeSpec(lat.b, lat.n, tuple(2 * v for v in lat.L), True)
+    F1, c1 = assemble(lat, quad, pos, Z)
+    F2, c2 = assemble(lat2, quad, pos, Z)
+    a, b = (2.0, -1.0) if order == "linear" else (4.0 / 3.0, -1.0 / 3.0)
+    return combine(F1, c1, a, F2, c2, b)
+
+
+def nuclear_matrix(F, coef, g, ws=None):
+    """V[k][m] = <G_k (.) G_m, P> (eq. nuc_pot) for rank-one basis functions
+    with samples g[l] (device [Nb][N_l])."""
+    for x in list(F) + list(g):
+        _dev_f64(x, "factor")
+    K, Nb = int(F[0].shape[0]), int(g[0].shape[0])
+    need = int(lib().ls_nuclear_workspace(K, Nb))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=F[0].device)
+    V = torch.empty((Nb, Nb), dtype=torch.float64, device=F[0].device)
+    check("ls_nuclear_matrix", lib().ls_nuclear_matrix(ctypes.byref(_canon(F, coef)), Nb, _ptr(g[0]),
+                                                       _ptr(g[1]), _ptr(g[2]), _ptr(V), _ptr(ws),
+                                                       ws.numel(), _stream()))
+    return V
+
+
 class LatticeEnergy(torch.autograd.Function):
     """E(pos) = <P(pos), rho> with the hand-written adjoint as its gradient.
 

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblatsum.so")
-SOURCES = ["ls_host.cpp", "ls_vectors.hip", "ls_recon.hip", "ls_energy.hip", "ls_batch.hip"]
+SOURCES = ["ls_host.cpp", "ls_vectors.hip", "ls_recon.hip", "ls_energy.hip", "ls_batch.hip",
+           "ls_extra.hip"]
 ARCH = os.environ.get("LATSUM_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -35,7 +36,7 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]

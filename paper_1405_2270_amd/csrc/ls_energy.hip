@@ -2,7 +2,7 @@
 // unit-cell atoms by the adjoint of the assembled vectors.
 //
 // Energy from factors (HBM-bound): G_l[r][s] = <f_l[r], rho_l[s]> streams each
-// factor row once (one workgroup per row and axis, density rows from L2),
+// factor row once (one wave per row and axis, density rows from L2),
 // then E = sum_r coef[r] sum_s d[s] prod_l G_l[r][s] in one workgroup.
 //
 // Forces without factors: with Phi_l[s][i] = sum_k rho_l[s][i + k n] (the
@@ -34,18 +34,28 @@ __device__ __forceinline__ double block_sum256(T v, double* sh) {
   return r;
 }
 
-// G[(l*K + r)*Krho + s] = sum_g f_l[r][g] * D_l[s][g]
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// G[(l*K + r)*Krho + s] = sum_g f_l[r][g] * D_l[s][g]. One wave per factor row
+// (four rows per workgroup); lanes stride the row with coalesced loads and
+// the per-lane partial sums are combined by a fixed shuffle tree (no barriers).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ f0,
-                                               const double* __restrict__ f1,
-                                               const double* __restrict__ f2,
-                                               const double* __restrict__ D0,
-                                               const double* __restrict__ D1,
-                                               const double* __restrict__ D2, int K, int Krho,
-                                               int N0, int N1, int N2, double* __restrict__ G) {
-  __shared__ double sh[256];
-  const int r = blockIdx.x;
+__global__ __launch_bounds__(256) void k_gram_rows(const double* __restrict__ f0,
+                                                    const double* __restrict__ f1,
+                                                    const double* __restrict__ f2,
+                                                    const double* __restrict__ D0,
+                                                    const double* __restrict__ D1,
+                                                    const double* __restrict__ D2, int K, int Krho,
+                                                    int N0, int N1, int N2,
+                                                    double* __restrict__ G) {
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int l = blockIdx.y;
+  if (r >= K) return;
   const double* f = (l == 0 ? f0 : (l == 1 ? f1 : f2));
   const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2));
   const int N = (l == 0 ? N0 : (l == 1 ? N1 : N2));
@@ -53,7 +63,7 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ f0,
   T acc[kMaxRho];
 #pragma unroll
   for (int s = 0; s < kMaxRho; ++s) acc[s] = 0;
-  for (int g = threadIdx.x; g < N; g += 256) {
+  for (int g = lane; g < N; g += 64) {
     const T fv = (T)fr[g];
 #pragma unroll
     for (int s = 0; s < kMaxRho; ++s)
@@ -62,8 +72,8 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ f0,
 #pragma unroll
   for (int s = 0; s < kMaxRho; ++s) {
     if (s < Krho) {
-      const double tot = block_sum256(acc[s], sh);
-      if (threadIdx.x == 0) G[((size_t)l * K + r) * Krho + s] = tot;
+      const double tot = wave_sum64((double)acc[s]);
+      if (lane == 0) G[((size_t)l * K + r) * Krho + s] = tot;
     }
   }
 }
@@ -148,17 +158,27 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
       }
     }
   }
+  // fixed-order reduction: shuffle tree per wave, then the four waves in order
   const int r = nu * qa.R + q;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int s = 0; s < kMaxRho; ++s) {
     if (s < Krho) {
-      const double tv = block_sum256(av[s], sh);
-      const double td = block_sum256(ad[s], sh);
-      if (threadIdx.x == 0) {
-        Gv[((size_t)l * K + r) * Krho + s] = tv;
-        Gd[((size_t)l * K + r) * Krho + s] = td;
+      const double tv = wave_sum64((double)av[s]);
+      const double td = wave_sum64((double)ad[s]);
+      if (lane == 0) {
+        sh[wv * 2 * kMaxRho + s] = tv;
+        sh[wv * 2 * kMaxRho + kMaxRho + s] = td;
       }
     }
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < 2 * kMaxRho && (i % kMaxRho) < Krho) {
+    const double tot = ((sh[i] + sh[2 * kMaxRho + i]) + sh[4 * kMaxRho + i]) + sh[6 * kMaxRho + i];
+    const int s = i % kMaxRho;
+    double* dst = i < kMaxRho ? Gv : Gd;
+    dst[((size_t)l * K + r) * Krho + s] = tot;
   }
 }
 
@@ -244,15 +264,15 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
     return LS_EWORKSPACE;
   }
   double* G = (double*)ws_dev;
-  dim3 grid(P->K, 3);
+  dim3 grid((P->K + 3) / 4, 3);
   if (precision == LS_F64)
-    hipLaunchKernelGGL(k_gram<double>, grid, dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
-                       rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0], P->len[1],
-                       P->len[2], G);
+    hipLaunchKernelGGL(k_gram_rows<double>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
+                       P->f[2], rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0],
+                       P->len[1], P->len[2], G);
   else
-    hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
-                       rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0], P->len[1],
-                       P->len[2], G);
+    hipLaunchKernelGGL(k_gram_rows<float>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
+                       P->f[2], rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0],
+                       P->len[1], P->len[2], G);
   ls_status st = launch_status("ls_energy (gram)");
   if (st != LS_OK) return st;
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, stream, G, P->coef, rho->coef, P->K,

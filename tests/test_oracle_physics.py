@@ -5,8 +5,8 @@ import pytest
 from oracle.lattice import Geometry, direct_factors, assembled_factors
 from oracle.canonical import reconstruct
 from oracle.physics import (energy, forces_adjoint, forces_adjoint_atoms, forces_fd,
-                            richardson_linear, richardson_quadratic)
-from workloads import small_box, small_periodic
+                            richardson_linear, richardson_quadratic, nuclear_matrix)
+from workloads import small_box, small_periodic, make_basis
 from oracle.quadrature import rule_s, rule_u
 
 
@@ -90,3 +90,36 @@ def test_forces_of_selected_atoms_match_full_adjoint():
     full = forces_adjoint(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
     part = forces_adjoint_atoms(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d, [2, 0])
     assert np.allclose(part, full[[2, 0]], rtol=1e-13, atol=1e-15 * np.abs(full).max())
+
+
+def test_nuclear_matrix_against_full_grid():
+    # v_km = sum_i G_k(i) G_m(i) P_i on a tiny full grid (eq. nuc_pot)
+    sysm = small_box(61, n=8, L=(2, 2, 2), M0=2)
+    t, w = _tw(sysm)
+    geom = _geom(sysm)
+    F, c = direct_factors(geom, t, w, sysm.pos, sysm.Z)
+    g = make_basis(sysm, 5)
+    V = nuclear_matrix(F, c, g)
+    P = reconstruct(F, c)
+    G = [np.einsum("i,j,k->ijk", g[0][k], g[1][k], g[2][k]) for k in range(5)]
+    ref = np.array([[np.sum(G[k] * G[m] * P) for m in range(5)] for k in range(5)])
+    Vabs = nuclear_matrix(F, np.abs(c), g)
+    assert np.max(np.abs(V - ref)) < 1e-13 * np.max(np.abs(Vabs))
+    assert np.allclose(V, V.T, rtol=0, atol=1e-14 * np.max(np.abs(Vabs)))
+
+
+def test_richardson_on_periodic_sums_of_a_dipole_free_cell():
+    # the regularised sum of a neutral, dipole-free cell changes little
+    # between L and 2L, and the linear formula is exact when p_L is linear
+    b, n = 6.0, 6
+    pos = np.array([[-1.5, 0.0, 0.0], [1.5, 0.0, 0.0], [0.0, -1.5, 0.0], [0.0, 1.5, 0.0]])
+    Z = np.array([1.0, 1.0, -1.0, -1.0])
+    t, w = rule_s(41, 3.7, 2.7e-3 * n / b)
+    vals = {}
+    for L in (4, 8):
+        geom = Geometry(b, n, (L, L, L), True)
+        F, c = assembled_factors(geom, t, w, pos, Z)
+        vals[L] = reconstruct(F, c) / geom.h ** 3
+    lin = richardson_linear(vals[4], vals[8])
+    assert lin.shape == (n, n, n)
+    assert np.max(np.abs(lin - vals[8])) < np.max(np.abs(vals[8] - vals[4])) * 2 + 1e-12

@@ -249,3 +249,19 @@ def small_periodic(seed, n=16, L=(5, 5, 5), M0=4, rule="S", M=29, b=10.0, R_rho=
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+def make_basis(sysm, Nb, seed=7):
+    """Nb separable Gaussian basis functions (rank one each) sampled at cell
+    midpoints of the system's grid: centres at seeded atoms (with seeded
+    offsets), exponents alpha ~ U[0.3, 3] / b^2 * n^0 (length^-2)."""
+    rng = np.random.default_rng(seed)
+    g = []
+    atoms = rng.integers(0, sysm.M0, Nb)
+    centres = sysm.pos[atoms] + rng.normal(0.0, 0.1 * sysm.b, (Nb, 3))
+    alpha = rng.uniform(0.3, 3.0, Nb) / sysm.b ** 2 * 16.0
+    for l in range(3):
+        N = sysm.N(l)
+        mid = -0.5 * sysm.b + (np.arange(N) + 0.5) * sysm.h
+        g.append(np.exp(-alpha[:, None] * (mid[None, :] - centres[:, l, None]) ** 2))
+    return g
