@@ -26,10 +26,49 @@
 
 namespace ls {
 
+// All boxes of one call (up to kBoxesPerLaunch) share one launch, so the
+// last partial round of workgroups is paid once, not once per box. Workgroup
+// g runs on XCD g mod 8; the logical tile index is chosen so that each XCD
+// takes a contiguous range of tiles (the tiles of one or two boxes), which
+// keeps each box's factor slices in one XCD's L2.
+constexpr int kBoxesPerLaunch = 24;
+
+struct BoxSet {
+  BoxArg box[kBoxesPerLaunch];
+  long long tile_start[kBoxesPerLaunch + 1];  // prefix sums of tiles per box
+  long long out_off[kBoxesPerLaunch];         // element offset of each box in out
+  int tiles_n[kBoxesPerLaunch];               // column tiles per box
+  int nbox;
+  long long per_xcd;                          // tiles per XCD range
+};
+
+__device__ __forceinline__ bool locate(const BoxSet& bs, int* b, int* tm, int* tn) {
+  const long long g = blockIdx.x;
+  const long long t = (g & 7) * bs.per_xcd + (g >> 3);
+  if (t >= bs.tile_start[bs.nbox]) return false;
+  int i = 0;
+  while (i + 1 < bs.nbox && bs.tile_start[i + 1] <= t) ++i;
+  const long long local = t - bs.tile_start[i];
+  *b = i;
+  *tm = (int)(local / bs.tiles_n[i]);
+  *tn = (int)(local - (long long)(*tm) * bs.tiles_n[i]);
+  return true;
+}
+
 template <typename T, int BM, int BN, int WM, int WN, int BK>
-__global__ __launch_bounds__(256) void k_recon(BoxArg a, T* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_recon(BoxSet bs, T* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) char smem[recon_smem_bytes<T, BM, BN, BK>()];
-  recon_tile<T, BM, BN, WM, WN, BK>(a, blockIdx.x * BM, blockIdx.y * BN, out, smem);
+  int b, tm, tn;
+  if (!locate(bs, &b, &tm, &tn)) return;
+  recon_tile<T, BM, BN, WM, WN, BK>(bs.box[b], tm * BM, tn * BN, out + bs.out_off[b], smem);
+}
+
+template <int BM, int BN, int WM, int WN, int BK>
+__global__ __launch_bounds__(256) void k_recon32(BoxSet bs, float* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) char smem[recon32_smem_bytes<BM, BN, BK>()];
+  int b, tm, tn;
+  if (!locate(bs, &b, &tm, &tn)) return;
+  recon_tile32<BM, BN, WM, WN, BK>(bs.box[b], tm * BM, tn * BN, out + bs.out_off[b], smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -59,7 +98,11 @@ __device__ __forceinline__ void split_store(double v, unsigned short* dst, int p
 }
 
 template <int NT, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_recon_bf16(BoxSet bs, float* __restrict__ out_all) {
+  int bidx, tmi, tni;
+  if (!locate(bs, &bidx, &tmi, &tni)) return;
+  const BoxArg& a = bs.box[bidx];
+  float* __restrict__ out = out_all + bs.out_off[bidx];
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   constexpr int BK = 32;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -69,8 +112,8 @@ __global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict_
   __shared__ __attribute__((aligned(16))) unsigned short Ys[2][NT][BN][KP];
 
   const int M = a.e0 * a.e1;
-  const int row0 = blockIdx.x * BM;
-  const int col0 = blockIdx.y * BN;
+  const int row0 = tmi * BM;
+  const int col0 = tni * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -147,23 +190,30 @@ __global__ __launch_bounds__(256) void k_recon_bf16(BoxArg a, float* __restrict_
 // ---------------------------------------------------------------------------
 // tile table
 // ---------------------------------------------------------------------------
-struct TileInfo {
-  int bm, bn;
-};
+static void fill_tiles(BoxSet* bs, int bm, int bn) {
+  long long acc = 0;
+  for (int i = 0; i < bs->nbox; ++i) {
+    const BoxArg& a = bs->box[i];
+    const long long tm = ((long long)a.e0 * a.e1 + bm - 1) / bm;
+    bs->tiles_n[i] = (a.e2 + bn - 1) / bn;
+    bs->tile_start[i] = acc;
+    acc += tm * bs->tiles_n[i];
+  }
+  bs->tile_start[bs->nbox] = acc;
+  bs->per_xcd = (acc + 7) / 8;
+}
 
 template <typename T>
-static void launch_fp(int tile, dim3 block, hipStream_t s, const BoxArg& a, void* out, int* bm,
-                      int* bn, bool dry) {
-  const int M = a.e0 * a.e1;
+static bool launch_fp(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
+  dim3 block(256);
 #define LS_T(ID, BM_, BN_, WM_, WN_, BK_)                                                     \
   if (tile == ID) {                                                                          \
-    *bm = BM_;                                                                               \
-    *bn = BN_;                                                                               \
     if (!dry) {                                                                              \
-      dim3 grid((M + BM_ - 1) / BM_, (a.e2 + BN_ - 1) / BN_);                                \
-      hipLaunchKernelGGL((k_recon<T, BM_, BN_, WM_, WN_, BK_>), grid, block, 0, s, a, (T*)out); \
+      fill_tiles(&bs, BM_, BN_);                                                             \
+      dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
+      hipLaunchKernelGGL((k_recon<T, BM_, BN_, WM_, WN_, BK_>), grid, block, 0, s, bs, (T*)out); \
     }                                                                                        \
-    return;                                                                                  \
+    return true;                                                                             \
   }
   LS_T(1, 128, 128, 64, 64, 16)
   LS_T(2, 64, 64, 32, 32, 16)
@@ -171,49 +221,64 @@ static void launch_fp(int tile, dim3 block, hipStream_t s, const BoxArg& a, void
   LS_T(4, 64, 128, 32, 64, 16)
   LS_T(5, 128, 128, 64, 64, 32)
 #undef LS_T
-  *bm = 0;
+  if (sizeof(T) == 4) {
+#define LS_T32(ID, BM_, BN_, WM_, WN_, BK_)                                                   \
+  if (tile == ID) {                                                                          \
+    if (!dry) {                                                                              \
+      fill_tiles(&bs, BM_, BN_);                                                             \
+      dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
+      hipLaunchKernelGGL((k_recon32<BM_, BN_, WM_, WN_, BK_>), grid, block, 0, s, bs, (float*)out); \
+    }                                                                                        \
+    return true;                                                                             \
+  }
+    LS_T32(6, 128, 128, 64, 64, 16)
+    LS_T32(7, 128, 64, 64, 32, 16)
+    LS_T32(8, 128, 128, 64, 64, 32)
+#undef LS_T32
+  }
+  return false;
 }
 
 template <int NT>
-static void launch_bf(int tile, dim3 block, hipStream_t s, const BoxArg& a, void* out, int* bm,
-                      int* bn, bool dry) {
-  const int M = a.e0 * a.e1;
+static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
+  dim3 block(256);
 #define LS_T(ID, BM_, BN_, WM_, WN_)                                                          \
   if (tile == ID) {                                                                          \
-    *bm = BM_;                                                                               \
-    *bn = BN_;                                                                               \
     if (!dry) {                                                                              \
-      dim3 grid((M + BM_ - 1) / BM_, (a.e2 + BN_ - 1) / BN_);                                \
-      hipLaunchKernelGGL((k_recon_bf16<NT, BM_, BN_, WM_, WN_>), grid, block, 0, s, a, (float*)out); \
+      fill_tiles(&bs, BM_, BN_);                                                             \
+      dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
+      hipLaunchKernelGGL((k_recon_bf16<NT, BM_, BN_, WM_, WN_>), grid, block, 0, s, bs, (float*)out); \
     }                                                                                        \
-    return;                                                                                  \
+    return true;                                                                             \
   }
   LS_T(1, 128, 128, 64, 64)
   LS_T(2, 64, 64, 32, 32)
   LS_T(3, 128, 64, 64, 32)
   LS_T(4, 64, 128, 32, 64)
 #undef LS_T
-  *bm = 0;
+  return false;
 }
 
-static int n_tiles(int precision) { return precision == LS_F64 || precision == LS_F32 ? 5 : 4; }
+static int n_tiles(int precision) {
+  return precision == LS_F32 ? 8 : (precision == LS_F64 ? 5 : 4);
+}
 
-static void dispatch(int precision, int tile, hipStream_t s, const BoxArg& a, void* out, int* bm,
-                     int* bn, bool dry) {
-  dim3 block(256);
+static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
   switch (precision) {
-    case LS_F64: launch_fp<double>(tile, block, s, a, out, bm, bn, dry); break;
-    case LS_F32: launch_fp<float>(tile, block, s, a, out, bm, bn, dry); break;
-    case LS_BF16X3: launch_bf<2>(tile, block, s, a, out, bm, bn, dry); break;
-    case LS_BF16X6: launch_bf<3>(tile, block, s, a, out, bm, bn, dry); break;
-    default: *bm = 0;
+    case LS_F64: return launch_fp<double>(tile, s, bs, out, dry);
+    case LS_F32: return launch_fp<float>(tile, s, bs, out, dry);
+    case LS_BF16X3: return launch_bf<2>(tile, s, bs, out, dry);
+    case LS_BF16X6: return launch_bf<3>(tile, s, bs, out, dry);
+    default: return false;
   }
 }
 
-// Tile picked when the caller passes tile = 0: the largest tile that still
-// gives every compute unit at least two workgroups.
+// Tile picked when the caller passes tile = 0 (measured on 256^3 boxes,
+// K = 384: FP32 128x128 rank chunk 32, FP64 64x128).
 static int auto_tile(int precision, long long M, long long Nc) {
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
+  if (precision == LS_F32 && big >= 256) return 5;
+  if (precision == LS_F64 && big >= 256) return 4;
   if (big >= 512) return 1;
   const long long mid = ((M + 127) / 128) * ((Nc + 63) / 64);
   if (mid >= 512) return 3;
@@ -252,35 +317,44 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     }
     LS_REQUIRE((long long)boxes[b].e[0] * boxes[b].e[1] < (1LL << 31), "box %d too large", b);
   }
-  const size_t esz = precision == LS_F64 ? sizeof(double) : sizeof(float);
-  char* out = (char*)out_dev;
-  for (int b = 0; b < nbox; ++b) {
-    BoxArg a;
-    a.A1 = P->f[0];
-    a.A2 = P->f[1];
-    a.A3 = P->f[2];
-    a.coef = P->coef;
-    a.K = P->K;
-    a.len0 = P->len[0];
-    a.len1 = P->len[1];
-    a.len2 = P->len[2];
-    a.o0 = boxes[b].o[0];
-    a.o1 = boxes[b].o[1];
-    a.o2 = boxes[b].o[2];
-    a.e0 = boxes[b].e[0];
-    a.e1 = boxes[b].e[1];
-    a.e2 = boxes[b].e[2];
-    a.scale = scale;
-    const int t = tile ? tile : auto_tile(precision, (long long)a.e0 * a.e1, a.e2);
-    int bm = 0, bn = 0;
-    dispatch(precision, t, stream, a, out, &bm, &bn, false);
-    if (bm == 0) {
-      set_error("tile %d not available for precision %d", t, precision);
-      return LS_EUNSUPPORTED;
+  const int t = tile ? tile : auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1],
+                                        boxes[0].e[2]);
+  BoxSet probe;
+  if (!dispatch(precision, t, stream, probe, nullptr, true)) {
+    set_error("tile %d not available for precision %d", t, precision);
+    return LS_EUNSUPPORTED;
+  }
+  long long off = 0;  // elements
+  for (int b0 = 0; b0 < nbox; b0 += kBoxesPerLaunch) {
+    BoxSet bs;
+    bs.nbox = (nbox - b0) < kBoxesPerLaunch ? (nbox - b0) : kBoxesPerLaunch;
+    long long local = 0;
+    for (int i = 0; i < bs.nbox; ++i) {
+      const ls_box& bx = boxes[b0 + i];
+      BoxArg& a = bs.box[i];
+      a.A1 = P->f[0];
+      a.A2 = P->f[1];
+      a.A3 = P->f[2];
+      a.coef = P->coef;
+      a.K = P->K;
+      a.len0 = P->len[0];
+      a.len1 = P->len[1];
+      a.len2 = P->len[2];
+      a.o0 = bx.o[0];
+      a.o1 = bx.o[1];
+      a.o2 = bx.o[2];
+      a.e0 = bx.e[0];
+      a.e1 = bx.e[1];
+      a.e2 = bx.e[2];
+      a.scale = scale;
+      bs.out_off[i] = local;
+      local += (long long)bx.e[0] * bx.e[1] * bx.e[2];
     }
+    char* out = (char*)out_dev + off * (precision == LS_F64 ? 8 : 4);
+    dispatch(precision, t, stream, bs, out, false);
     ls_status st = launch_status("ls_reconstruct");
     if (st != LS_OK) return st;
-    out += esz * (size_t)a.e0 * a.e1 * a.e2;
+    off += local;
   }
   return LS_OK;
 }

@@ -125,7 +125,7 @@ struct Stager {
 // recon_smem_bytes<T, BM, BN, BK>() bytes.
 template <typename T, int BM, int BN, int BK>
 constexpr int recon_smem_bytes() {
-  return 2 * BK * (BM + BN + 2 * ((sizeof(T) == 8) ? 2 : 4)) * (int)sizeof(T);
+  return 2 * BK * (BM + BN + 2 * ((sizeof(T) == 8) ? 2 : 16)) * (int)sizeof(T);
 }
 
 template <typename T, int BM, int BN, int WM, int WN, int BK>
@@ -134,7 +134,9 @@ __device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, 
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   typedef typename Acc<T>::type acc_t;
   constexpr int FM = WM / 16, FN = WN / 16;
-  constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
+  // row padding: the four rank rows of one MFMA operand read (and of one
+  // staging store) then start 16 banks apart (FP32: stride = 16 mod 64 words)
+  constexpr int PAD = (sizeof(T) == 8) ? 2 : 16;
   typedef T WsRow[BK][BM + PAD];
   typedef T YsRow[BK][BN + PAD];
   WsRow* Ws = reinterpret_cast<WsRow*>(smem);
@@ -193,6 +195,88 @@ __device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, 
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wr + i * 16 + (f64_layout ? lk + 4 * v : 4 * lk + v);
         const int col = col0 + wc + j * 16 + lr;
+        if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
+      }
+}
+
+typedef float f16v_t __attribute__((ext_vector_type(16)));
+
+// FP32 tile on v_mfma_f32_32x32x2f32: each wave owns a WM x WN sub-tile of
+// 32x32 blocks; lane l supplies A[l%32][k = l/32] and B[k = l/32][l%32] and
+// receives D[8(v/4) + 4(l/32) + v%4][l%32], v = 0..15. Row stride of the LDS
+// operands is 32 mod 64 words, so the two rank rows of one operand read fall
+// on disjoint banks.
+template <int BM, int BN, int BK>
+constexpr int recon32_smem_bytes() {
+  return 2 * BK * (BM + BN + 2 * 32) * (int)sizeof(float);
+}
+
+template <int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0,
+                                             float* __restrict__ out, char* smem) {
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int PAD = 32;
+  typedef float WsRow[BK][BM + PAD];
+  typedef float YsRow[BK][BN + PAD];
+  WsRow* Ws = reinterpret_cast<WsRow*>(smem);
+  YsRow* Ys = reinterpret_cast<YsRow*>(smem + 2 * sizeof(WsRow));
+
+  const int M = a.e0 * a.e1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave / (BN / WN)) * WM;
+  const int wc = (wave % (BN / WN)) * WN;
+  const int lr = lane & 31;
+  const int lk = lane >> 5;
+
+  f16v_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+
+  Stager<BM, BN, BK> st;
+  st.init(a, row0, col0);
+  st.load(a, 0);
+  const int nchunk = (a.K + BK - 1) / BK;
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+#pragma unroll
+    for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
+      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (float)st.w[e];
+#pragma unroll
+    for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
+      Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (float)st.y[e];
+    __syncthreads();
+    if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      float av[FM], bv[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) av[i] = Ws[buf][kk + lk][wr + i * 32 + lr];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bv[j] = Ys[buf][kk + lk][wc + j * 32 + lr];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  const float sc = (float)a.scale;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = row0 + wr + i * 32 + 8 * (v >> 2) + 4 * lk + (v & 3);
+        const int col = col0 + wc + j * 32 + lr;
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
       }
 }
