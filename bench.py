@@ -57,8 +57,9 @@ def kernels_once():
     T = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
     a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
+    L.probe_copy(a, b)
     torch.cuda.synchronize()
+    del a, b
     s = config2()
     q = s.quad
     spec = L.LatticeSpec(s.b, s.n, s.L, False)
@@ -68,7 +69,7 @@ def kernels_once():
     F, coef = L.assemble(spec, qt, pos, Z, masters)
     E = L.energy(F, coef, [T(x) for x in s.density.D], T(s.density.d), "f64")
     box = [tuple(int(v) for v in s.boxes[0])]
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "bf16x6"):
         L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))

@@ -287,6 +287,25 @@ ls_status ls_batch_report(ls_batch_t batch, const void* ws_dev, double* seconds,
                           double* phase_seconds, int32_t* error_flag);
 void ls_batch_destroy(ls_batch_t batch);
 
+/* ------------------------------------------------------------------------
+ * Reference kernels for the rooflines (not part of the method).
+ * ------------------------------------------------------------------------ */
+/* Plain device copy of `bytes` bytes from src_dev to dst_dev (both device,
+ * 16-byte aligned, caller-owned; bytes a positive multiple of 16). Its
+ * duration gives the attainable HBM bandwidth; its hardware-counter readings
+ * (bytes fetched and written per dispatch) calibrate those of other kernels.
+ * Errors: LS_EINVAL for null or misaligned pointers or a bad size. */
+ls_status ls_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, hipStream_t stream);
+/* MFMA issue loop: `blocks` workgroups of four waves, each wave issuing
+ * iters x 8 independent MFMAs of the precision's instruction (F64:
+ * v_mfma_f64_16x16x4f64, F32: v_mfma_f32_16x16x4f32, BF16X3/BF16X6:
+ * v_mfma_f32_16x16x32_bf16) and writing one float per thread to
+ * out_dev[blocks * 256] (device, caller-owned). *flops (host) receives the
+ * floating-point operations of the launch. Timing is the caller's. Errors:
+ * LS_EINVAL for null pointers, an unknown precision or out-of-range counts. */
+ls_status ls_probe_mfma(int32_t precision, int32_t blocks, int32_t iters, float* out_dev,
+                        double* flops, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -94,6 +94,10 @@ _SIGNATURES = {
     "ls_batch_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p,
                                        c_int32_p]),
     "ls_batch_destroy": (None, [ctypes.c_void_p]),
+    "ls_probe_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]),
+    "ls_probe_mfma": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     c_double_p, ctypes.c_void_p]),
 }
 
 EXPORTS = tuple(_SIGNATURES)

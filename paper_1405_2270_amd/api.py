@@ -337,3 +337,22 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def probe_copy(src, dst):
+    """Plain device copy of src into dst (reference kernel for the HBM roofline)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    check("ls_probe_copy", lib().ls_probe_copy(_ptr(src), _ptr(dst), nbytes, _stream()))
+
+
+def probe_mfma(precision, blocks, iters, out):
+    """MFMA issue loop (reference kernel for the matrix-core roofline); returns
+    the floating-point operations of the launch. out: float32, blocks*256."""
+    if out.dtype != torch.float32 or out.numel() < blocks * 256:
+        raise ValueError("out must be float32 with blocks*256 elements")
+    flops = ctypes.c_double(0.0)
+    check("ls_probe_mfma", lib().ls_probe_mfma(_lib.PRECISIONS[precision], int(blocks), int(iters),
+                                               _ptr(out), ctypes.byref(flops), _stream()))
+    return flops.value

@@ -50,6 +50,10 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
 // so W[r][m] = alpha_r * f1[r][o1 + j0 + m - row0] with alpha_r = coef[r] f0[r][o0 + i]
 // (two scalar loads per rank row); otherwise every element does its own
 // index arithmetic.
+// load() only issues loads: the products are formed by w_value() when the
+// chunk is written to LDS one step later, so the loads of chunk c+1 stay in
+// flight while the MFMAs consume chunk c (a use right after the load would
+// make the wave wait for memory there).
 template <int BM, int BN, int BK>
 struct Stager {
   static constexpr int EPT_W = BK * BM / 256;
@@ -61,6 +65,7 @@ struct Stager {
   int wk, wq, yk, yq;
   int row0, col0, M, i0, j0;
   bool wfast, yfast;
+  double cr, a1;  // fast path: alpha = cr * a1 (1, 1 on the other paths)
   double w[EPT_W];
   double y[EPT_Y];
 
@@ -79,14 +84,19 @@ struct Stager {
     yfast = col0 + BN <= a.e2;
   }
 
+  __device__ __forceinline__ double w_value(int e) const { return (cr * a1) * w[e]; }
+
   __device__ __forceinline__ void load(const BoxArg& a, int k0) {
     const int r = k0 + wk;
+    cr = 1.0;
+    a1 = 1.0;
     if (r < a.K) {
       if (wfast) {
-        const double alpha = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i0];
+        cr = a.coef[r];
+        a1 = a.A1[(size_t)r * a.len0 + a.o0 + i0];
         const double* src = a.A2 + (size_t)r * a.len1 + a.o1 + j0 + wq;
 #pragma unroll
-        for (int e = 0; e < EPT_W; ++e) w[e] = alpha * src[e * TPR_W];
+        for (int e = 0; e < EPT_W; ++e) w[e] = src[e * TPR_W];
       } else {
 #pragma unroll
         for (int e = 0; e < EPT_W; ++e) {
@@ -165,7 +175,7 @@ __device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, 
     const int buf = c & 1;
 #pragma unroll
     for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
-      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (T)st.w[e];
+      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (T)st.w_value(e);
 #pragma unroll
     for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
       Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (T)st.y[e];
@@ -247,7 +257,7 @@ __device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0
     const int buf = c & 1;
 #pragma unroll
     for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
-      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (float)st.w[e];
+      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (float)st.w_value(e);
 #pragma unroll
     for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
       Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (float)st.y[e];
