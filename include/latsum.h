@@ -164,11 +164,21 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * C-order; element type double for LS_F64, float otherwise.
  * boxes: host [nbox]. tile: 0 = automatic, otherwise a tile id from
  * ls_reconstruct_tiles (used by the autotuner).
+ * ws_dev, ws_bytes: device workspace, caller-owned, used by the split-bf16
+ * precisions only: tiles 6..9 of LS_BF16X3 / LS_BF16X6 first split f1 into
+ * bf16 terms there (ls_reconstruct_workspace bytes); tile 0 uses them when the
+ * workspace is large enough and the boxes are large, and otherwise tiles that
+ * split both operands inside the kernel. NULL / 0 is valid for every other
+ * precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
- * LS_EUNSUPPORTED (tile id not valid for the precision).
+ * LS_EUNSUPPORTED (tile id not valid for the precision), LS_EWORKSPACE
+ * (tile 6..9 of a split precision with a missing or short workspace).
  */
 ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
-                         int32_t precision, int32_t tile, void* out_dev, hipStream_t stream);
+                         int32_t precision, int32_t tile, void* out_dev, void* ws_dev,
+                         size_t ws_bytes, hipStream_t stream);
+/* Workspace bytes of ls_reconstruct for a precision (0 unless split-bf16). */
+size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision);
 
 /* Number of reconstruction tile variants for a precision (for autotuning). */
 int32_t ls_reconstruct_tiles(int32_t precision);
@@ -297,14 +307,16 @@ void ls_batch_destroy(ls_batch_t batch);
  * Errors: LS_EINVAL for null or misaligned pointers or a bad size. */
 ls_status ls_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, hipStream_t stream);
 /* MFMA issue loop: `blocks` workgroups of four waves, each wave issuing
- * iters x 8 independent MFMAs of the precision's instruction (F64:
- * v_mfma_f64_16x16x4f64, F32: v_mfma_f32_16x16x4f32, BF16X3/BF16X6:
- * v_mfma_f32_16x16x32_bf16) and writing one float per thread to
- * out_dev[blocks * 256] (device, caller-owned). *flops (host) receives the
- * floating-point operations of the launch. Timing is the caller's. Errors:
- * LS_EINVAL for null pointers, an unknown precision or out-of-range counts. */
-ls_status ls_probe_mfma(int32_t precision, int32_t blocks, int32_t iters, float* out_dev,
-                        double* flops, hipStream_t stream);
+ * iters x 8 (16x16 shapes) or iters x 4 (32x32 shapes) independent MFMAs of
+ * the precision's instruction, shape 0: F64 v_mfma_f64_16x16x4f64, F32
+ * v_mfma_f32_16x16x4f32, BF16X3/BF16X6 v_mfma_f32_16x16x32_bf16; shape 1: F32
+ * v_mfma_f32_32x32x2f32, BF16X3/BF16X6 v_mfma_f32_32x32x16_bf16. Writes one
+ * float per thread to out_dev[blocks * 256] (device, caller-owned); *flops
+ * (host) receives the floating-point operations of the launch. Timing is the
+ * caller's. Errors: LS_EINVAL for null pointers, an unknown precision or
+ * shape, or out-of-range counts. */
+ls_status ls_probe_mfma(int32_t precision, int32_t shape, int32_t blocks, int32_t iters,
+                        float* out_dev, double* flops, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -66,7 +66,9 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "ls_reconstruct": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_void_p, ctypes.c_void_p]),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p]),
+    "ls_reconstruct_workspace": (ctypes.c_size_t, [ctypes.POINTER(Canon), ctypes.c_int32]),
     "ls_reconstruct_tiles": (ctypes.c_int32, [ctypes.c_int32]),
     "ls_energy_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "ls_energy": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Canon), ctypes.c_int32,
@@ -96,8 +98,8 @@ _SIGNATURES = {
     "ls_batch_destroy": (None, [ctypes.c_void_p]),
     "ls_probe_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]),
-    "ls_probe_mfma": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
-                                     c_double_p, ctypes.c_void_p]),
+    "ls_probe_mfma": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p, c_double_p, ctypes.c_void_p]),
 }
 
 EXPORTS = tuple(_SIGNATURES)

@@ -118,10 +118,20 @@ def _canon(F, coef):
                  (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F]), coef.data_ptr())
 
 
-def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0):
+def _recon_ws(canon, prec, device, ws):
+    need = int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec))
+    if need == 0:
+        return None, 0
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws, ws.numel()
+
+
+def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
     """Sub-boxes of the canonical tensor. ``boxes``: iterable of
     (o0, o1, o2, e0, e1, e2). Returns one tensor [e0][e1][e2] per box
-    (views of a single allocation)."""
+    (views of a single allocation). ``ws``: optional uint8 device workspace
+    (split-bf16 precisions; allocated here when missing or short)."""
     for f in F:
         _dev_f64(f, "factor")
     _dev_f64(coef, "coef")
@@ -130,11 +140,7 @@ def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0):
     dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
     sizes = [b[3] * b[4] * b[5] for b in boxes]
     flat = torch.empty(sum(sizes), dtype=dtype, device=F[0].device)
-    cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
-                              for b in boxes])
-    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(_canon(F, coef)), cb, len(boxes),
-                                                 float(scale), prec, int(tile), _ptr(flat),
-                                                 _stream()))
+    reconstruct_into(F, coef, boxes, flat, scale, precision, tile, ws)
     out, off = [], 0
     for b, s in zip(boxes, sizes):
         out.append(flat[off:off + s].view(b[3], b[4], b[5]))
@@ -142,15 +148,17 @@ def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0):
     return out
 
 
-def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0):
+def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws=None):
     """As ``reconstruct`` but into a caller-provided flat tensor."""
     boxes = [tuple(int(v) for v in b) for b in boxes]
     prec = _lib.PRECISIONS[precision]
+    canon = _canon(F, coef)
+    ws, nws = _recon_ws(canon, prec, F[0].device, ws)
     cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
                               for b in boxes])
-    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(_canon(F, coef)), cb, len(boxes),
+    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(canon), cb, len(boxes),
                                                  float(scale), prec, int(tile), _ptr(out),
-                                                 _stream()))
+                                                 _ptr(ws), nws, _stream()))
     return out
 
 
@@ -347,12 +355,14 @@ def probe_copy(src, dst):
     check("ls_probe_copy", lib().ls_probe_copy(_ptr(src), _ptr(dst), nbytes, _stream()))
 
 
-def probe_mfma(precision, blocks, iters, out):
+def probe_mfma(precision, blocks, iters, out, shape=0):
     """MFMA issue loop (reference kernel for the matrix-core roofline); returns
-    the floating-point operations of the launch. out: float32, blocks*256."""
+    the floating-point operations of the launch. out: float32, blocks*256.
+    shape 0: 16x16 instructions, 1: 32x32."""
     if out.dtype != torch.float32 or out.numel() < blocks * 256:
         raise ValueError("out must be float32 with blocks*256 elements")
     flops = ctypes.c_double(0.0)
-    check("ls_probe_mfma", lib().ls_probe_mfma(_lib.PRECISIONS[precision], int(blocks), int(iters),
-                                               _ptr(out), ctypes.byref(flops), _stream()))
+    check("ls_probe_mfma", lib().ls_probe_mfma(_lib.PRECISIONS[precision], int(shape), int(blocks),
+                                               int(iters), _ptr(out), ctypes.byref(flops),
+                                               _stream()))
     return flops.value

@@ -7,19 +7,64 @@
 
 namespace ls {
 
+// Each workgroup copies one contiguous block of 1024 16-byte elements: four
+// independent loads per thread, all issued before the stores.
 __global__ __launch_bounds__(256) void k_probe_copy(const uint4* __restrict__ src,
                                                      uint4* __restrict__ dst, size_t n) {
-  const size_t stride = (size_t)gridDim.x * 256;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+  const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+  uint4 v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (base + 256 * e < n) v[e] = src[base + 256 * e];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (base + 256 * e < n) dst[base + 256 * e] = v[e];
 }
 
-// Each wave keeps 8 independent accumulators so that the issue of one MFMA
-// never waits for the result of the previous one.
-template <int P>
+// Each wave keeps 8 (16x16 shapes) or 4 (32x32 shapes) independent
+// accumulators so that the issue of one MFMA never waits for the result of
+// the previous one.
+typedef float f16v_probe_t __attribute__((ext_vector_type(16)));
+
+template <int P, int SHAPE>
 __global__ __launch_bounds__(256) void k_probe_mfma(int iters, float* __restrict__ out) {
   const int lane = threadIdx.x & 63;
   float r = 0.0f;
-  if constexpr (P == LS_F64) {
+  if constexpr (SHAPE == 1 && P == LS_F32) {
+    const float x = 1.0f + 1e-3f * lane, z = 0.5f - 1e-4f * lane;
+    f16v_probe_t acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, z, acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) r += acc[u][v];
+  } else if constexpr (SHAPE == 1) {
+    s8_t xs, zs;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      xs[e] = (short)(0x3f80 + ((lane + e) & 7));
+      zs[e] = (short)(0x3f00 + ((lane * 3 + e) & 7));
+    }
+    const bf8_t x = __builtin_bit_cast(bf8_t, xs), z = __builtin_bit_cast(bf8_t, zs);
+    f16v_probe_t acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, z, acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) r += acc[u][v];
+  } else if constexpr (P == LS_F64) {
     const double x = 1.0 + 1e-3 * lane, z = 0.5 - 1e-4 * lane;
     d4_t acc[8];
 #pragma unroll
@@ -70,39 +115,51 @@ extern "C" ls_status ls_probe_copy(const void* src_dev, void* dst_dev, size_t by
   LS_REQUIRE(bytes % 16 == 0 && bytes > 0, "bytes must be a positive multiple of 16");
   LS_REQUIRE(((uintptr_t)src_dev | (uintptr_t)dst_dev) % 16 == 0, "pointers must be 16-byte aligned");
   const size_t n = bytes / 16;
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
+  const size_t blocks = (n + 1023) / 1024;
+  LS_REQUIRE(blocks <= 0x7fffffff, "copy too large");
   hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)blocks), dim3(256), 0, stream,
                      (const uint4*)src_dev, (uint4*)dst_dev, n);
   return launch_status("ls_probe_copy");
 }
 
-extern "C" ls_status ls_probe_mfma(int32_t precision, int32_t blocks, int32_t iters,
+extern "C" ls_status ls_probe_mfma(int32_t precision, int32_t shape, int32_t blocks, int32_t iters,
                                    float* out_dev, double* flops, hipStream_t stream) {
   clear_error();
   LS_REQUIRE(out_dev != nullptr && flops != nullptr, "null pointer");
   LS_REQUIRE(blocks >= 1 && blocks <= (1 << 20), "blocks must be in [1, 2^20]");
   LS_REQUIRE(iters >= 1 && iters <= (1 << 24), "iters must be in [1, 2^24]");
-  double per = 0.0;
+  LS_REQUIRE(shape == 0 || shape == 1, "shape must be 0 (16x16) or 1 (32x32)");
+  LS_REQUIRE(!(shape == 1 && precision == LS_F64), "no 32x32 FP64 instruction");
+  double per = 0.0;  // flops per wave per loop iteration
+  const dim3 g(blocks), b(256);
   switch (precision) {
     case LS_F64:
-      hipLaunchKernelGGL(k_probe_mfma<LS_F64>, dim3(blocks), dim3(256), 0, stream, iters, out_dev);
-      per = 2.0 * 16 * 16 * 4;
+      hipLaunchKernelGGL((k_probe_mfma<LS_F64, 0>), g, b, 0, stream, iters, out_dev);
+      per = 8 * 2.0 * 16 * 16 * 4;
       break;
     case LS_F32:
-      hipLaunchKernelGGL(k_probe_mfma<LS_F32>, dim3(blocks), dim3(256), 0, stream, iters, out_dev);
-      per = 2.0 * 16 * 16 * 4;
+      if (shape == 0) {
+        hipLaunchKernelGGL((k_probe_mfma<LS_F32, 0>), g, b, 0, stream, iters, out_dev);
+        per = 8 * 2.0 * 16 * 16 * 4;
+      } else {
+        hipLaunchKernelGGL((k_probe_mfma<LS_F32, 1>), g, b, 0, stream, iters, out_dev);
+        per = 4 * 2.0 * 32 * 32 * 2;
+      }
       break;
     case LS_BF16X3:
     case LS_BF16X6:
-      hipLaunchKernelGGL(k_probe_mfma<LS_BF16X3>, dim3(blocks), dim3(256), 0, stream, iters,
-                         out_dev);
-      per = 2.0 * 16 * 16 * 32;
+      if (shape == 0) {
+        hipLaunchKernelGGL((k_probe_mfma<LS_BF16X3, 0>), g, b, 0, stream, iters, out_dev);
+        per = 8 * 2.0 * 16 * 16 * 32;
+      } else {
+        hipLaunchKernelGGL((k_probe_mfma<LS_BF16X3, 1>), g, b, 0, stream, iters, out_dev);
+        per = 4 * 2.0 * 32 * 32 * 16;
+      }
       break;
     default:
       set_error("unknown precision %d", precision);
       return LS_EINVAL;
   }
-  *flops = per * 8.0 * iters * 4.0 * blocks;
+  *flops = per * iters * 4.0 * blocks;
   return launch_status("ls_probe_mfma");
 }

@@ -40,6 +40,8 @@ struct BoxSet {
   int tiles_n[kBoxesPerLaunch];               // column tiles per box
   int nbox;
   long long per_xcd;                          // tiles per XCD range
+  const unsigned* P2;                         // pre-split f1 (tiles 6..9 of the split precisions)
+  int nch;                                    // rank chunks of 32 in P2
 };
 
 __device__ __forceinline__ bool locate(const BoxSet& bs, int* b, int* tm, int* tn) {
@@ -80,15 +82,13 @@ __global__ __launch_bounds__(256) void k_recon32(BoxSet bs, float* __restrict__ 
 // significands hold the whole 24-bit FP32 significand, so x0 + x1 + x2 = x.
 // With NT = 2 the last term is rounded to nearest (|x - x0 - x1| <= 2^-16 |x|).
 // Products: x0y0 + x0y1 + x1y0, and for NT = 3 also x1y1 + x0y2 + x2y0, on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, smallest terms first.
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, small terms first.
 //
 // Staging map: thread t owns operand row m = t % BM and the KW = BM/8
 // consecutive ranks from (t / BM) * KW of each 32-rank chunk, so its terms go
 // to LDS as packed 16-byte writes (8 ranks: what one MFMA lane reads). One LDS
-// row holds the 32 ranks of one operand row (64 bytes); 16-byte slot s of row
-// m sits at slot s ^ ((m >> 2) & 3), which keeps the packed writes of
-// consecutive rows and the MFMA reads (16 rows, one slot) free of bank
-// conflicts.
+// row holds the 32 ranks of one operand row (64 bytes), with its 16-byte
+// slots permuted by lds_swz.
 //
 // The rank factor alpha_r = coef[r] f0[r][o0 + i] of a tile whose rows share
 // one i (else coef[r], with f0 multiplied into each element) is kept in LDS:
@@ -111,17 +111,102 @@ __device__ __forceinline__ void split_fp32(float x, unsigned (&u)[NT]) {
   u[NT - 1] = b;  // low half dropped when packed
 }
 
+// LDS placement of the split operands: 16-byte slot s of row R sits at slot
+// s ^ lds_swz(R). With 64-byte rows this keeps the 16-byte accesses of 16
+// consecutive rows (one slot each) free of bank conflicts whether the LDS
+// serves 8 or 16 lanes per cycle (32 or 64 banks).
+__device__ __forceinline__ int lds_swz(int row) {
+  const int r = row & 15;
+  return ((r >> 1) ^ (r >> 3)) & 3;
+}
+
 __device__ __forceinline__ unsigned pack_hi(unsigned even, unsigned odd) {
   return (odd & 0xffff0000u) | (even >> 16);
 }
 
-template <int NT, int BM, int BN, int WM, int WN, int NBUF>
+// MFMA shape of the split kernels. 16: v_mfma_f32_16x16x32_bf16, lane l
+// supplies row l%16 and ranks 8(l/16)..+7 of the 32-rank chunk, receives
+// D[4(l/16) + v][l%16], v < 4. 32: v_mfma_f32_32x32x16_bf16 on each half of
+// the chunk, lane l supplies row l%32 and ranks 16h + 8(l/32)..+7, receives
+// D[8(v/4) + 4(l/32) + v%4][l%32], v < 16. On gfx950 the 32x32 shape issues
+// at twice the rate of the 16x16 one.
+template <int MF>
+struct SplitMma;
+template <>
+struct SplitMma<16> {
+  typedef f4_t acc_t;
+  static constexpr int NV = 4;
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static __device__ __forceinline__ int dcol(int lane) { return lane & 15; }
+};
+template <>
+struct SplitMma<32> {
+  typedef f16v_t acc_t;
+  static constexpr int NV = 16;
+  static __device__ __forceinline__ int drow(int lane, int v) {
+    return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+  }
+  static __device__ __forceinline__ int dcol(int lane) { return lane & 31; }
+};
+
+// The MFMAs of one 32-rank chunk: term planes W + t*wplane and Y + t*yplane
+// (rows of 16 dwords, 16-byte slot s of row R at s ^ lds_swz(R)), A rows
+// from arow, B rows from brow. Products x_ta y_tb with ta + tb <= NT - 1; the
+// B fragments of all terms stay in registers, the A fragments are read one
+// term at a time.
+template <int NT, int MF, int FM, int FN>
+__device__ __forceinline__ void split_products(typename SplitMma<MF>::acc_t (&acc)[FM][FN],
+                                               const unsigned* W, int wplane, const unsigned* Y,
+                                               int yplane, int arow, int brow, int lane) {
+  constexpr int NH = MF == 16 ? 1 : 2;  // MFMA k-steps per chunk
+  const int lr = lane & (MF - 1), lg = lane / MF;
+  int slot[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) slot[h] = ((NH * h + lg) ^ lds_swz(lr)) * 4;
+  s8_t bv[NT][FN][NH];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+        bv[t][j][h] = *reinterpret_cast<const s8_t*>(Y + t * yplane + (brow + MF * j + lr) * 16 + slot[h]);
+#pragma unroll
+  for (int ta = NT - 1; ta >= 0; --ta) {
+    s8_t av[FM][NH];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+        av[i][h] = *reinterpret_cast<const s8_t*>(W + ta * wplane + (arow + MF * i + lr) * 16 + slot[h]);
+#pragma unroll
+    for (int tb = NT - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            if constexpr (MF == 16)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf8_t, av[i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                  acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf8_t, av[i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                  acc[i][j], 0, 0, 0);
+          }
+  }
+}
+
+template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
 __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restrict__ out_all) {
   constexpr int BK = SPLIT_BK;
   constexpr int KW = BK * BM / 256, KY = BK * BN / 256;
   static_assert(BM >= 64 && BN >= 64 && 256 % BM == 0 && 256 % BN == 0, "staging map");
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
-  constexpr int FM = WM / 16, FN = WN / 16;
+  constexpr int FM = WM / MF, FN = WN / MF;
+  typedef SplitMma<MF> Mma;
   __shared__ __attribute__((aligned(16))) unsigned Ws[NBUF][NT][BM][16];
   __shared__ __attribute__((aligned(16))) unsigned Ys[NBUF][NT][BN][16];
   __shared__ double alphaS[2][BK];
@@ -134,7 +219,6 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
   const int row0 = tmi * BM, col0 = tni * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave / (BN / WN)) * WM, wc = (wave % (BN / WN)) * WN;
-  const int lr = lane & 15, lk = lane >> 4;
 
   // staging ownership (tid / BM and tid / BN are uniform per wave: BM, BN >= 64)
   const int mw = tid % BM, ny = tid % BN;
@@ -197,7 +281,7 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
-      const int slot = ((kbw >> 3) + g) ^ ((mw >> 2) & 3);
+      const int slot = ((kbw >> 3) + g) ^ lds_swz(mw);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         *reinterpret_cast<uint4*>(&Ws[sb][t][mw][slot * 4]) =
@@ -215,7 +299,7 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
-      const int slot = ((kby >> 3) + g) ^ ((ny >> 2) & 3);
+      const int slot = ((kby >> 3) + g) ^ lds_swz(ny);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
         *reinterpret_cast<uint4*>(&Ys[sb][t][ny][slot * 4]) =
@@ -223,14 +307,14 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
     }
   };
 
-  f4_t acc[FM][FN];
+  typename Mma::acc_t acc[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
 
-  // read slot of this lane: rows wr + 16 i + lr all have (row >> 2) & 3 = (lr >> 2) & 3
-  const int rslot = (lk ^ ((lr >> 2) & 3)) * 4;
 
   load_alpha(0);
   put_alpha(0);
@@ -245,28 +329,8 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
     __syncthreads();
     if (c + 1 < nchunk) load_ops((c + 1) * BK);
     load_alpha((c + 2) * BK);
-    s8_t av[NT][FM], bv[NT][FN];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-        av[t][i] = *reinterpret_cast<const s8_t*>(&Ws[sb][t][wr + i * 16 + lr][rslot]);
-#pragma unroll
-      for (int j = 0; j < FN; ++j)
-        bv[t][j] = *reinterpret_cast<const s8_t*>(&Ys[sb][t][wc + j * 16 + lr][rslot]);
-    }
-    constexpr int NP = (NT == 3) ? 6 : 3;
-    constexpr int PA[6] = {1, 2, 0, 1, 0, 0};  // NT = 3 order; NT = 2 uses the last three
-    constexpr int PB[6] = {1, 0, 2, 0, 1, 0};
-#pragma unroll
-    for (int p = 6 - NP; p < 6; ++p)
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf8_t, av[PA[p]][i]), __builtin_bit_cast(bf8_t, bv[PB[p]][j]),
-              acc[i][j], 0, 0, 0);
+    split_products<NT, MF, FM, FN>(acc, &Ws[sb][0][0][0], BM * 16, &Ys[sb][0][0][0], BN * 16, wr,
+                                   wc, lane);
   }
 
   const float sc = (float)a.scale;
@@ -275,21 +339,367 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
 #pragma unroll
     for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = row0 + wr + i * 16 + 4 * lk + v;
-        const int col = col0 + wc + j * 16 + lr;
+      for (int v = 0; v < Mma::NV; ++v) {
+        const int row = row0 + wr + i * MF + Mma::drow(lane, v);
+        const int col = col0 + wc + j * MF + Mma::dcol(lane);
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// split-bf16 with pre-split f1 (tiles 6..9, workspace)
+// ---------------------------------------------------------------------------
+// Per i the box is the GEMM out[i][j][k] = sum_r f1[r][o1+j] Y_i[r][k] with
+// Y_i[r][k] = alpha_r(i) f2[r][o2+k], alpha_r(i) = coef[r] f0[r][o0+i]. The
+// left operand does not depend on i, so f1 is split into bf16 terms once per
+// call, into the workspace as P[t][c][x][32]: term t of f1[32c + q][x],
+// q = 0..31 (zero beyond K), one 64-byte row per grid cell x and rank chunk c.
+// A tile (one i, BM values of j, BN values of k) then copies its left operand
+// rows into LDS as they are (16-byte loads and stores, no arithmetic) and
+// splits only the BN x 32 values of Y_i per rank chunk.
+template <int NT>
+__global__ __launch_bounds__(256) void k_presplit(const double* __restrict__ f, int K, int len,
+                                                   int nch, unsigned* __restrict__ P) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (x >= len) return;
+  unsigned pk[NT][16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r0 = 32 * c + 2 * q;
+    unsigned u0[NT], u1[NT];
+    split_fp32<NT>(r0 < K ? (float)f[(size_t)r0 * len + x] : 0.0f, u0);
+    split_fp32<NT>(r0 + 1 < K ? (float)f[(size_t)(r0 + 1) * len + x] : 0.0f, u1);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    uint4* dst = reinterpret_cast<uint4*>(P + (((size_t)t * nch + c) * len + x) * 16);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      dst[s] = make_uint4(pk[t][4 * s], pk[t][4 * s + 1], pk[t][4 * s + 2], pk[t][4 * s + 3]);
+  }
+}
+
+template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
+__global__ __launch_bounds__(256, 2) void k_recon_presplit(BoxSet bs, float* __restrict__ out_all) {
+  constexpr int BK = SPLIT_BK;
+  constexpr int KY = BK * BN / 256;
+  constexpr int PW = NT * BM * 4 / 256;  // 16-byte pieces of the left operand per thread
+  static_assert(BN >= 64 && 256 % BN == 0 && (NT * BM * 4) % 256 == 0, "staging map");
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  constexpr int FM = WM / MF, FN = WN / MF;
+  typedef SplitMma<MF> Mma;
+  __shared__ __attribute__((aligned(16))) unsigned Ws[NBUF][NT][BM][16];
+  __shared__ __attribute__((aligned(16))) unsigned Ys[NBUF][NT][BN][16];
+  __shared__ double alphaS[2][BK];
+
+  int bidx, tmi, tni;
+  if (!locate(bs, &bidx, &tmi, &tni)) return;
+  const BoxArg& a = bs.box[bidx];
+  float* __restrict__ out = out_all + bs.out_off[bidx];
+  const int jtn = (a.e1 + BM - 1) / BM;
+  const int ib = tmi / jtn;
+  const int j0 = (tmi - ib * jtn) * BM;
+  const int col0 = tni * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave / (BN / WN)) * WM, wc = (wave % (BN / WN)) * WN;
+  const int nch = bs.nch;
+  const unsigned* __restrict__ P = bs.P2;
+
+  const int ny = tid % BN;
+  const int kby = __builtin_amdgcn_readfirstlane(tid / BN) * KY;
+  const bool nok = col0 + ny < a.e2;
+  const double* __restrict__ a3row = a.A3 + a.o2 + col0 + ny;
+  const double* __restrict__ a1col = a.A1 + a.o0 + ib;
+  const int nchunk = (a.K + BK - 1) / BK;
+
+  uint4 wv[PW];
+  double y[KY];
+  double cr = 0.0, ca = 1.0;
+
+  auto load_ops = [&](int c) {
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int id = tid + 256 * e;
+      const int slot = id & 3, row = (id >> 2) % BM, t = (id >> 2) / BM;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (j0 + row < a.e1)
+        v = *reinterpret_cast<const uint4*>(
+            P + (((size_t)t * nch + c) * a.len1 + a.o1 + j0 + row) * 16 + slot * 4);
+      wv[e] = v;
+    }
+#pragma unroll
+    for (int kk = 0; kk < KY; ++kk) {
+      const int r = c * BK + kby + kk;
+      y[kk] = (r < a.K && nok) ? a3row[(size_t)r * a.len2] : 0.0;
+    }
+  };
+  auto load_alpha = [&](int k0) {
+    const int r = k0 + tid;
+    cr = 0.0;
+    ca = 1.0;
+    if (tid < BK && r < a.K) {
+      cr = a.coef[r];
+      ca = a1col[(size_t)r * a.len0];
+    }
+  };
+  auto put_alpha = [&](int ab) {
+    if (tid < BK) alphaS[ab][tid] = cr * ca;
+  };
+  auto store = [&](int sb, int ab) {
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int id = tid + 256 * e;
+      const int slot = id & 3, row = (id >> 2) % BM, t = (id >> 2) / BM;
+      *reinterpret_cast<uint4*>(&Ws[sb][t][row][(slot ^ lds_swz(row)) * 4]) = wv[e];
+    }
+#pragma unroll
+    for (int g = 0; g < KY / 8; ++g) {
+      unsigned pk[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = g * 8 + 2 * q;
+        unsigned u0[NT], u1[NT];
+        split_fp32<NT>((float)(alphaS[ab][kby + kk] * y[kk]), u0);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * y[kk + 1]), u1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+      }
+      const int slot = ((kby >> 3) + g) ^ lds_swz(ny);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        *reinterpret_cast<uint4*>(&Ys[sb][t][ny][slot * 4]) =
+            make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+    }
+  };
+
+  typename Mma::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
+
+  load_alpha(0);
+  put_alpha(0);
+  load_alpha(BK);
+  load_ops(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int sb = (NBUF == 2) ? (c & 1) : 0;
+    if (NBUF == 1 && c > 0) __syncthreads();
+    store(sb, c & 1);
+    put_alpha((c + 1) & 1);
+    __syncthreads();
+    if (c + 1 < nchunk) load_ops(c + 1);
+    load_alpha((c + 2) * BK);
+    split_products<NT, MF, FM, FN>(acc, &Ws[sb][0][0][0], BM * 16, &Ys[sb][0][0][0], BN * 16, wr,
+                                   wc, lane);
+  }
+
+  const float sc = (float)a.scale;
+  const size_t base = (size_t)ib * a.e1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) {
+        const int jj = j0 + wr + i * MF + Mma::drow(lane, v);
+        const int col = col0 + wc + j * MF + Mma::dcol(lane);
+        if (jj < a.e1 && col < a.e2) out[(base + jj) * a.e2 + col] = sc * acc[i][j][v];
+      }
+}
+
+// Pre-split f1, BM = 256 rows of j per tile with the four waves stacked along
+// j (each wave 64 x BN): no two waves share a left-operand row, so each wave
+// loads its bf16 fragments straight from the pre-split planes into registers
+// (16-byte loads of consecutive 64-byte rows) and only the shared Y_i operand
+// goes through LDS. The fragments of term t for the next chunk are loaded as
+// soon as the MFMAs of this chunk are done with term t.
+template <int NT, int BN, int MF>
+__global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __restrict__ out_all) {
+  constexpr int BM = 256, WM = 64, WN = BN;
+  constexpr int BK = SPLIT_BK;
+  constexpr int KY = BK * BN / 256;
+  constexpr int FM = WM / MF, FN = WN / MF, NH = MF == 16 ? 1 : 2;
+  static_assert(BN == 64, "four waves stacked along j, one column block of 64");
+  typedef SplitMma<MF> Mma;
+  // Y_i in LDS in fragment order: the 16-byte piece that lane l supplies for
+  // term t, column block j and MFMA k-step h sits at ((t*FN + j)*NH + h)*64 + l,
+  // so each fragment read is one contiguous 1 KB
+  __shared__ uint4 Ysf[NT * FN * NH * 64];
+  __shared__ double alphaS[2][BK];
+
+  int bidx, tmi, tni;
+  if (!locate(bs, &bidx, &tmi, &tni)) return;
+  const BoxArg& a = bs.box[bidx];
+  float* __restrict__ out = out_all + bs.out_off[bidx];
+  const int jtn = (a.e1 + BM - 1) / BM;
+  const int ib = tmi / jtn;
+  const int j0 = (tmi - ib * jtn) * BM;
+  const int col0 = tni * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave * WM;
+  const int lr = lane & (MF - 1), lg = lane / MF;
+  const int nch = bs.nch;
+  const unsigned* __restrict__ P = bs.P2;
+
+  const int ny = tid % BN;
+  const int kby = __builtin_amdgcn_readfirstlane(tid / BN) * KY;
+  const bool nok = col0 + ny < a.e2;
+  const double* __restrict__ a3row = a.A3 + a.o2 + col0 + ny;
+  const double* __restrict__ a1col = a.A1 + a.o0 + ib;
+  const int nchunk = (a.K + BK - 1) / BK;
+
+  // this lane's left-operand rows and their offsets (dwords) in one term plane
+  bool rok[FM];
+  size_t roff[FM];
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    const int jj = j0 + wr + MF * i + lr;
+    rok[i] = jj < a.e1;
+    roff[i] = (size_t)(a.o1 + (rok[i] ? jj : 0)) * 16;
+  }
+  const size_t plane = (size_t)a.len1 * 16;  // dwords per rank chunk of one term
+
+  s8_t av[NT][FM][NH];
+  auto load_a = [&](int t, int c) {
+    const unsigned* base = P + ((size_t)t * nch + c) * plane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (rok[i]) v = *reinterpret_cast<const uint4*>(base + roff[i] + (NH * h + lg) * 4);
+        av[t][i][h] = __builtin_bit_cast(s8_t, v);
+      }
+  };
+  double y[KY];
+  double cr = 0.0, ca = 1.0;
+  auto load_y = [&](int c) {
+#pragma unroll
+    for (int kk = 0; kk < KY; ++kk) {
+      const int r = c * BK + kby + kk;
+      y[kk] = (r < a.K && nok) ? a3row[(size_t)r * a.len2] : 0.0;
+    }
+  };
+  auto load_alpha = [&](int k0) {
+    const int r = k0 + tid;
+    cr = 0.0;
+    ca = 1.0;
+    if (tid < BK && r < a.K) {
+      cr = a.coef[r];
+      ca = a1col[(size_t)r * a.len0];
+    }
+  };
+  auto put_alpha = [&](int ab) {
+    if (tid < BK) alphaS[ab][tid] = cr * ca;
+  };
+  auto store_y = [&](int ab) {
+#pragma unroll
+    for (int g = 0; g < KY / 8; ++g) {
+      unsigned pk[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = g * 8 + 2 * q;
+        unsigned u0[NT], u1[NT];
+        split_fp32<NT>((float)(alphaS[ab][kby + kk] * y[kk]), u0);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * y[kk + 1]), u1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+      }
+      // rank slot s (8 ranks) of column ny: k-step h = s / (64/MF), lane group s % (64/MF)
+      const int sl = (kby >> 3) + g;
+      const int hh = sl / (64 / MF), lgw = sl % (64 / MF);
+      const int piece = ((ny / MF) * NH + hh) * 64 + lgw * MF + (ny % MF);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        Ysf[t * FN * NH * 64 + piece] = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+    }
+  };
+
+  typename Mma::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
+
+  load_alpha(0);
+  put_alpha(0);
+  load_alpha(BK);
+  load_y(0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) load_a(t, 0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    if (c > 0) __syncthreads();
+    store_y(c & 1);
+    put_alpha((c + 1) & 1);
+    __syncthreads();
+    const bool more = c + 1 < nchunk;
+    if (more) load_y(c + 1);
+    load_alpha((c + 2) * BK);
+    s8_t bv[NT][FN][NH];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[((t * FN + j) * NH + h) * 64 + lane]);
+#pragma unroll
+    for (int ta = NT - 1; ta >= 0; --ta) {
+#pragma unroll
+      for (int tb = NT - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+              if constexpr (MF == 16)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+              else
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+            }
+      if (more) load_a(ta, c + 1);
+    }
+  }
+
+  const float sc = (float)a.scale;
+  const size_t obase = (size_t)ib * a.e1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) {
+        const int jj = j0 + wr + i * MF + Mma::drow(lane, v);
+        const int col = col0 + j * MF + Mma::dcol(lane);
+        if (jj < a.e1 && col < a.e2) out[(obase + jj) * a.e2 + col] = sc * acc[i][j][v];
       }
 }
 
 // ---------------------------------------------------------------------------
 // tile table
 // ---------------------------------------------------------------------------
-static void fill_tiles(BoxSet* bs, int bm, int bn) {
+// Row tiles: BM rows of the (i, j) rows, or (per_i) BM values of j for each i.
+static void fill_tiles(BoxSet* bs, int bm, int bn, bool per_i = false) {
   long long acc = 0;
   for (int i = 0; i < bs->nbox; ++i) {
     const BoxArg& a = bs->box[i];
-    const long long tm = ((long long)a.e0 * a.e1 + bm - 1) / bm;
+    const long long tm = per_i ? (long long)a.e0 * ((a.e1 + bm - 1) / bm)
+                               : ((long long)a.e0 * a.e1 + bm - 1) / bm;
     bs->tiles_n[i] = (a.e2 + bn - 1) / bn;
     bs->tile_start[i] = acc;
     acc += tm * bs->tiles_n[i];
@@ -337,27 +747,65 @@ static bool launch_fp(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
 template <int NT>
 static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
   dim3 block(256);
-#define LS_T(ID, BM_, BN_, WM_, WN_, NB_)                                                     \
+#define LS_T(ID, BM_, BN_, WM_, WN_, NB_, MF_)                                                \
   if (tile == ID) {                                                                          \
     if (!dry) {                                                                              \
       fill_tiles(&bs, BM_, BN_);                                                             \
       dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
-      hipLaunchKernelGGL((k_recon_split<NT, BM_, BN_, WM_, WN_, NB_>), grid, block, 0, s, bs, \
-                         (float*)out);                                                       \
+      hipLaunchKernelGGL((k_recon_split<NT, BM_, BN_, WM_, WN_, NB_, MF_>), grid, block, 0, s, \
+                         bs, (float*)out);                                                   \
     }                                                                                        \
     return true;                                                                             \
   }
-  LS_T(1, 128, 128, 64, 64, 2)
-  LS_T(2, 128, 128, 64, 64, 1)
-  LS_T(3, 64, 128, 32, 64, 2)
-  LS_T(4, 128, 64, 64, 32, 2)
-  LS_T(5, 64, 64, 32, 32, 2)
+  LS_T(1, 128, 128, 64, 64, 1, 16)
+  LS_T(2, 128, 128, 64, 64, 1, 32)
+  LS_T(3, 128, 64, 64, 32, 1, 32)
+  LS_T(4, 64, 128, 32, 64, 1, 32)
+  LS_T(5, 64, 64, 32, 32, 2, 16)
 #undef LS_T
+#define LS_P(ID, BM_, BN_, WM_, WN_, NB_, MF_)                                                \
+  if (tile == ID) {                                                                          \
+    if (!dry) {                                                                              \
+      fill_tiles(&bs, BM_, BN_, true);                                                       \
+      dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
+      hipLaunchKernelGGL((k_recon_presplit<NT, BM_, BN_, WM_, WN_, NB_, MF_>), grid, block, 0, \
+                         s, bs, (float*)out);                                                \
+    }                                                                                        \
+    return true;                                                                             \
+  }
+  LS_P(6, 256, 64, 64, 64, 1, 16)
+  LS_P(7, 256, 64, 64, 64, 1, 32)
+  LS_P(8, 128, 128, 64, 64, 1, 32)
+  LS_P(9, 128, 64, 64, 32, 1, 32)
+#undef LS_P
+#define LS_D(ID, MF_)                                                                         \
+  if (tile == ID) {                                                                          \
+    if (!dry) {                                                                              \
+      fill_tiles(&bs, 256, 64, true);                                                        \
+      dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
+      hipLaunchKernelGGL((k_recon_direct<NT, 64, MF_>), grid, block, 0, s, bs, (float*)out);  \
+    }                                                                                        \
+    return true;                                                                             \
+  }
+  LS_D(10, 16)
+  LS_D(11, 32)
+#undef LS_D
   return false;
 }
 
+// tiles of the split precisions that read f1 pre-split from the workspace
+static bool presplit_tile(int precision, int tile) {
+  return (precision == LS_BF16X3 || precision == LS_BF16X6) && tile >= 6;
+}
+
+static size_t presplit_bytes(int precision, int K, int len1) {
+  if (precision != LS_BF16X3 && precision != LS_BF16X6) return 0;
+  const size_t nt = precision == LS_BF16X6 ? 3 : 2;
+  return nt * (size_t)((K + SPLIT_BK - 1) / SPLIT_BK) * (size_t)len1 * 64;
+}
+
 static int n_tiles(int precision) {
-  return precision == LS_F32 ? 8 : 5;
+  return precision == LS_F32 ? 8 : (precision == LS_F64 ? 5 : 11);
 }
 
 static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
@@ -371,10 +819,15 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 }
 
 // Tile picked when the caller passes tile = 0 (measured on 256^3 boxes,
-// K = 384: FP64 128x64, FP32 128x128 with rank chunk 16, BF16x6 128x128 single
-// LDS buffer, BF16x3 128x128 double buffer).
-static int auto_tile(int precision, long long M, long long Nc) {
+// K = 384: FP64 128x64, FP32 128x128 with rank chunk 16, split-bf16 with a
+// workspace 256x64 with the left operand read straight into registers).
+static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
+  const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
+  if (split && have_ws && big >= 256) {
+    if (e1 >= 256) return 10;
+    if (e1 >= 128) return 9;
+  }
   if (big >= 256) {
     switch (precision) {
       case LS_F64: return 3;
@@ -383,7 +836,7 @@ static int auto_tile(int precision, long long M, long long Nc) {
       default: return 1;
     }
   }
-  if (precision == LS_BF16X3 || precision == LS_BF16X6) return big >= 128 ? 4 : 5;
+  if (split) return big >= 128 ? 4 : 5;
   const long long mid = ((M + 127) / 128) * ((Nc + 63) / 64);
   if (mid >= 512) return 3;
   return 2;
@@ -398,9 +851,14 @@ extern "C" int32_t ls_reconstruct_tiles(int32_t precision) {
   return n_tiles(precision);
 }
 
+extern "C" size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision) {
+  if (P == nullptr || P->K < 1 || P->len[1] < 1) return 0;
+  return presplit_bytes(precision, P->K, P->len[1]);
+}
+
 extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox,
                                     double scale, int32_t precision, int32_t tile, void* out_dev,
-                                    hipStream_t stream) {
+                                    void* ws_dev, size_t ws_bytes, hipStream_t stream) {
   clear_error();
   LS_REQUIRE(P != nullptr && boxes != nullptr && out_dev != nullptr, "null pointer");
   LS_REQUIRE(P->K >= 1, "rank K must be >= 1");
@@ -421,17 +879,39 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     }
     LS_REQUIRE((long long)boxes[b].e[0] * boxes[b].e[1] < (1LL << 31), "box %d too large", b);
   }
-  const int t = tile ? tile : auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1],
-                                        boxes[0].e[2]);
+  const size_t need = presplit_bytes(precision, P->K, P->len[1]);
+  const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
+  const int t = tile ? tile
+                     : auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1],
+                                 boxes[0].e[2], boxes[0].e[1], have_ws);
   BoxSet probe;
   if (!dispatch(precision, t, stream, probe, nullptr, true)) {
     set_error("tile %d not available for precision %d", t, precision);
     return LS_EUNSUPPORTED;
   }
+  const bool pre = presplit_tile(precision, t);
+  if (pre && !have_ws) {
+    set_error("tile %d needs a workspace of %zu bytes", t, need);
+    return LS_EWORKSPACE;
+  }
+  const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
+  if (pre) {
+    dim3 grid((P->len[1] + 255) / 256, nch);
+    if (precision == LS_BF16X6)
+      hipLaunchKernelGGL(k_presplit<3>, grid, dim3(256), 0, stream, P->f[1], P->K, P->len[1], nch,
+                         (unsigned*)ws_dev);
+    else
+      hipLaunchKernelGGL(k_presplit<2>, grid, dim3(256), 0, stream, P->f[1], P->K, P->len[1], nch,
+                         (unsigned*)ws_dev);
+    ls_status st = launch_status("ls_reconstruct (pre-split)");
+    if (st != LS_OK) return st;
+  }
   long long off = 0;  // elements
   for (int b0 = 0; b0 < nbox; b0 += kBoxesPerLaunch) {
     BoxSet bs;
     bs.nbox = (nbox - b0) < kBoxesPerLaunch ? (nbox - b0) : kBoxesPerLaunch;
+    bs.P2 = pre ? (const unsigned*)ws_dev : nullptr;
+    bs.nch = nch;
     long long local = 0;
     for (int i = 0; i < bs.nbox; ++i) {
       const ls_box& bx = boxes[b0 + i];

@@ -72,9 +72,10 @@ def test_invalid_host_arguments(lib):
     bad = _lib.Lattice(0, (ctypes.c_int32 * 3)(1, 1, 1), 10.0, 0)
     assert lib.ls_master_halfwidth(ctypes.byref(bad), ctypes.byref(X)) == _lib.LS_EINVAL
     # null descriptors: rejected on the host, nothing launched
-    assert lib.ls_reconstruct(None, None, 1, 1.0, 0, 0, None, None) == _lib.LS_EINVAL
+    assert lib.ls_reconstruct(None, None, 1, 1.0, 0, 0, None, None, 0, None) == _lib.LS_EINVAL
     assert lib.ls_energy(None, None, 0, None, None, 0, None) == _lib.LS_EINVAL
     assert lib.ls_assemble(None, None, 1, None, None, None, 0, 0, None, None, None, None,
                            None) == _lib.LS_EINVAL
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
+    assert lib.ls_reconstruct_workspace(None, 2) == 0
     assert lib.ls_energy_workspace(10, 8) >= 3 * 10 * 8 * 8
