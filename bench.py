@@ -181,6 +181,43 @@ def cpu_baseline(sysm, edge):
                       f"reconstruction of one {edge}^3 sub-box of box 0; {dt:.1f} s single-threaded"}
 
 
+def measured_peaks(L, dev):
+    """Attainable rates on this GPU from the reference kernels: a 1 GiB device
+    copy (read + write bytes) and MFMA issue loops (the instruction shapes the
+    kernels use and the faster 32x32 shapes)."""
+    import torch
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    sec = timed(lambda: L.probe_copy(a, b), 10)
+    del a, b
+    out = torch.empty(4096 * 256, dtype=torch.float32, device=dev)
+    res = {"hbm_copy_GBps": round(2 * nbytes / sec / 1e9, 1)}
+    for name, prec, shape, iters in (("f64_16x16x4", "f64", 0, 1000), ("f32_16x16x4", "f32", 0, 1000),
+                                     ("f32_32x32x2", "f32", 1, 1000),
+                                     ("bf16_16x16x32", "bf16x6", 0, 2000),
+                                     ("bf16_32x32x16", "bf16x6", 1, 1000)):
+        fl = [0.0]
+
+        def run():
+            fl[0] = L.probe_mfma(prec, 4096, iters, out, shape)
+        sec = timed(run, 3)
+        res[f"mfma_{name}_TFLOPs"] = round(fl[0] / sec / 1e12, 1)
+    return res
+
+
 def main():
     args = parse()
     if args.mode == "kernels":
@@ -207,7 +244,11 @@ def main():
     nvals = sum(b[3] * b[4] * b[5] for b in boxes)
     scale = 1.0 / sysm.h ** 3
     K = sysm.K
-    ws = torch.empty(L.api.lib().ls_energy_workspace(K, 8), dtype=torch.uint8, device=dev)
+    lib = L.api.lib()
+    ews = torch.empty(lib.ls_energy_workspace(K, 8), dtype=torch.uint8, device=dev)
+    N = sysm.L[1] * sysm.n
+    # reconstruction workspace (pre-split f1 of the split-bf16 precisions)
+    rws = torch.empty(3 * ((K + 31) // 32) * N * 64, dtype=torch.uint8, device=dev)
     outs = {"f64": torch.empty(nvals, dtype=torch.float64, device=dev)}
     precs = [p for p in args.precisions.split(",") if p]
     for p in precs:
@@ -215,35 +256,68 @@ def main():
             outs[p] = torch.empty(nvals, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(prec, ev=None):
-        qt = L.quadrature("S", q["M"], q["C0"], q["s"])                 # a1 (host)
+    def device_step(prec, qt, ev=None):
         masters = L.kernel_vectors(spec, qt, pos)                          # a2
+        if ev is not None:
+            ev[0].record(torch.cuda.current_stream())
         F, coef = L.assemble(spec, qt, pos, Z, masters)                    # a3
-        E = L.energy(F, coef, D, d, "f64", ws)                             # a6
         if ev is not None:
-            ev[0].record(stream)
-        L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec)        # a5
+            ev[1].record(torch.cuda.current_stream())
+        E = L.energy(F, coef, D, d, "f64", ews)                            # a6
         if ev is not None:
-            ev[1].record(stream)
+            ev[2].record(torch.cuda.current_stream())
+        L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws)  # a5
+        if ev is not None:
+            ev[3].record(torch.cuda.current_stream())
         return F, coef, E
 
+    def quad():
+        return L.quadrature("S", q["M"], q["C0"], q["s"])                  # a1 (host)
+
     results = {}
+    graphs = {}
     for prec in ["f64"] + [p for p in precs if p != "f64"]:
+        # eager steps with events around the assembly and reconstruction launches
         for _ in range(args.warmup):
-            step(prec)
+            device_step(prec, quad())
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
         t0 = time.perf_counter()
         for i in range(args.steps):
-            step(prec, evs[i])
+            device_step(prec, quad(), evs[i])
+        torch.cuda.synchronize()
+        eager = time.perf_counter() - t0
+        asm_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+        en_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+        recon_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+        # the whole device step captured once and replayed: one replay per step
+        qt = quad()
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            device_step(prec, qt)
+        stream.wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            gF, gc, gE = device_step(prec, qt)
+        graphs[prec] = (g, gF, gc, gE)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            quad()
+            g.replay()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        recon_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
-        results[prec] = {"ms_per_step": 1e3 * wall / args.steps, "recon_ms": recon_ms}
+        results[prec] = {"ms_per_step": 1e3 * wall / args.steps,
+                         "eager_ms_per_step": 1e3 * eager / args.steps,
+                         "assembly_ms": asm_ms, "energy_ms": en_ms, "recon_ms": recon_ms}
 
     # errors of the mixed variants against the FP64 path (not timed)
-    F, coef, E = step("f64")
+    graphs["f64"][0].replay()
+    torch.cuda.synchronize()
+    F, coef, E = graphs["f64"][1], graphs["f64"][2], graphs["f64"][3]
     absout = torch.empty(nvals, dtype=torch.float64, device=dev)
     L.reconstruct_into(F, coef.abs(), boxes, absout, scale, "f64")
     vmax = float(outs["f64"].abs().max())
@@ -251,10 +325,12 @@ def main():
     for prec in precs:
         if prec == "f64":
             continue
-        step(prec)
+        graphs[prec][0].replay()
+        torch.cuda.synchronize()
         err = float((outs[prec].double() - outs["f64"]).abs().max())
         results[prec]["rel_inf"] = err / vmax
         results[prec]["rel_mag"] = err / vabs
+    E = float(graphs["f64"][3].cpu())
 
     flops = 2.0 * nvals * K
     for prec, r in results.items():
@@ -264,13 +340,36 @@ def main():
     gated = [p for p in precs if p != "f64" and results[p].get("rel_mag", 1.0) <= 1e-6]
     best = min(gated, key=lambda p: results[p]["ms_per_step"]) if gated else "f64"
     rb = results[best]
-    per_launch_ms = rb["recon_ms"] / len(boxes)
-    achieved = flops / len(boxes) / (per_launch_ms / 1e3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAKS_TFLOPS[best],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAKS_TFLOPS[best], 4),
-                "traffic": None, "kernel": f"k_recon ({best})",
-                "per_launch_ms": round(per_launch_ms, 4),
-                "algorithmic_flops_per_launch": flops / len(boxes)}
+    peaks = measured_peaks(L, dev)
+    # dominant kernel: the reconstruction launch (all 16 boxes), timed by the
+    # event pair around ls_reconstruct (includes the pre-split of f1 for the
+    # split precisions). Split-bf16 runs 6 (x6) or 3 (x3) bf16 products per
+    # product of the algorithm: its peak is the bf16 dense peak over that.
+    nprod = {"f64": 1, "f32": 1, "bf16x6": 6, "bf16x3": 3}[best]
+    achieved = flops / (rb["recon_ms"] / 1e3) / 1e12
+    peak = PEAKS_TFLOPS[best] / nprod
+    mkey = {"f64": "mfma_f64_16x16x4_TFLOPs", "f32": "mfma_f32_32x32x2_TFLOPs",
+            "bf16x6": "mfma_bf16_32x32x16_TFLOPs", "bf16x3": "mfma_bf16_32x32x16_TFLOPs"}[best]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": f"reconstruction ({best}), 16 boxes 256^3 per launch",
+                "peak_basis": (f"{PEAKS_TFLOPS[best]} TFLOP/s dense / {nprod} products"
+                               if nprod > 1 else "dense peak of the dtype"),
+                "launch_ms": round(rb["recon_ms"], 4),
+                "algorithmic_flops_per_launch": flops,
+                "measured_peak": round(peaks[mkey] / nprod, 2),
+                "frac_of_measured": round(achieved / (peaks[mkey] / nprod), 4)}
+    # assembly from stored masters (HBM-bound): each master entry it uses read
+    # once, each factor entry written once
+    Lm = sysm.L[0]
+    asm_bytes = 3 * sysm.M0 * sysm.R * ((2 * Lm - 1) * sysm.n + N) * 8 + K * 8
+    asm_ms = results["f64"]["assembly_ms"]
+    assembly = {"bound": "hbm", "achieved": round(asm_bytes / (asm_ms / 1e3) / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(asm_bytes / (asm_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "measured_peak": peaks["hbm_copy_GBps"],
+                "frac_of_measured": round(asm_bytes / (asm_ms / 1e3) / 1e9 / peaks["hbm_copy_GBps"], 4),
+                "launch_ms": round(asm_ms, 4), "algorithmic_bytes_per_launch": asm_bytes}
 
     forces = None
     if not args.no_forces:
@@ -319,6 +418,8 @@ def main():
         "config": {"workload": "box lattice L=32, n=128 (N=4096), 8 charges/cell rock-salt +-1 "
                                "with jitter, rule S R=48 (K=384), 16 sub-boxes 256^3, rank-8 density",
                    "global_batch": len(boxes), "seq_len": None, "parallelism": "none"},
+        "step": "host quadrature table + one replay of the captured device step "
+                "(kernel vectors, assembly, energy, reconstruction of the 16 boxes)",
         "values_per_step": nvals,
         "fp64": {"values_per_s": results["f64"]["values_per_s"],
                  "ms_per_step": results["f64"]["ms_per_step"],
@@ -326,11 +427,13 @@ def main():
         "mixed_speedup_vs_fp64": results["f64"]["ms_per_step"] / rb["ms_per_step"],
         "variants": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()}
                      for p, r in results.items()},
-        "energy": float(E.cpu()),
+        "energy": E,
         "forces": forces,
         "batched": batched,
         "periodic": periodic,
         "roofline": roofline,
+        "assembly_roofline": assembly,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -2,8 +2,8 @@
 // unit-cell atoms by the adjoint of the assembled vectors.
 //
 // Energy from factors (HBM-bound): G_l[r][s] = <f_l[r], rho_l[s]> streams each
-// factor row once (one wave per row and axis, density rows from L2),
-// then E = sum_r coef[r] sum_s d[s] prod_l G_l[r][s] in one workgroup.
+// factor row once through the matrix cores (density rows from L2), then
+// E = sum_r coef[r] sum_s d[s] prod_l G_l[r][s] in one workgroup.
 //
 // Forces without factors: with Phi_l[s][i] = sum_k rho_l[s][i + k n] (the
 // density folded back over the lattice shifts, the transpose of the shift
@@ -40,42 +40,96 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// G[(l*K + r)*Krho + s] = sum_g f_l[r][g] * D_l[s][g]. One wave per factor row
-// (four rows per workgroup); lanes stride the row with coalesced loads and
-// the per-lane partial sums are combined by a fixed shuffle tree (no barriers).
+// Grams G_l = f_l rho_l^T on MFMA, read as G_l^T (Krho x K) = rho_l (Krho x N)
+// times f_l^T (N x K): one wave per 16 factor rows and cell chunk, density
+// rows as the A operand (rows s, zero beyond Krho), factor rows as B (columns
+// r). Lane l loads four consecutive cells c0 + 4(l/16) + j of its row r0 + l%16
+// and of density row l%16, one 32-byte run per row, and issues one MFMA per j
+// (its k index l/16 then stands for cell c0 + 4(l/16) + j): each factor row is
+// read once from HBM in whole 128-byte lines. The cells are split into
+// kGramChunks chunks; the partial Grams are summed in a fixed order.
+constexpr int kGramChunks = 16;
+typedef double gram_d4_t __attribute__((ext_vector_type(4)));
+typedef float gram_f4_t __attribute__((ext_vector_type(4)));
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_rows(const double* __restrict__ f0,
+struct GramMma;
+template <>
+struct GramMma<double> {
+  typedef gram_d4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct GramMma<float> {
+  typedef gram_f4_t acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ f0,
                                                     const double* __restrict__ f1,
                                                     const double* __restrict__ f2,
                                                     const double* __restrict__ D0,
                                                     const double* __restrict__ D1,
                                                     const double* __restrict__ D2, int K, int Krho,
-                                                    int N0, int N1, int N2,
-                                                    double* __restrict__ G) {
+                                                    int N0, int N1, int N2, int chunk,
+                                                    double* __restrict__ part) {
+  typedef GramMma<T> G;
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int l = blockIdx.y;
-  if (r >= K) return;
+  const int r0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int q = blockIdx.y;
+  const int l = blockIdx.z;
+  if (r0 >= K) return;
   const double* f = (l == 0 ? f0 : (l == 1 ? f1 : f2));
   const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2));
   const int N = (l == 0 ? N0 : (l == 1 ? N1 : N2));
-  const double* fr = f + (size_t)r * N;
-  T acc[kMaxRho];
+  const int c_beg = q * chunk;
+  const int c_end = min(N, c_beg + chunk);
+  const int row = lane & 15, kq = lane >> 4;
+  const bool rok = r0 + row < K, sok = row < Krho;
+  const double* fr = f + (size_t)(rok ? r0 + row : 0) * N;
+  const double* dr = D + (size_t)(sok ? row : 0) * N;
+  const double fs = rok ? 1.0 : 0.0, ds = sok ? 1.0 : 0.0;
+  typename G::acc_t acc = {0, 0, 0, 0};
+#pragma unroll 4
+  for (int c0 = c_beg; c0 < c_end; c0 += 16) {
+    const int c = c0 + 4 * kq;
+    double fv[4], dv[4];
+    // unconditional loads at clamped cells (always in range), masked after
 #pragma unroll
-  for (int s = 0; s < kMaxRho; ++s) acc[s] = 0;
-  for (int g = lane; g < N; g += 64) {
-    const T fv = (T)fr[g];
-#pragma unroll
-    for (int s = 0; s < kMaxRho; ++s)
-      if (s < Krho) acc[s] += fv * (T)D[(size_t)s * N + g];
-  }
-#pragma unroll
-  for (int s = 0; s < kMaxRho; ++s) {
-    if (s < Krho) {
-      const double tot = wave_sum64((double)acc[s]);
-      if (lane == 0) G[((size_t)l * K + r) * Krho + s] = tot;
+    for (int j = 0; j < 4; ++j) {
+      const int cc = min(c + j, c_end - 1);
+      const double m = (c + j < c_end) ? 1.0 : 0.0;
+      fv[j] = fr[cc] * (fs * m);
+      dv[j] = dr[cc] * (ds * m);
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc = G::mma((T)dv[j], (T)fv[j], acc);
   }
+  // acc[v] = G_l^T[s][r] with s = drow(lane, v), r = r0 + lane % 16
+  double* out = part + ((size_t)q * 3 + l) * (size_t)K * Krho;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int s = G::drow(lane, v);
+    if (s < Krho && rok) out[(size_t)(r0 + row) * Krho + s] = (double)acc[v];
+  }
+}
+
+// G[l][r][s] = sum over the chunks q (ascending) of part[q][l][r][s]
+__global__ __launch_bounds__(256) void k_gram_sum(const double* __restrict__ part, int n,
+                                                   double* __restrict__ G) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < kGramChunks; ++q) acc += part[(size_t)q * n + i];
+  G[i] = acc;
 }
 
 // E = sum_r coef[r] sum_s d[s] G0[r][s] G1[r][s] G2[r][s]
@@ -236,9 +290,11 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 using namespace ls;
 
+// workspace: G [3][K][Krho] | partial Grams [kGramChunks][3][K][Krho]
 extern "C" size_t ls_energy_workspace(int32_t K, int32_t Krho) {
   if (K < 1 || Krho < 1) return 0;
-  return align256((size_t)3 * K * Krho * sizeof(double));
+  return align256((size_t)3 * K * Krho * sizeof(double)) +
+         align256((size_t)kGramChunks * 3 * K * Krho * sizeof(double));
 }
 
 extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t precision,
@@ -264,16 +320,24 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
     return LS_EWORKSPACE;
   }
   double* G = (double*)ws_dev;
-  dim3 grid((P->K + 3) / 4, 3);
+  double* part = (double*)((char*)ws_dev + align256((size_t)3 * P->K * rho->K * sizeof(double)));
+  const int Nmax = std::max(P->len[0], std::max(P->len[1], P->len[2]));
+  const int chunk = ((Nmax + kGramChunks - 1) / kGramChunks + 15) / 16 * 16;
+  // chunks past the end of a shorter axis still write their (zero) partials
+  dim3 grid((P->K + 63) / 64, kGramChunks, 3);
   if (precision == LS_F64)
-    hipLaunchKernelGGL(k_gram_rows<double>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
+    hipLaunchKernelGGL(k_gram_mfma<double>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
                        P->f[2], rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0],
-                       P->len[1], P->len[2], G);
+                       P->len[1], P->len[2], chunk, part);
   else
-    hipLaunchKernelGGL(k_gram_rows<float>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
+    hipLaunchKernelGGL(k_gram_mfma<float>, grid, dim3(256), 0, stream, P->f[0], P->f[1],
                        P->f[2], rho->f[0], rho->f[1], rho->f[2], P->K, rho->K, P->len[0],
-                       P->len[1], P->len[2], G);
+                       P->len[1], P->len[2], chunk, part);
   ls_status st = launch_status("ls_energy (gram)");
+  if (st != LS_OK) return st;
+  const int n = 3 * P->K * rho->K;
+  hipLaunchKernelGGL(k_gram_sum, dim3((n + 255) / 256), dim3(256), 0, stream, part, n, G);
+  st = launch_status("ls_energy (gram sum)");
   if (st != LS_OK) return st;
   hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, stream, G, P->coef, rho->coef, P->K,
                      rho->K, E_dev);

@@ -358,18 +358,25 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
 // rows into LDS as they are (16-byte loads and stores, no arithmetic) and
 // splits only the BN x 32 values of Y_i per rank chunk.
 template <int NT>
-__global__ __launch_bounds__(256) void k_presplit(const double* __restrict__ f, int K, int len,
-                                                   int nch, unsigned* __restrict__ P) {
-  const int x = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(64) void k_presplit(const double* __restrict__ f, int K, int len,
+                                                  int nch, unsigned* __restrict__ P) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
   const int c = blockIdx.y;
   if (x >= len) return;
+  // all 32 loads first (rank clamped into range, zero beyond K), then the splits
+  double v[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    const int r = 32 * c + q;
+    v[q] = f[(size_t)(r < K ? r : K - 1) * len + x];
+  }
   unsigned pk[NT][16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int r0 = 32 * c + 2 * q;
     unsigned u0[NT], u1[NT];
-    split_fp32<NT>(r0 < K ? (float)f[(size_t)r0 * len + x] : 0.0f, u0);
-    split_fp32<NT>(r0 + 1 < K ? (float)f[(size_t)(r0 + 1) * len + x] : 0.0f, u1);
+    split_fp32<NT>(r0 < K ? (float)v[2 * q] : 0.0f, u0);
+    split_fp32<NT>(r0 + 1 < K ? (float)v[2 * q + 1] : 0.0f, u1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
   }
@@ -531,7 +538,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   // Y_i in LDS in fragment order: the 16-byte piece that lane l supplies for
   // term t, column block j and MFMA k-step h sits at ((t*FN + j)*NH + h)*64 + l,
   // so each fragment read is one contiguous 1 KB
-  __shared__ uint4 Ysf[NT * FN * NH * 64];
+  __shared__ uint4 Ysf[2][NT * FN * NH * 64];
   __shared__ double alphaS[2][BK];
 
   int bidx, tmi, tni;
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   auto put_alpha = [&](int ab) {
     if (tid < BK) alphaS[ab][tid] = cr * ca;
   };
-  auto store_y = [&](int ab) {
+  auto store_y = [&](int yb, int ab) {
 #pragma unroll
     for (int g = 0; g < KY / 8; ++g) {
       unsigned pk[NT][4];
@@ -618,7 +625,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
       const int piece = ((ny / MF) * NH + hh) * 64 + lgw * MF + (ny % MF);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        Ysf[t * FN * NH * 64 + piece] = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+        Ysf[yb][t * FN * NH * 64 + piece] = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
     }
   };
 
@@ -637,9 +644,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
 #pragma unroll
   for (int t = 0; t < NT; ++t) load_a(t, 0);
   __syncthreads();
+  // Y_i double-buffered: one barrier per chunk. Buffer c&1 is rewritten at
+  // chunk c+2, after every wave has passed the barrier of chunk c+1, i.e.
+  // finished its MFMAs of chunk c.
   for (int c = 0; c < nchunk; ++c) {
-    if (c > 0) __syncthreads();
-    store_y(c & 1);
+    const int yb = c & 1;
+    store_y(yb, c & 1);
     put_alpha((c + 1) & 1);
     __syncthreads();
     const bool more = c + 1 < nchunk;
@@ -652,7 +662,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int h = 0; h < NH; ++h)
-          bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[((t * FN + j) * NH + h) * 64 + lane]);
+          bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
 #pragma unroll
     for (int ta = NT - 1; ta >= 0; --ta) {
 #pragma unroll
@@ -896,12 +906,12 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
   }
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
   if (pre) {
-    dim3 grid((P->len[1] + 255) / 256, nch);
+    dim3 grid((P->len[1] + 63) / 64, nch);
     if (precision == LS_BF16X6)
-      hipLaunchKernelGGL(k_presplit<3>, grid, dim3(256), 0, stream, P->f[1], P->K, P->len[1], nch,
+      hipLaunchKernelGGL(k_presplit<3>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
                          (unsigned*)ws_dev);
     else
-      hipLaunchKernelGGL(k_presplit<2>, grid, dim3(256), 0, stream, P->f[1], P->K, P->len[1], nch,
+      hipLaunchKernelGGL(k_presplit<2>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
                          (unsigned*)ws_dev);
     ls_status st = launch_status("ls_reconstruct (pre-split)");
     if (st != LS_OK) return st;

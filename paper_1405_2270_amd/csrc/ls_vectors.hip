@@ -42,16 +42,21 @@ __global__ __launch_bounds__(256) void k_masters(const double* __restrict__ pos,
 // ---------------------------------------------------------------------------
 template <int LMAX>
 __global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__ masters,
-                                                       const double* __restrict__ pos, int R, int n,
+                                                       const double* __restrict__ pos,
+                                                       const double* __restrict__ Z, QuadArg qa,
+                                                       int n,
                                                        int L0, int L1, int L2, double b, double h,
                                                        int X, double* __restrict__ f0,
                                                        double* __restrict__ f1,
-                                                       double* __restrict__ f2) {
+                                                       double* __restrict__ f2,
+                                                       double* __restrict__ coef) {
+  const int R = qa.R;
   const int rho = blockIdx.x * 64 + (threadIdx.x & 63);
   const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int c = blockIdx.z;
   if (rho >= n || q >= R) return;
   const int nu = c / 3, l = c - 3 * (c / 3);
+  if (coef != nullptr && rho == 0 && l == 0) coef[nu * R + q] = Z[nu] * qa.w[q];
   const int L = (l == 0) ? L0 : (l == 1 ? L1 : L2);
   const size_t N = (size_t)L * n;
   int p;
@@ -82,12 +87,16 @@ __global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__
 
 // Box assembly from masters for any L: one lane per output, L reads.
 __global__ __launch_bounds__(256) void k_assemble_box_direct(const double* __restrict__ masters,
-                                                              const double* __restrict__ pos, int R,
-                                                              int n, int L0, int L1, int L2,
+                                                              const double* __restrict__ pos,
+                                                              const double* __restrict__ Z,
+                                                              QuadArg qa, int n, int L0, int L1,
+                                                              int L2,
                                                               double b, double h, int X,
                                                               double* __restrict__ f0,
                                                               double* __restrict__ f1,
-                                                              double* __restrict__ f2) {
+                                                              double* __restrict__ f2,
+                                                              double* __restrict__ coef) {
+  const int R = qa.R;
   const int q = blockIdx.y;
   const int c = blockIdx.z;
   const int nu = c / 3, l = c - 3 * (c / 3);
@@ -95,6 +104,7 @@ __global__ __launch_bounds__(256) void k_assemble_box_direct(const double* __res
   const int N = L * n;
   const int g = blockIdx.x * 256 + threadIdx.x;
   if (g >= N) return;
+  if (coef != nullptr && g == 0 && l == 0) coef[nu * R + q] = Z[nu] * qa.w[q];
   int p;
   double delta;
   node_offset(pos[c], b, h, n, &p, &delta);
@@ -111,13 +121,16 @@ __global__ __launch_bounds__(256) void k_assemble_box_direct(const double* __res
 __global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict__ pos, QuadArg qa,
                                                          Lat lat, int deriv, double* __restrict__ f0,
                                                          double* __restrict__ f1,
-                                                         double* __restrict__ f2) {
+                                                         double* __restrict__ f2,
+                                                         const double* __restrict__ Z,
+                                                         double* __restrict__ coef) {
   const int q = blockIdx.y;
   const int c = blockIdx.z;
   const int nu = c / 3, l = c - 3 * (c / 3);
   const int N = lat.N[l];
   const int g = blockIdx.x * 256 + threadIdx.x;
   if (g >= N) return;
+  if (coef != nullptr && g == 0 && l == 0) coef[nu * qa.R + q] = Z[nu] * qa.w[q];
   int p;
   double delta;
   node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
@@ -136,12 +149,6 @@ __global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict
   }
   double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * qa.R + q) * (size_t)N;
   out[g] = deriv ? acc : lat.h * acc;
-}
-
-__global__ void k_coef(const double* __restrict__ Z, QuadArg qa, int M0, double* __restrict__ coef) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= M0 * qa.R) return;
-  coef[r] = Z[r / qa.R] * qa.w[r % qa.R];
 }
 
 }  // namespace ls
@@ -190,19 +197,23 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
   if (masters_dev != nullptr)
     LS_REQUIRE(X == master_halfwidth(L), "X = %d does not match the lattice (%d)", X,
                master_halfwidth(L));
+  // the coefficients coef[nu R + q] = Z[nu] w[q] are written by the assembly
+  // kernel itself (value vectors only)
+  double* coef = derivative ? nullptr : coef_dev;
   if (masters_dev == nullptr) {
     const int Nmax = L.N[0] > L.N[1] ? (L.N[0] > L.N[2] ? L.N[0] : L.N[2])
                                      : (L.N[1] > L.N[2] ? L.N[1] : L.N[2]);
     dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
     hipLaunchKernelGGL(k_assemble_fused, grid, dim3(256), 0, stream, pos_dev, qa, L,
-                       derivative ? 1 : 0, f0_dev, f1_dev, f2_dev);
+                       derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, Z_dev, coef);
   } else {
     const int Lmax = L.L[0] > L.L[1] ? (L.L[0] > L.L[2] ? L.L[0] : L.L[2])
                                      : (L.L[1] > L.L[2] ? L.L[1] : L.L[2]);
     dim3 grid((L.n + 63) / 64, (qa.R + 3) / 4, 3 * M0);
 #define LS_ASM(LM)                                                                            \
   hipLaunchKernelGGL(k_assemble_box<LM>, grid, dim3(256), 0, stream, masters_dev, pos_dev,    \
-                     qa.R, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev, f2_dev)
+                     Z_dev, qa, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev, f2_dev,  \
+                     coef)
     if (Lmax <= 8)
       LS_ASM(8);
     else if (Lmax <= 16)
@@ -215,13 +226,10 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
       const int Nmax = Lmax * L.n;
       dim3 g2((Nmax + 255) / 256, qa.R, 3 * M0);
       hipLaunchKernelGGL(k_assemble_box_direct, g2, dim3(256), 0, stream, masters_dev, pos_dev,
-                         qa.R, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev, f2_dev);
+                         Z_dev, qa, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h, X, f0_dev, f1_dev,
+                         f2_dev, coef);
     }
 #undef LS_ASM
   }
-  st = launch_status("ls_assemble");
-  if (st != LS_OK || derivative) return st;
-  const int K = M0 * qa.R;
-  hipLaunchKernelGGL(k_coef, dim3((K + 255) / 256), dim3(256), 0, stream, Z_dev, qa, M0, coef_dev);
-  return launch_status("ls_assemble (coef)");
+  return launch_status("ls_assemble");
 }
