@@ -149,13 +149,24 @@ __device__ void fold_task(const SysDev& S, int l) {
   }
 }
 
-// Out-of-line cell integral: keeps the erfc/series evaluation's constants and
+// Out-of-line edge and cell evaluations: keep the erfc/series constants and
 // temporaries out of the persistent kernel's loop nests (register pressure).
-__device__ __attribute__((noinline)) double cell_integral_ool(double tau, double y0) {
-  return cell_integral(tau, y0);
+__device__ __attribute__((noinline)) double edge_ool(double tau, int j, double delta) {
+  return edge_needed(tau, j, delta) ? edge_value(tau, (double)j - delta) : 0.0;
+}
+__device__ __attribute__((noinline)) double cell_ool(double tau, double y0, double eL, double eR) {
+  return cell_from_edges(tau, y0, eL, eR);
 }
 
-// Vector task: atom nu, axis l, all q.
+// Vector task: atom nu, axis l, all q, in groups of kVecQ quadrature points
+// (per cell the folded density values Phi_l[s][j + p] are loaded once for the
+// whole group). One point per group keeps the persistent kernel at two waves
+// per SIMD without spills; larger groups need per-thread accumulators that do
+// not fit beside the reconstruction tile. Edges are evaluated once per cell
+// boundary (shared edges), 255 cells per 256-thread chunk.
+constexpr int kVecQ = 1;
+constexpr int kVecSmem = (2 * kVecQ * 256 + 4 * kVecQ * kBatchRho) * 8;
+
 __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbuf) {
   const int nu = c / 3, l = c - 3 * (c / 3);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -167,65 +178,116 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
   const double* ph = S.Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
   // master cells that land on the sub-box: g = j + p + k n in [o, o+e), k in [0, L)
   const int jlo = o - p - (L - 1) * n, jhi = o + e - 1 - p;
-  double* cbuf = sbuf;            // 256 cell values
-  double* red = sbuf + 256;       // [4][kBatchRho] wave partials
+  double* ebuf = sbuf;                       // [kVecQ][256] edge values
+  double* cbuf = sbuf + kVecQ * 256;         // [kVecQ][256] cell values
+  double* red = sbuf + 2 * kVecQ * 256;      // [4 waves][kVecQ][kBatchRho] partials
+  constexpr int CH = 255;                    // cells per chunk: thread t evaluates edge j0 + t
 #pragma unroll 1
-  for (int q = 0; q < S.R; ++q) {
-    const double tau = ba.tau[S.qoff + q];
-    double acc[kBatchRho];
+  for (int q0 = 0; q0 < S.R; q0 += kVecQ) {
+    double tau[kVecQ];
+    int jb[kVecQ], je[kVecQ];
+    int jbeg = X, jend = -X;
 #pragma unroll
-    for (int s = 0; s < kBatchRho; ++s) acc[s] = 0.0;
-    double v = 0.0;
-    // cells beyond the Gaussian's support contribute exactly 0
-    const double hw = support_halfwidth(tau);
-    const int jbeg = (int)fmax((double)-X, floor(delta - hw));
-    const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
+    for (int g = 0; g < kVecQ; ++g) {
+      // cells beyond each Gaussian's support contribute exactly 0
+      tau[g] = q0 + g < S.R ? ba.tau[S.qoff + q0 + g] : 0.0;
+      const double hw = support_halfwidth(tau[g]);
+      jb[g] = (int)fmax((double)-X, floor(delta - hw));
+      je[g] = q0 + g < S.R ? (int)fmin((double)X, ceil(delta + hw) + 1.0) : jb[g];
+      jbeg = min(jbeg, jb[g]);
+      jend = max(jend, je[g]);
+    }
+    double acc[kVecQ][kBatchRho], v[kVecQ];
+#pragma unroll
+    for (int g = 0; g < kVecQ; ++g) {
+      v[g] = 0.0;
+#pragma unroll
+      for (int s = 0; s < kBatchRho; ++s) acc[g][s] = 0.0;
+    }
 #pragma unroll 1
-    for (int j0 = jbeg; j0 < jend; j0 += 256) {
+    for (int j0 = jbeg; j0 < jend; j0 += CH) {
       const int j = j0 + tid;
-      double bv = 0.0;
-      if (j < jend) {
-        bv = S.h * cell_integral_ool(tau, (double)j - delta);
-        if (bv != 0.0) {
 #pragma unroll
-          for (int s = 0; s < kBatchRho; ++s)
-            if (s < Krho) acc[s] += bv * ph[(size_t)s * W + j];
+      for (int g = 0; g < kVecQ; ++g)
+        ebuf[g * 256 + tid] = (j >= jb[g] && j <= je[g]) ? edge_ool(tau[g], j, delta) : 0.0;
+      __syncthreads();
+      double bv[kVecQ];
+#pragma unroll
+      for (int g = 0; g < kVecQ; ++g) bv[g] = 0.0;
+      if (tid < CH && j < jend) {
+        const double y0 = (double)j - delta;
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < kVecQ; ++g) {
+          if (j >= jb[g] && j < je[g])
+            bv[g] = S.h * cell_ool(tau[g], y0, ebuf[g * 256 + tid], ebuf[g * 256 + tid + 1]);
+          any = any || bv[g] != 0.0;
+        }
+        if (any) {
+#pragma unroll
+          for (int s = 0; s < kBatchRho; ++s) {
+            if (s < Krho) {
+              const double f = ph[(size_t)s * W + j];
+#pragma unroll
+              for (int g = 0; g < kVecQ; ++g) acc[g][s] += bv[g] * f;
+            }
+          }
         }
       }
-      if (j0 + 255 >= jlo && j0 <= jhi) {  // uniform per chunk
-        cbuf[tid] = bv;
+      if (j0 + CH - 1 >= jlo && j0 <= jhi) {  // uniform per chunk
+#pragma unroll
+        for (int g = 0; g < kVecQ; ++g) cbuf[g * 256 + tid] = bv[g];
         __syncthreads();
         if (tid < e) {
           // cells i of this chunk with (j0 + i + p - o) == tid (mod n)
           int i0 = (tid + o - p - j0) % n;
           if (i0 < 0) i0 += n;
 #pragma unroll 1
-          for (int i = i0; i < 256; i += n) {
+          for (int i = i0; i < CH; i += n) {
             const int jj = j0 + i;
             if (jj >= jlo && jj <= jhi) {
               const int k = (o + tid - jj - p) / n;  // exact
-              if (k >= 0 && k < L) v += cbuf[i];
+              if (k >= 0 && k < L) {
+#pragma unroll
+                for (int g = 0; g < kVecQ; ++g) v[g] += cbuf[g * 256 + i];
+              }
             }
           }
         }
-        __syncthreads();
       }
+      __syncthreads();  // ebuf and cbuf are rewritten by the next chunk
     }
     // Gram entries: fixed-order wave then cross-wave sums
-    const int r = nu * S.R + q;
 #pragma unroll
-    for (int s = 0; s < kBatchRho; ++s) {
-      if (s < Krho) {
-        const double t = wave_sum(acc[s]);
-        if (lane == 0) red[wv * kBatchRho + s] = t;
+    for (int g = 0; g < kVecQ; ++g)
+#pragma unroll
+      for (int s = 0; s < kBatchRho; ++s) {
+        if (s < Krho) {
+          const double t = wave_sum(acc[g][s]);
+          if (lane == 0) red[(wv * kVecQ + g) * kBatchRho + s] = t;
+        }
+      }
+    __syncthreads();
+    if (tid < kVecQ * kBatchRho) {
+      const int g = tid / kBatchRho, s = tid % kBatchRho;
+      const int q = q0 + g;
+      if (q < S.R && s < Krho) {
+        const int r = nu * S.R + q;
+        const int i = g * kBatchRho + s;
+        const int st = kVecQ * kBatchRho;
+        S.G[((size_t)l * S.K + r) * Krho + s] =
+            ((red[i] + red[st + i]) + red[2 * st + i]) + red[3 * st + i];
       }
     }
-    __syncthreads();
-    if (tid < Krho)
-      S.G[((size_t)l * S.K + r) * Krho + tid] =
-          ((red[tid] + red[kBatchRho + tid]) + red[2 * kBatchRho + tid]) + red[3 * kBatchRho + tid];
-    if (tid < e) S.Fc[l][(size_t)r * e + tid] = v;
-    if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q];
+#pragma unroll
+    for (int g = 0; g < kVecQ; ++g) {
+      const int q = q0 + g;
+      if (q < S.R) {
+        const int r = nu * S.R + q;
+        if (tid < e) S.Fc[l][(size_t)r * e + tid] = v[g];
+        if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q];
+      }
+    }
     __syncthreads();
   }
 }
@@ -252,7 +314,7 @@ __device__ void energy_task(const SysDev& S, double* sbuf) {
 template <typename T, int BM, int BN, int WM, int WN, int BK>
 __global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
   constexpr int RB = recon_smem_bytes<T, BM, BN, BK>();
-  constexpr int VB = (256 + 4 * kBatchRho) * 8;
+  constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
   __shared__ int s_task, s_flag;
   for (;;) {

@@ -60,48 +60,53 @@ ls_status launch_status(const char* what);
 //
 // With u = tau*y, a = tau*(y0 + 1/2) and c = tau/2 the integral is
 // (1/tau) * integral over [a - c, a + c] of exp(-u^2) du. Two evaluations:
-//  * nearly flat integrand (tau <= 0.35 and |a| tau <= 0.25): expand around
-//    the cell centre, exp(-(a+s)^2) = exp(-a^2) exp(-2as - s^2), whose even
-//    part in s has the Hermite series sum_m H_2m(a) s^2m/(2m)!, so
+//  * nearly flat integrand (tau <= 0.35 and |a| tau <= 0.25, hermite_cell):
+//    expand around the cell centre, exp(-(a+s)^2) = exp(-a^2) exp(-2as - s^2),
+//    whose even part in s has the Hermite series sum_m H_2m(a) s^2m/(2m)!, so
 //    integral = exp(-a^2) * sum_m H_2m(a) c^2m / (2m+1)!   (8 terms);
 //    this avoids the cancelling difference of two nearly equal erf values.
 //  * otherwise the erfc difference on the tail side (or the erf sum across
 //    the origin); there erfc(far)/erfc(near) <= ~0.6, so nothing cancels.
 // Entries whose near edge is beyond |u| = 27 are below 1e-318 and return 0.
+__device__ __forceinline__ bool hermite_cell(double tau, double y0) {
+  const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
+  return tau <= 0.35 && fabs(a) * tau <= 0.25;
+}
+
+__device__ __forceinline__ double hermite_series(double tau, double y0) {
+  const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
+  const double c = 0.5 * tau;
+  const double c2 = c * c;
+  const double two_a = 2.0 * fabs(a);
+  // H_0 = 1, H_1 = 2a, H_{k+1} = 2a H_k - 2k H_{k-1}
+  double hkm1 = 1.0, hk = two_a;
+  double sum = 1.0, cp = 1.0;
+  const double inv_fact[8] = {1.0,
+                              1.0 / 6.0,
+                              1.0 / 120.0,
+                              1.0 / 5040.0,
+                              1.0 / 362880.0,
+                              1.0 / 39916800.0,
+                              1.0 / 6227020800.0,
+                              1.0 / 1307674368000.0};
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    // advance twice: k = 2m-1 -> 2m
+    double h2 = two_a * hk - 2.0 * (2 * m - 1) * hkm1;  // H_{2m}
+    double h3 = two_a * h2 - 2.0 * (2 * m) * hk;        // H_{2m+1}
+    hkm1 = h2;
+    hk = h3;
+    cp *= c2;
+    sum = fma(h2 * cp, inv_fact[m], sum);
+  }
+  return exp(-a * a) * sum;
+}
+
 __device__ __forceinline__ double cell_integral(double tau, double y0) {
   if (tau == 0.0) return 1.0;
-  const double y1 = y0 + 1.0;
+  if (hermite_cell(tau, y0)) return hermite_series(tau, y0);
   const double u0 = tau * y0;
-  const double u1 = tau * y1;
-  const double a = 0.5 * (u0 + u1);
-  const double aa = fabs(a);
-  if (tau <= 0.35 && aa * tau <= 0.25) {
-    const double c = 0.5 * tau;
-    const double c2 = c * c;
-    const double two_a = 2.0 * aa;
-    // H_0 = 1, H_1 = 2a, H_{k+1} = 2a H_k - 2k H_{k-1}
-    double hkm1 = 1.0, hk = two_a;
-    double sum = 1.0, cp = 1.0;
-    const double inv_fact[8] = {1.0,
-                                1.0 / 6.0,
-                                1.0 / 120.0,
-                                1.0 / 5040.0,
-                                1.0 / 362880.0,
-                                1.0 / 39916800.0,
-                                1.0 / 6227020800.0,
-                                1.0 / 1307674368000.0};
-#pragma unroll
-    for (int m = 1; m < 8; ++m) {
-      // advance twice: k = 2m-1 -> 2m
-      double h2 = two_a * hk - 2.0 * (2 * m - 1) * hkm1;  // H_{2m}
-      double h3 = two_a * h2 - 2.0 * (2 * m) * hk;        // H_{2m+1}
-      hkm1 = h2;
-      hk = h3;
-      cp *= c2;
-      sum = fma(h2 * cp, inv_fact[m], sum);
-    }
-    return exp(-a * a) * sum;
-  }
+  const double u1 = tau * (y0 + 1.0);
   const double k = 0.88622692545275801365 / tau;  // sqrt(pi)/(2 tau)
   if (u0 >= 0.0) {
     if (u0 > 27.0) return 0.0;
@@ -112,6 +117,30 @@ __device__ __forceinline__ double cell_integral(double tau, double y0) {
     return k * (erfc(-u1) - erfc(-u0));
   }
   return k * (erf(u1) + erf(-u0));
+}
+
+// Shared edges. Outside the series range a cell integral is a fixed
+// combination of E(y) = erfc(tau |y|) at its two edges (difference on one
+// side of the origin, 2 - E - E across it), so a thread that covers
+// consecutive cells y0 = j - delta evaluates each edge once: edge j, between
+// cells j-1 and j, at y = j - delta, only where one of the two cells needs it.
+__device__ __forceinline__ bool edge_needed(double tau, int j, double delta) {
+  return !hermite_cell(tau, (double)(j - 1) - delta) || !hermite_cell(tau, (double)j - delta);
+}
+
+__device__ __forceinline__ double edge_value(double tau, double y) {
+  const double u = fabs(tau * y);
+  return u > 27.0 ? 0.0 : erfc(u);
+}
+
+// Integral over cell [y0, y0 + 1] from its edge values eL = E(y0), eR = E(y0 + 1).
+__device__ __forceinline__ double cell_from_edges(double tau, double y0, double eL, double eR) {
+  if (tau == 0.0) return 1.0;
+  if (hermite_cell(tau, y0)) return hermite_series(tau, y0);
+  const double k = 0.88622692545275801365 / tau;
+  if (y0 >= 0.0) return k * (eL - eR);
+  if (y0 + 1.0 <= 0.0) return k * (eR - eL);
+  return k * ((1.0 - eL) + (1.0 - eR));
 }
 
 // d/da of the integral of exp(-t^2 (x - a)^2) over a cell, in grid units:

@@ -180,6 +180,7 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
                                                       double* __restrict__ Gv,
                                                       double* __restrict__ Gd) {
   __shared__ double sh[256];
+  __shared__ double eb[256];
   const int q = blockIdx.x;
   const int c = blockIdx.y;  // nu*3 + l
   const int nu = c / 3, l = c - 3 * (c / 3);
@@ -198,19 +199,27 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
   const double hw = support_halfwidth(tau);
   const int jbeg = (int)fmax((double)-X, floor(delta - hw));
   const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
-  for (int j = jbeg + (int)threadIdx.x; j < jend; j += 256) {
-    const double y0 = (double)j - delta;
-    const double bv = lat.h * cell_integral(tau, y0);
-    const double bd = cell_derivative(tau, y0);
-    if (bv == 0.0 && bd == 0.0) continue;
+  // chunks of 255 cells: thread t evaluates edge j0 + t once (shared edges)
+  for (int j0 = jbeg; j0 < jend; j0 += 255) {
+    const int j = j0 + (int)threadIdx.x;
+    eb[threadIdx.x] = edge_needed(tau, j, delta) ? edge_value(tau, (double)j - delta) : 0.0;
+    __syncthreads();
+    if (threadIdx.x < 255 && j < jend) {
+      const double y0 = (double)j - delta;
+      const double bv = lat.h * cell_from_edges(tau, y0, eb[threadIdx.x], eb[threadIdx.x + 1]);
+      const double bd = cell_derivative(tau, y0);
+      if (bv != 0.0 || bd != 0.0) {
 #pragma unroll
-    for (int s = 0; s < kMaxRho; ++s) {
-      if (s < Krho) {
-        const T f = (T)ph[(size_t)s * W + j];
-        av[s] += (T)bv * f;
-        ad[s] += (T)bd * f;
+        for (int s = 0; s < kMaxRho; ++s) {
+          if (s < Krho) {
+            const T f = (T)ph[(size_t)s * W + j];
+            av[s] += (T)bv * f;
+            ad[s] += (T)bd * f;
+          }
+        }
       }
     }
+    __syncthreads();
   }
   // fixed-order reduction: shuffle tree per wave, then the four waves in order
   const int r = nu * qa.R + q;

@@ -21,20 +21,34 @@ namespace ls {
 // ---------------------------------------------------------------------------
 // masters
 // ---------------------------------------------------------------------------
+// A wave covers 63 consecutive master cells: lane i evaluates the left edge
+// of cell base + i and takes the right edge from lane i + 1, so each edge's
+// erfc is computed once (lane 63 only supplies an edge).
+constexpr int kMasterCellsPerWave = 63;
+
 __global__ __launch_bounds__(256) void k_masters(const double* __restrict__ pos, QuadArg qa,
                                                   double b, double h, int n, int X, int deriv,
                                                   double* __restrict__ out) {
-  const int jj = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int jj = wave * kMasterCellsPerWave + lane;  // master cell (edge for lane 63)
   const int q = blockIdx.y;
   const int c = blockIdx.z;  // nu*3 + l
-  if (jj >= 2 * X) return;
   int p;
   double delta;
   node_offset(pos[c], b, h, n, &p, &delta);
-  const double y0 = (double)(jj - X) - delta;
   const double tau = qa.tau[q];
-  const double v = deriv ? cell_derivative(tau, y0) : h * cell_integral(tau, y0);
-  out[((size_t)c * qa.R + q) * (size_t)(2 * X) + jj] = v;
+  const double y0 = (double)(jj - X) - delta;
+  double v;
+  if (deriv) {
+    v = cell_derivative(tau, y0);
+  } else {
+    const double e = edge_needed(tau, jj - X, delta) ? edge_value(tau, y0) : 0.0;
+    const double eR = __shfl_down(e, 1, 64);
+    v = h * cell_from_edges(tau, y0, e, eR);
+  }
+  if (lane < kMasterCellsPerWave && jj < 2 * X)
+    out[((size_t)c * qa.R + q) * (size_t)(2 * X) + jj] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -169,7 +183,8 @@ extern "C" ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* qua
   LS_REQUIRE(pos_dev != nullptr && masters_dev != nullptr, "null device pointer");
   LS_REQUIRE(X == master_halfwidth(L), "X = %d does not match the lattice (%d)", X,
              master_halfwidth(L));
-  dim3 grid((2 * X + 255) / 256, qa.R, 3 * M0);
+  const int waves = (2 * X + kMasterCellsPerWave - 1) / kMasterCellsPerWave;
+  dim3 grid((waves + 3) / 4, qa.R, 3 * M0);
   hipLaunchKernelGGL(k_masters, grid, dim3(256), 0, stream, pos_dev, qa, L.b, L.h, L.n, X,
                      derivative ? 1 : 0, masters_dev);
   return launch_status("ls_kernel_vectors");
