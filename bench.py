@@ -25,6 +25,41 @@ sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 HBM_PEAK_GBS = 8000.0
+# reconstruction sources whose hash a traffic summary in profiles/ must match
+RECON_SOURCES = ("paper_1405_2270_amd/csrc/ls_recon.hip", "paper_1405_2270_amd/csrc/ls_recon_tile.hpp",
+                 "paper_1405_2270_amd/csrc/ls_common.hpp", "include/latsum.h")
+TRAFFIC_SUMMARY = "profiles/traffic_recon_box_L32_n128_16boxes.md"
+
+
+def recon_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in RECON_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(precision):
+    """HBM bytes per reconstruction launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated by the copy kernel), or None when the
+    summary is missing, covers another precision, or the kernel sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k.strip("`")] = v.strip().strip("`")
+    if fields.get("source_sha256") != recon_source_hash() or fields.get("precision") != precision:
+        return None
+    try:
+        return int(fields["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -46,8 +81,9 @@ def parse():
 
 
 def kernels_once():
-    """One launch of each hot-path kernel on the headline workload, preceded by
-    a plain 1 GiB device-to-device copy whose counters calibrate the traffic
+    """One launch of each hot-path kernel on the headline workload (the
+    reconstruction of all 16 boxes per precision, as timed by the benchmark),
+    preceded by a plain 1 GiB device copy whose counters calibrate the traffic
     counters (FETCH_SIZE / WRITE_SIZE per dispatch)."""
     import numpy as np
     import torch
@@ -68,9 +104,12 @@ def kernels_once():
     masters = L.kernel_vectors(spec, qt, pos)
     F, coef = L.assemble(spec, qt, pos, Z, masters)
     E = L.energy(F, coef, [T(x) for x in s.density.D], T(s.density.d), "f64")
-    box = [tuple(int(v) for v in s.boxes[0])]
+    boxes = [tuple(int(v) for v in b) for b in s.boxes]
+    nv = sum(b[3] * b[4] * b[5] for b in boxes)
     for prec in ("f64", "f32", "bf16x6"):
-        L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec)
+        out = torch.empty(nv, dtype=torch.float64 if prec == "f64" else torch.float32, device=dev)
+        L.reconstruct_into(F, coef, boxes, out, 1.0 / s.h ** 3, prec)
+        del out
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))
 
@@ -351,7 +390,8 @@ def main():
     mkey = {"f64": "mfma_f64_16x16x4_TFLOPs", "f32": "mfma_f32_32x32x2_TFLOPs",
             "bf16x6": "mfma_bf16_32x32x16_TFLOPs", "bf16x3": "mfma_bf16_32x32x16_TFLOPs"}[best]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": recorded_traffic(best),
                 "kernel": f"reconstruction ({best}), 16 boxes 256^3 per launch",
                 "peak_basis": (f"{PEAKS_TFLOPS[best]} TFLOP/s dense / {nprod} products"
                                if nprod > 1 else "dense peak of the dtype"),
