@@ -6,11 +6,12 @@ the adjoint. All arithmetic runs in the HIP library ``liblatsum.so``; this
 package only marshals torch tensors into its C ABI.
 """
 from .api import (LatticeSpec, QuadTable, quadrature, master_halfwidth, kernel_vectors, assemble,
+                  assemble_into,
                   reconstruct, reconstruct_into, reconstruct_tiles, energy, forces, LatticeEnergy,
                   lattice_energy, Batch, combine, richardson,
                   nuclear_matrix, probe_copy, probe_mfma)
 
 __all__ = ["LatticeSpec", "QuadTable", "quadrature", "master_halfwidth", "kernel_vectors",
-           "assemble", "reconstruct", "reconstruct_into", "reconstruct_tiles", "energy", "forces",
+           "assemble", "assemble_into", "reconstruct", "reconstruct_into", "reconstruct_tiles", "energy", "forces",
            "LatticeEnergy", "lattice_energy", "Batch", "combine", "richardson",
            "nuclear_matrix", "probe_copy", "probe_mfma"]

@@ -101,15 +101,31 @@ def assemble(lat, quad, pos, Z, masters=None, derivative=False):
     dev = pos.device
     F = [torch.empty((K, lat.N(l)), dtype=torch.float64, device=dev) for l in range(3)]
     coef = None if derivative else torch.empty(K, dtype=torch.float64, device=dev)
+    return assemble_into(lat, quad, pos, Z, masters, F, coef, derivative)
+
+
+def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
+    """As ``assemble`` but into caller-provided factors F and coef."""
+    pos = _dev_f64(pos, "pos")
+    M0 = pos.shape[0]
+    K = M0 * quad.R
+    for l in range(3):
+        f = _dev_f64(F[l], "factor")
+        if tuple(f.shape) != (K, lat.N(l)):
+            raise ValueError(f"factor {l} must have shape {(K, lat.N(l))}")
     if not derivative:
         Z = _dev_f64(Z, "Z")
+        coef = _dev_f64(coef, "coef")
+        if coef.numel() != K:
+            raise ValueError("coef must have K entries")
     if masters is not None:
         masters = _dev_f64(masters, "masters")
     X = master_halfwidth(lat)
     check("ls_assemble", lib().ls_assemble(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0,
                                            _ptr(pos), _ptr(None if derivative else Z),
                                            _ptr(masters), X, int(derivative), _ptr(F[0]),
-                                           _ptr(F[1]), _ptr(F[2]), _ptr(coef), _stream()))
+                                           _ptr(F[1]), _ptr(F[2]), _ptr(None if derivative else coef),
+                                           _stream()))
     return F, coef
 
 

@@ -158,14 +158,21 @@ __device__ __attribute__((noinline)) double cell_ool(double tau, double y0, doub
   return cell_from_edges(tau, y0, eL, eR);
 }
 
-// Vector task: atom nu, axis l, all q, in groups of kVecQ quadrature points
-// (per cell the folded density values Phi_l[s][j + p] are loaded once for the
-// whole group). One point per group keeps the persistent kernel at two waves
-// per SIMD without spills; larger groups need per-thread accumulators that do
-// not fit beside the reconstruction tile. Edges are evaluated once per cell
-// boundary (shared edges), 255 cells per 256-thread chunk.
-constexpr int kVecQ = 1;
-constexpr int kVecSmem = (2 * kVecQ * 256 + 4 * kVecQ * kBatchRho) * 8;
+// Vector task: atom nu, axis l, all q, in groups of kVecQ = 16 quadrature
+// points. Per chunk of 4 x 63 master cells (63 per wave, each lane's right edge
+// from the next lane: shared edges) the 16 integrals of every cell go to LDS
+// as bq[g][cell]. The Gram sums G[q][s] = sum_j b_q(j) Phi_s(j)
+// then run on v_mfma_f64_16x16x4f64 with the cell values as the A operand
+// (rows q) and the folded density as B (columns s): each density value is
+// loaded once per 16 points, and a wave keeps one 16x16 accumulator tile
+// (four registers per lane). The central-cell factor columns are gathered
+// from the same LDS values. All sums run in a fixed order.
+constexpr int kVecQ = 16;
+// LDS row stride in doubles, 2 mod 32: the 16 rows x 2 cells that a half-wave
+// reads as the MFMA A operand fall on distinct bank pairs
+constexpr int kVecRow = 258;
+constexpr int kVecSmem = (kVecQ * kVecRow + kVecQ * 256 + 4 * kVecQ * kBatchRho) * 8;
+typedef double vec_d4_t __attribute__((ext_vector_type(4)));
 
 __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbuf) {
   const int nu = c / 3, l = c - 3 * (c / 3);
@@ -178,66 +185,60 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
   const double* ph = S.Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
   // master cells that land on the sub-box: g = j + p + k n in [o, o+e), k in [0, L)
   const int jlo = o - p - (L - 1) * n, jhi = o + e - 1 - p;
-  double* ebuf = sbuf;                       // [kVecQ][256] edge values
-  double* cbuf = sbuf + kVecQ * 256;         // [kVecQ][256] cell values
-  double* red = sbuf + 2 * kVecQ * 256;      // [4 waves][kVecQ][kBatchRho] partials
-  constexpr int CH = 255;                    // cells per chunk: thread t evaluates edge j0 + t
+  double* bq = sbuf;                          // [kVecQ][kVecRow] cell values
+  double* vb = sbuf + kVecQ * kVecRow;        // [kVecQ][256] central-cell columns
+  double* red = vb + kVecQ * 256;             // [4 waves][kVecQ][kBatchRho]
+  // a chunk is 4 x 63 cells: wave wv covers cells 63 wv .. 63 wv + 62; lane i
+  // evaluates the left edge of cell 63 wv + i and takes the right edge from
+  // lane i + 1 (lane 63 only supplies an edge)
+  constexpr int CH = 4 * 63;
+  const int ci = 63 * wv + lane;              // this lane's cell within the chunk
+  // MFMA lane roles: A row (point) gq = lane % 16, cell offset ck = lane / 16
+  const int gq = lane & 15, ck = lane >> 4;
 #pragma unroll 1
   for (int q0 = 0; q0 < S.R; q0 += kVecQ) {
-    double tau[kVecQ];
-    int jb[kVecQ], je[kVecQ];
+    const int ng = min(kVecQ, S.R - q0);
+    // support of the group: the union of the points' supports
     int jbeg = X, jend = -X;
-#pragma unroll
-    for (int g = 0; g < kVecQ; ++g) {
-      // cells beyond each Gaussian's support contribute exactly 0
-      tau[g] = q0 + g < S.R ? ba.tau[S.qoff + q0 + g] : 0.0;
-      const double hw = support_halfwidth(tau[g]);
-      jb[g] = (int)fmax((double)-X, floor(delta - hw));
-      je[g] = q0 + g < S.R ? (int)fmin((double)X, ceil(delta + hw) + 1.0) : jb[g];
-      jbeg = min(jbeg, jb[g]);
-      jend = max(jend, je[g]);
+    for (int g = 0; g < ng; ++g) {
+      const double hw = support_halfwidth(ba.tau[S.qoff + q0 + g]);
+      jbeg = min(jbeg, (int)fmax((double)-X, floor(delta - hw)));
+      jend = max(jend, (int)fmin((double)X, ceil(delta + hw) + 1.0));
     }
-    double acc[kVecQ][kBatchRho], v[kVecQ];
+    vec_d4_t acc = {0.0, 0.0, 0.0, 0.0};
+    // each thread tid < e owns column tid of vb (no other thread touches it)
 #pragma unroll
-    for (int g = 0; g < kVecQ; ++g) {
-      v[g] = 0.0;
-#pragma unroll
-      for (int s = 0; s < kBatchRho; ++s) acc[g][s] = 0.0;
-    }
+    for (int g = 0; g < kVecQ; ++g) vb[g * 256 + tid] = 0.0;
 #pragma unroll 1
     for (int j0 = jbeg; j0 < jend; j0 += CH) {
-      const int j = j0 + tid;
-#pragma unroll
-      for (int g = 0; g < kVecQ; ++g)
-        ebuf[g * 256 + tid] = (j >= jb[g] && j <= je[g]) ? edge_ool(tau[g], j, delta) : 0.0;
+      const int j = j0 + ci;
+      const double y0 = (double)j - delta;
+      const bool cell_ok = lane < 63 && j < jend;
+#pragma unroll 1
+      for (int g = 0; g < kVecQ; ++g) {
+        double cv = 0.0;
+        if (g < ng) {  // uniform
+          const double tau = ba.tau[S.qoff + q0 + g];
+          const double hw = support_halfwidth(tau);
+          const bool in = (double)j >= delta - hw - 1.0 && (double)j <= delta + hw + 1.0;
+          const double eL = in ? edge_ool(tau, j, delta) : 0.0;
+          const double eR = __shfl_down(eL, 1, 64);
+          if (cell_ok && in) cv = S.h * cell_ool(tau, y0, eL, eR);
+        }
+        if (lane < 63) bq[g * kVecRow + ci] = cv;
+      }
       __syncthreads();
-      double bv[kVecQ];
-#pragma unroll
-      for (int g = 0; g < kVecQ; ++g) bv[g] = 0.0;
-      if (tid < CH && j < jend) {
-        const double y0 = (double)j - delta;
-        bool any = false;
-#pragma unroll
-        for (int g = 0; g < kVecQ; ++g) {
-          if (j >= jb[g] && j < je[g])
-            bv[g] = S.h * cell_ool(tau[g], y0, ebuf[g * 256 + tid], ebuf[g * 256 + tid + 1]);
-          any = any || bv[g] != 0.0;
-        }
-        if (any) {
-#pragma unroll
-          for (int s = 0; s < kBatchRho; ++s) {
-            if (s < Krho) {
-              const double f = ph[(size_t)s * W + j];
-#pragma unroll
-              for (int g = 0; g < kVecQ; ++g) acc[g][s] += bv[g] * f;
-            }
-          }
-        }
+      // Gram: wave wv takes cells 64 wv .. 64 wv + 63 of the chunk, 4 per MFMA
+#pragma unroll 4
+      for (int k4 = 0; k4 < 16; ++k4) {
+        const int i = 64 * wv + 4 * k4 + ck;  // cell within the chunk
+        const double av = (i < CH) ? bq[gq * kVecRow + i] : 0.0;  // rows g >= ng hold 0
+        const int jj = j0 + i;
+        double bvv = 0.0;
+        if (gq < Krho && i < CH && jj < jend) bvv = ph[(size_t)gq * W + jj];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bvv, acc, 0, 0, 0);
       }
       if (j0 + CH - 1 >= jlo && j0 <= jhi) {  // uniform per chunk
-#pragma unroll
-        for (int g = 0; g < kVecQ; ++g) cbuf[g * 256 + tid] = bv[g];
-        __syncthreads();
         if (tid < e) {
           // cells i of this chunk with (j0 + i + p - o) == tid (mod n)
           int i0 = (tid + o - p - j0) % n;
@@ -249,43 +250,36 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
               const int k = (o + tid - jj - p) / n;  // exact
               if (k >= 0 && k < L) {
 #pragma unroll
-                for (int g = 0; g < kVecQ; ++g) v[g] += cbuf[g * 256 + i];
+                for (int g = 0; g < kVecQ; ++g) vb[g * 256 + tid] += bq[g * kVecRow + i];
               }
             }
           }
         }
       }
-      __syncthreads();  // ebuf and cbuf are rewritten by the next chunk
+      __syncthreads();  // bq is rewritten by the next chunk
     }
-    // Gram entries: fixed-order wave then cross-wave sums
+    // acc[vv] = G[q0 + row][s], row = lane / 16 + 4 vv, s = lane % 16 (f64 MFMA layout)
 #pragma unroll
-    for (int g = 0; g < kVecQ; ++g)
-#pragma unroll
-      for (int s = 0; s < kBatchRho; ++s) {
-        if (s < Krho) {
-          const double t = wave_sum(acc[g][s]);
-          if (lane == 0) red[(wv * kVecQ + g) * kBatchRho + s] = t;
-        }
-      }
+    for (int vv = 0; vv < 4; ++vv) {
+      const int row = (lane >> 4) + 4 * vv;
+      if (gq < kBatchRho) red[(wv * kVecQ + row) * kBatchRho + gq] = acc[vv];
+    }
     __syncthreads();
     if (tid < kVecQ * kBatchRho) {
-      const int g = tid / kBatchRho, s = tid % kBatchRho;
-      const int q = q0 + g;
-      if (q < S.R && s < Krho) {
-        const int r = nu * S.R + q;
-        const int i = g * kBatchRho + s;
+      const int g = tid / kBatchRho, sidx = tid % kBatchRho;
+      if (g < ng && sidx < Krho) {
+        const int r = nu * S.R + q0 + g;
         const int st = kVecQ * kBatchRho;
-        S.G[((size_t)l * S.K + r) * Krho + s] =
-            ((red[i] + red[st + i]) + red[2 * st + i]) + red[3 * st + i];
+        S.G[((size_t)l * S.K + r) * Krho + sidx] =
+            ((red[tid] + red[st + tid]) + red[2 * st + tid]) + red[3 * st + tid];
       }
     }
 #pragma unroll
     for (int g = 0; g < kVecQ; ++g) {
-      const int q = q0 + g;
-      if (q < S.R) {
-        const int r = nu * S.R + q;
-        if (tid < e) S.Fc[l][(size_t)r * e + tid] = v[g];
-        if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q];
+      if (g < ng) {
+        const int r = nu * S.R + q0 + g;
+        if (tid < e) S.Fc[l][(size_t)r * e + tid] = vb[g * 256 + tid];
+        if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q0 + g];
       }
     }
     __syncthreads();
@@ -312,7 +306,7 @@ __device__ void energy_task(const SysDev& S, double* sbuf) {
 }
 
 template <typename T, int BM, int BN, int WM, int WN, int BK>
-__global__ __launch_bounds__(256) void k_batch(BatchArg ba) {
+__global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
   constexpr int RB = recon_smem_bytes<T, BM, BN, BK>();
   constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];

@@ -254,13 +254,15 @@ __global__ __launch_bounds__(256) void k_force_combine(const double* __restrict_
                                                         const double* __restrict__ Gd,
                                                         double* __restrict__ F,
                                                         double* __restrict__ Eatom) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;  // nu*4 + (l or 3 = energy)
+  // one wave per (atom, l or 3 = energy); lanes over q, fixed-order shuffle sum
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);  // nu*4 + (l or 3)
   if (idx >= 4 * M0) return;
   const int nu = idx >> 2, l = idx & 3;
   const int K = M0 * qa.R;
   const size_t stride = (size_t)K * Krho;
   double acc = 0.0;
-  for (int q = 0; q < qa.R; ++q) {
+  for (int q = lane; q < qa.R; q += 64) {
     const size_t base = ((size_t)nu * qa.R + q) * Krho;
     double v = 0.0;
     for (int s = 0; s < Krho; ++s) {
@@ -278,10 +280,13 @@ __global__ __launch_bounds__(256) void k_force_combine(const double* __restrict_
     }
     acc += qa.w[q] * v;
   }
-  if (l < 3)
-    F[nu * 3 + l] = -Z[nu] * acc;
-  else
-    Eatom[nu] = Z[nu] * acc;
+  acc = wave_sum64(acc);
+  if (lane == 0) {
+    if (l < 3)
+      F[nu * 3 + l] = -Z[nu] * acc;
+    else
+      Eatom[nu] = Z[nu] * acc;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum(const double* __restrict__ x, int n,
@@ -429,7 +434,7 @@ extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32
                        qa, L, Phi, rho->K, X, W, K, Gv, Gd);
   st = launch_status("ls_forces (grams)");
   if (st != LS_OK) return st;
-  hipLaunchKernelGGL(k_force_combine, dim3((4 * M0 + 255) / 256), dim3(256), 0, stream, Z_dev, qa,
+  hipLaunchKernelGGL(k_force_combine, dim3(M0), dim3(256), 0, stream, Z_dev, qa,
                      M0, rho->K, rho->coef, Gv, Gd, F_dev, Eatom);
   st = launch_status("ls_forces (combine)");
   if (st != LS_OK || E_dev == nullptr) return st;
