@@ -62,7 +62,8 @@ __global__ __launch_bounds__(256) void k_recon(BoxSet bs, T* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) char smem[recon_smem_bytes<T, BM, BN, BK>()];
   int b, tm, tn;
   if (!locate(bs, &b, &tm, &tn)) return;
-  recon_tile<T, BM, BN, WM, WN, BK>(bs.box[b], tm * BM, tn * BN, out + bs.out_off[b], smem);
+  recon_tile<T, BM, BN, WM, WN, BK>(uniform_box(bs.box[b]), tm * BM, tn * BN, out + bs.out_off[b],
+                                    smem);
 }
 
 template <int BM, int BN, int WM, int WN, int BK>
@@ -70,7 +71,8 @@ __global__ __launch_bounds__(256) void k_recon32(BoxSet bs, float* __restrict__ 
   __shared__ __attribute__((aligned(16))) char smem[recon32_smem_bytes<BM, BN, BK>()];
   int b, tm, tn;
   if (!locate(bs, &b, &tm, &tn)) return;
-  recon_tile32<BM, BN, WM, WN, BK>(bs.box[b], tm * BM, tn * BN, out + bs.out_off[b], smem);
+  recon_tile32<BM, BN, WM, WN, BK>(uniform_box(bs.box[b]), tm * BM, tn * BN, out + bs.out_off[b],
+                                   smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(256) void k_recon_split(BoxSet bs, float* __restric
 
   int bidx, tmi, tni;
   if (!locate(bs, &bidx, &tmi, &tni)) return;
-  const BoxArg& a = bs.box[bidx];
+  const BoxArg a = uniform_box(bs.box[bidx]);
   float* __restrict__ out = out_all + bs.out_off[bidx];
   const int M = a.e0 * a.e1;
   const int row0 = tmi * BM, col0 = tni * BN;
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_presplit(BoxSet bs, float* __r
 
   int bidx, tmi, tni;
   if (!locate(bs, &bidx, &tmi, &tni)) return;
-  const BoxArg& a = bs.box[bidx];
+  const BoxArg a = uniform_box(bs.box[bidx]);
   float* __restrict__ out = out_all + bs.out_off[bidx];
   const int jtn = (a.e1 + BM - 1) / BM;
   const int ib = tmi / jtn;
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_presplit(BoxSet bs, float* __r
   const int col0 = tni * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave / (BN / WN)) * WM, wc = (wave % (BN / WN)) * WN;
-  const int nch = bs.nch;
+  const int nch = rfl(bs.nch);
   const unsigned* __restrict__ P = bs.P2;
 
   const int ny = tid % BN;
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
 
   int bidx, tmi, tni;
   if (!locate(bs, &bidx, &tmi, &tni)) return;
-  const BoxArg& a = bs.box[bidx];
+  const BoxArg a = uniform_box(bs.box[bidx]);
   float* __restrict__ out = out_all + bs.out_off[bidx];
   const int jtn = (a.e1 + BM - 1) / BM;
   const int ib = tmi / jtn;
@@ -552,13 +554,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave * WM;
   const int lr = lane & (MF - 1), lg = lane / MF;
-  const int nch = bs.nch;
+  const int nch = rfl(bs.nch);
   const unsigned* __restrict__ P = bs.P2;
 
   const int ny = tid % BN;
   const int kby = __builtin_amdgcn_readfirstlane(tid / BN) * KY;
   const bool nok = col0 + ny < a.e2;
-  const double* __restrict__ a3row = a.A3 + a.o2 + col0 + ny;
   const double* __restrict__ a1col = a.A1 + a.o0 + ib;
   const int nchunk = (a.K + BK - 1) / BK;
 
@@ -573,40 +574,43 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   }
   const size_t plane = (size_t)a.len1 * 16;  // dwords per rank chunk of one term
 
+  // Every load below is unconditional, at an address clamped into range, and
+  // its raw value is kept until it is consumed: a load under a branch, or a
+  // value used right after its load, would make the wave wait for memory
+  // there. Left-operand rows past e1 read row o1 instead; their products land
+  // in output rows that are never stored. f2 values and rank factors past K or
+  // outside the box are zeroed when they are written to LDS.
   s8_t av[NT][FM][NH];
   auto load_a = [&](int t, int c) {
     const unsigned* base = P + ((size_t)t * nch + c) * plane;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int h = 0; h < NH; ++h) {
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (rok[i]) v = *reinterpret_cast<const uint4*>(base + roff[i] + (NH * h + lg) * 4);
-        av[t][i][h] = __builtin_bit_cast(s8_t, v);
-      }
+      for (int h = 0; h < NH; ++h)
+        av[t][i][h] = *reinterpret_cast<const s8_t*>(base + roff[i] + (NH * h + lg) * 4);
   };
   double y[KY];
   double cr = 0.0, ca = 1.0;
+  bool aok = false;
+  const int ycol = min(col0 + ny, a.e2 - 1);  // clamped column
+  const double* __restrict__ a3c = a.A3 + a.o2 + ycol;
   auto load_y = [&](int c) {
 #pragma unroll
     for (int kk = 0; kk < KY; ++kk) {
       const int r = c * BK + kby + kk;
-      y[kk] = (r < a.K && nok) ? a3row[(size_t)r * a.len2] : 0.0;
+      y[kk] = a3c[(size_t)min(r, a.K - 1) * a.len2];
     }
   };
   auto load_alpha = [&](int k0) {
-    const int r = k0 + tid;
-    cr = 0.0;
-    ca = 1.0;
-    if (tid < BK && r < a.K) {
-      cr = a.coef[r];
-      ca = a1col[(size_t)r * a.len0];
-    }
+    const int r = min(k0 + min(tid, BK - 1), a.K - 1);
+    cr = a.coef[r];
+    ca = a1col[(size_t)r * a.len0];
+    aok = tid < BK && k0 + tid < a.K;
   };
   auto put_alpha = [&](int ab) {
-    if (tid < BK) alphaS[ab][tid] = cr * ca;
+    if (tid < BK) alphaS[ab][tid] = aok ? cr * ca : 0.0;
   };
-  auto store_y = [&](int yb, int ab) {
+  auto store_y = [&](int yb, int ab, int c) {
 #pragma unroll
     for (int g = 0; g < KY / 8; ++g) {
       unsigned pk[NT][4];
@@ -614,8 +618,11 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        split_fp32<NT>((float)(alphaS[ab][kby + kk] * y[kk]), u0);
-        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * y[kk + 1]), u1);
+        const int r = c * BK + kby + kk;
+        const double m0 = (r < a.K && nok) ? 1.0 : 0.0;
+        const double m1 = (r + 1 < a.K && nok) ? 1.0 : 0.0;
+        split_fp32<NT>((float)(alphaS[ab][kby + kk] * (y[kk] * m0)), u0);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * (y[kk + 1] * m1)), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -649,11 +656,11 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   // finished its MFMAs of chunk c.
   for (int c = 0; c < nchunk; ++c) {
     const int yb = c & 1;
-    store_y(yb, c & 1);
+    store_y(yb, c & 1, c);
     put_alpha((c + 1) & 1);
     __syncthreads();
-    const bool more = c + 1 < nchunk;
-    if (more) load_y(c + 1);
+    const int cn = min(c + 1, nchunk - 1);  // the last chunk reloads itself (no branch)
+    load_y(cn);
     load_alpha((c + 2) * BK);
     s8_t bv[NT][FN][NH];
 #pragma unroll
@@ -682,7 +689,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
                     __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
                     acc[i][j], 0, 0, 0);
             }
-      if (more) load_a(ta, c + 1);
+      load_a(ta, cn);
     }
   }
 
@@ -829,7 +836,7 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 }
 
 // Tile picked when the caller passes tile = 0 (measured on 256^3 boxes,
-// K = 384: FP64 128x64, FP32 128x128 with rank chunk 16, split-bf16 with a
+// K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
 // workspace 256x64 with the left operand read straight into registers).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
@@ -840,7 +847,7 @@ static int auto_tile(int precision, long long M, long long Nc, int e1, bool have
   }
   if (big >= 256) {
     switch (precision) {
-      case LS_F64: return 3;
+      case LS_F64: return 2;
       case LS_F32: return 1;
       case LS_BF16X6: return 2;
       default: return 1;

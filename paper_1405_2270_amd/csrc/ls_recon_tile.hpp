@@ -24,6 +24,27 @@ struct BoxArg {
   double scale;
 };
 
+// A copy of a box descriptor whose integer fields are workgroup-uniform values
+// held in scalar registers: read once through readfirstlane, so the compiler
+// cannot re-load them from the kernel arguments inside the rank loop (each
+// re-load would also wait on every outstanding LDS operation). The pointers
+// keep their provenance (global address space).
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ BoxArg uniform_box(const BoxArg& a) {
+  BoxArg u = a;
+  u.K = rfl(a.K);
+  u.len0 = rfl(a.len0);
+  u.len1 = rfl(a.len1);
+  u.len2 = rfl(a.len2);
+  u.o0 = rfl(a.o0);
+  u.o1 = rfl(a.o1);
+  u.o2 = rfl(a.o2);
+  u.e0 = rfl(a.e0);
+  u.e1 = rfl(a.e1);
+  u.e2 = rfl(a.e2);
+  return u;
+}
+
 template <typename T>
 struct Acc;
 template <>
