@@ -157,7 +157,8 @@ def bench_batch(L, T, count, steps, warmup):
 
 def bench_periodic(L, T, steps, warmup):
     """Periodic workload: 64 charges, n=256, 64 images per axis, R=60 (K=3840):
-    fused periodic assembly -> energy -> reconstruction of the 256^3 cell."""
+    fused periodic assembly -> energy -> reconstruction of the 256^3 cell, for
+    FP64, FP32 and BF16x6 reconstruction."""
     import torch
     from workloads import config3
     s = config3()
@@ -169,12 +170,13 @@ def bench_periodic(L, T, steps, warmup):
     box = [tuple(int(v) for v in s.boxes[0])]
     res = {}
     outs = {}
-    for prec in ("f64", "f32"):
+    rws = torch.empty(3 * ((s.K + 31) // 32) * s.n * 64, dtype=torch.uint8, device="cuda")
+    for prec in ("f64", "f32", "bf16x6"):
         def step():
             qt = L.quadrature("S", q["M"], q["C0"], q["s"])
             F, coef = L.assemble(spec, qt, pos, Z)
             E = L.energy(F, coef, D, d, "f64")
-            V = L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec)[0]
+            V = L.reconstruct(F, coef, box, 1.0 / s.h ** 3, prec, 0, rws)[0]
             return F, coef, E, V
         for _ in range(warmup):
             step()
@@ -189,9 +191,10 @@ def bench_periodic(L, T, steps, warmup):
         outs[prec] = V
         res[prec] = {"ms_per_step": round(ms, 4), "values_per_s": s.n ** 3 / (ms / 1e3)}
     Vabs = L.reconstruct(F, coef.abs(), box, 1.0 / s.h ** 3, "f64")[0]
-    err = float((outs["f32"].double() - outs["f64"]).abs().max())
-    res["f32"]["rel_inf"] = err / float(outs["f64"].abs().max())
-    res["f32"]["rel_mag"] = err / float(Vabs.abs().max())
+    for prec in ("f32", "bf16x6"):
+        err = float((outs[prec].double() - outs["f64"]).abs().max())
+        res[prec]["rel_inf"] = err / float(outs["f64"].abs().max())
+        res[prec]["rel_mag"] = err / float(Vabs.abs().max())
     res["energy"] = float(E.cpu())
     res["K"] = s.K
     return res
