@@ -165,14 +165,15 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * boxes: host [nbox]. tile: 0 = automatic, otherwise a tile id from
  * ls_reconstruct_tiles (used by the autotuner).
  * ws_dev, ws_bytes: device workspace, caller-owned, used by the split-bf16
- * precisions only: tiles 6..9 of LS_BF16X3 / LS_BF16X6 first split f1 into
- * bf16 terms there (ls_reconstruct_workspace bytes); tile 0 uses them when the
- * workspace is large enough and the boxes are large, and otherwise tiles that
- * split both operands inside the kernel. NULL / 0 is valid for every other
- * precision and tile.
+ * precisions only: tiles 6 and above of LS_BF16X3 / LS_BF16X6 first split f1
+ * into bf16 terms there (ls_reconstruct_workspace bytes); tile 0 uses them
+ * when the workspace is large enough and the boxes are large (the persistent
+ * kernel, one workgroup per resident slot, for boxes of 256 or more values of
+ * j), and otherwise tiles that split both operands inside the kernel. NULL / 0
+ * is valid for every other precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
  * LS_EUNSUPPORTED (tile id not valid for the precision), LS_EWORKSPACE
- * (tile 6..9 of a split precision with a missing or short workspace).
+ * (tile 6 or above of a split precision with a missing or short workspace).
  */
 ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
                          int32_t precision, int32_t tile, void* out_dev, void* ws_dev,

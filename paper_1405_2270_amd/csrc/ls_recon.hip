@@ -22,6 +22,8 @@
 // A[l%16][k-group l/16] and B[k-group l/16][l%16]. It receives D[4*(l/16) + v][l%16]
 // (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
 // f64 one (checked on gfx950).
+#include <atomic>
+
 #include "ls_recon_tile.hpp"
 
 namespace ls {
@@ -98,6 +100,9 @@ __global__ __launch_bounds__(256) void k_recon32(BoxSet bs, float* __restrict__ 
 // c+1 stay raw in registers while the MFMAs consume chunk c; all arithmetic
 // happens when the chunk is written to LDS.
 constexpr int SPLIT_BK = 32;
+// word 3 of a raw buffer resource on gfx9-family chips (32-bit data format)
+constexpr int kBufferFlags = 0x00020000;
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 template <int NT>
 __device__ __forceinline__ void split_fp32(float x, unsigned (&u)[NT]) {
@@ -529,7 +534,11 @@ __global__ __launch_bounds__(256, 2) void k_recon_presplit(BoxSet bs, float* __r
 // (16-byte loads of consecutive 64-byte rows) and only the shared Y_i operand
 // goes through LDS. The fragments of term t for the next chunk are loaded as
 // soon as the MFMAs of this chunk are done with term t.
-template <int NT, int BN, int MF>
+// PIPE = 0: per chunk, write the chunk to LDS, one barrier, then its MFMAs.
+// PIPE = 1: software pipelined, the MFMAs of chunk c run while the same wave
+// splits and writes chunk c+1 into the other LDS buffer (one barrier per
+// chunk).
+template <int NT, int BN, int MF, int PIPE>
 __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __restrict__ out_all) {
   constexpr int BM = 256, WM = 64, WN = BN;
   constexpr int BK = SPLIT_BK;
@@ -541,7 +550,10 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   // term t, column block j and MFMA k-step h sits at ((t*FN + j)*NH + h)*64 + l,
   // so each fragment read is one contiguous 1 KB
   __shared__ uint4 Ysf[2][NT * FN * NH * 64];
-  __shared__ double alphaS[2][BK];
+  // rank factors of one chunk; the pipelined variants let every thread write
+  // its slot (those past BK hold zeros) so that no branch splits the chunk's
+  // instruction stream
+  __shared__ double alphaS[2][PIPE ? 256 : BK];
 
   int bidx, tmi, tni;
   if (!locate(bs, &bidx, &tmi, &tni)) return;
@@ -563,16 +575,18 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   const double* __restrict__ a1col = a.A1 + a.o0 + ib;
   const int nchunk = (a.K + BK - 1) / BK;
 
-  // this lane's left-operand rows and their offsets (dwords) in one term plane
+  // this lane's left-operand rows and their byte offsets in one term plane
   bool rok[FM];
-  size_t roff[FM];
+  unsigned roff[FM];  // bytes
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
     const int jj = j0 + wr + MF * i + lr;
     rok[i] = jj < a.e1;
-    roff[i] = (size_t)(a.o1 + (rok[i] ? jj : 0)) * 16;
+    roff[i] = (unsigned)(a.o1 + (rok[i] ? jj : 0)) * 64u;
   }
-  const size_t plane = (size_t)a.len1 * 16;  // dwords per rank chunk of one term
+  const size_t plane = (size_t)a.len1 * 64;  // bytes per rank chunk of one term
+  // Global addresses are a wave-uniform base plus a 32-bit per-lane byte
+  // offset (one SGPR pair and one VGPR per load).
 
   // Every load below is unconditional, at an address clamped into range, and
   // its raw value is kept until it is consumed: a load under a branch, or a
@@ -582,23 +596,24 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
   // outside the box are zeroed when they are written to LDS.
   s8_t av[NT][FM][NH];
   auto load_a = [&](int t, int c) {
-    const unsigned* base = P + ((size_t)t * nch + c) * plane;
+    const char* base = reinterpret_cast<const char*>(P) + ((size_t)t * nch + c) * plane;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int h = 0; h < NH; ++h)
-        av[t][i][h] = *reinterpret_cast<const s8_t*>(base + roff[i] + (NH * h + lg) * 4);
+        av[t][i][h] = *reinterpret_cast<const s8_t*>(base + (roff[i] + (NH * h + lg) * 16));
   };
   double y[KY];
   double cr = 0.0, ca = 1.0;
   bool aok = false;
   const int ycol = min(col0 + ny, a.e2 - 1);  // clamped column
-  const double* __restrict__ a3c = a.A3 + a.o2 + ycol;
+  const char* __restrict__ a3c = reinterpret_cast<const char*>(a.A3 + a.o2);
+  const unsigned yoff = (unsigned)ycol * 8u;
   auto load_y = [&](int c) {
 #pragma unroll
     for (int kk = 0; kk < KY; ++kk) {
       const int r = c * BK + kby + kk;
-      y[kk] = a3c[(size_t)min(r, a.K - 1) * a.len2];
+      y[kk] = *reinterpret_cast<const double*>(a3c + (size_t)min(r, a.K - 1) * a.len2 * 8 + yoff);
     }
   };
   auto load_alpha = [&](int k0) {
@@ -608,9 +623,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
     aok = tid < BK && k0 + tid < a.K;
   };
   auto put_alpha = [&](int ab) {
-    if (tid < BK) alphaS[ab][tid] = aok ? cr * ca : 0.0;
+    if constexpr (PIPE)
+      alphaS[ab][tid] = aok ? cr * ca : 0.0;
+    else if (tid < BK)
+      alphaS[ab][tid] = aok ? cr * ca : 0.0;
   };
-  auto store_y = [&](int yb, int ab, int c) {
+  auto store_y = [&](const double (&yv)[KY], int yb, int ab, int c) {
 #pragma unroll
     for (int g = 0; g < KY / 8; ++g) {
       unsigned pk[NT][4];
@@ -621,8 +639,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
         const int r = c * BK + kby + kk;
         const double m0 = (r < a.K && nok) ? 1.0 : 0.0;
         const double m1 = (r + 1 < a.K && nok) ? 1.0 : 0.0;
-        split_fp32<NT>((float)(alphaS[ab][kby + kk] * (y[kk] * m0)), u0);
-        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * (y[kk + 1] * m1)), u1);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk] * (yv[kk] * m0)), u0);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * (yv[kk + 1] * m1)), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -644,24 +662,412 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
 #pragma unroll
       for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
 
-  load_alpha(0);
-  put_alpha(0);
-  load_alpha(BK);
-  load_y(0);
-#pragma unroll
-  for (int t = 0; t < NT; ++t) load_a(t, 0);
-  __syncthreads();
-  // Y_i double-buffered: one barrier per chunk. Buffer c&1 is rewritten at
-  // chunk c+2, after every wave has passed the barrier of chunk c+1, i.e.
-  // finished its MFMAs of chunk c.
-  for (int c = 0; c < nchunk; ++c) {
-    const int yb = c & 1;
-    store_y(yb, c & 1, c);
-    put_alpha((c + 1) & 1);
+  if constexpr (!PIPE) {
+    load_alpha(0);
+    put_alpha(0);
+    load_alpha(BK);
+    load_y(0);
+  #pragma unroll
+    for (int t = 0; t < NT; ++t) load_a(t, 0);
     __syncthreads();
-    const int cn = min(c + 1, nchunk - 1);  // the last chunk reloads itself (no branch)
-    load_y(cn);
-    load_alpha((c + 2) * BK);
+    // Y_i double-buffered: one barrier per chunk. Buffer c&1 is rewritten at
+    // chunk c+2, after every wave has passed the barrier of chunk c+1, i.e.
+    // finished its MFMAs of chunk c.
+    for (int c = 0; c < nchunk; ++c) {
+      const int yb = c & 1;
+      store_y(y, yb, c & 1, c);
+      put_alpha((c + 1) & 1);
+      __syncthreads();
+      const int cn = min(c + 1, nchunk - 1);  // the last chunk reloads itself (no branch)
+      load_y(cn);
+      load_alpha((c + 2) * BK);
+      s8_t bv[NT][FN][NH];
+  #pragma unroll
+      for (int t = 0; t < NT; ++t)
+  #pragma unroll
+        for (int j = 0; j < FN; ++j)
+  #pragma unroll
+          for (int h = 0; h < NH; ++h)
+            bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
+  #pragma unroll
+      for (int ta = NT - 1; ta >= 0; --ta) {
+  #pragma unroll
+        for (int tb = NT - 1 - ta; tb >= 0; --tb)
+  #pragma unroll
+          for (int h = 0; h < NH; ++h)
+  #pragma unroll
+            for (int i = 0; i < FM; ++i)
+  #pragma unroll
+              for (int j = 0; j < FN; ++j) {
+                if constexpr (MF == 16)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+                else
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+              }
+        load_a(ta, cn);
+      }
+    }
+
+  } else {
+    // Chunk m's rank factors live in alphaS[m & 1] and its split f2 values in
+    // Ysf[m & 1]. In the step of chunk c every wave loads the raw f2 values of
+    // chunk c+2 and the rank factors of chunk c+3 into one register set,
+    // reads Ysf[c & 1] for the MFMAs, writes chunk c+1 (raw values loaded one
+    // step earlier, in the other set) into Ysf[(c+1) & 1], last read in the
+    // step of chunk c-1, before the barrier that ends it, and the factors of
+    // chunk c+2 into alphaS[c & 1], last read when chunk c was written. Every
+    // load thus has a full step to arrive. Indices past the last chunk are
+    // clamped: those writes go to a buffer that is never read again.
+    double yr[2][KY], al[2][2];
+    auto ld_y = [&](double (&yv)[KY], int c) {
+#pragma unroll
+      for (int kk = 0; kk < KY; ++kk) {
+        const int r = c * BK + kby + kk;
+        yv[kk] = *reinterpret_cast<const double*>(a3c + (size_t)min(r, a.K - 1) * a.len2 * 8 + yoff);
+      }
+    };
+    auto ld_al = [&](double (&v)[2], int k0) {
+      const int r = min(k0 + min(tid, BK - 1), a.K - 1);
+      v[0] = a.coef[r];
+      v[1] = a1col[(size_t)r * a.len0];
+    };
+    auto pt_al = [&](int ab, const double (&v)[2], int k0) {
+      alphaS[ab][tid] = (tid < BK && k0 + tid < a.K) ? v[0] * v[1] : 0.0;
+    };
+    auto step = [&](int c, const double (&ys)[KY], double (&yl)[KY], const double (&as)[2],
+                    double (&aload)[2]) {
+      const int yb = c & 1;
+      const int cn = min(c + 1, nchunk - 1);
+      ld_y(yl, min(c + 2, nchunk - 1));
+      ld_al(aload, (c + 3) * BK);
+      s8_t bv[NT][FN][NH];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+            bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
+#pragma unroll
+      for (int ta = NT - 1; ta >= 0; --ta) {
+#pragma unroll
+        for (int tb = NT - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+              for (int j = 0; j < FN; ++j) {
+                if constexpr (MF == 16)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+                else
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+              }
+        load_a(ta, cn);
+      }
+      store_y(ys, yb ^ 1, yb ^ 1, cn);
+      pt_al(yb, as, (c + 2) * BK);
+      __syncthreads();
+    };
+
+    ld_al(al[0], 0);
+    ld_y(yr[0], 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) load_a(t, 0);
+    pt_al(0, al[0], 0);
+    ld_al(al[1], BK);
+    __syncthreads();
+    store_y(yr[0], 0, 0, 0);
+    pt_al(1, al[1], BK);
+    ld_y(yr[0], min(1, nchunk - 1));
+    ld_al(al[0], 2 * BK);
+    __syncthreads();
+    for (int c = 0; c < nchunk; c += 2) {
+      step(c, yr[0], yr[1], al[0], al[1]);
+      if (c + 1 < nchunk) step(c + 1, yr[1], yr[0], al[1], al[0]);
+    }
+  }
+  const float sc = (float)a.scale;
+  const size_t obase = (size_t)ib * a.e1;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) {
+        const int jj = j0 + wr + i * MF + Mma::drow(lane, v);
+        const int col = col0 + j * MF + Mma::dcol(lane);
+        if (jj < a.e1 && col < a.e2) out[(obase + jj) * a.e2 + col] = sc * acc[i][j][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// persistent split-bf16 kernel
+// ---------------------------------------------------------------------------
+// One workgroup per resident slot. The workgroups of one XCD share that
+// XCD's range of tiles (numbered as in fill_tiles with per-i row tiles):
+// workgroup l of nbx takes tiles l, l + nbx, l + 2 nbx, ... of the range, so
+// at any time the XCD works on neighbouring tiles, which read the same f1 and
+// f2 slices from its L2. A workgroup walks its tiles as one stream of steps,
+// step s being rank chunk s % nchunk of its tile s / nchunk, and runs the
+// pipeline of the direct kernel (PIPE = 1) over the whole stream: the split
+// of step s+1 and the loads of steps s+2 and s+3 overlap the MFMAs of step s
+// also across tile boundaries, so a tile starts without waiting for memory,
+// and its results are stored (non-temporal) while the stream goes on.
+struct StreamPos {
+  int c;  // rank chunk
+  int g;  // tile number
+  int ib, j0, col0;
+  int o0, o1, o2, e1, e2;
+  long long ooff;  // element offset of the tile's box in the output
+};
+
+__device__ __forceinline__ void stream_tile(const BoxSet& bs, int g, StreamPos& p) {
+  int i = 0;
+  while (i + 1 < bs.nbox && bs.tile_start[i + 1] <= g) ++i;
+  const BoxArg& a = bs.box[i];
+  const int local = g - (int)bs.tile_start[i];
+  const int tn = bs.tiles_n[i];
+  const int tmi = local / tn;
+  const int jtn = (a.e1 + 255) / 256;
+  const int ib = tmi / jtn;
+  p.g = g;
+  p.ib = rfl(ib);
+  p.j0 = rfl((tmi - ib * jtn) * 256);
+  p.col0 = rfl((local - tmi * tn) * 64);
+  p.o0 = rfl(a.o0);
+  p.o1 = rfl(a.o1);
+  p.o2 = rfl(a.o2);
+  p.e1 = rfl(a.e1);
+  p.e2 = rfl(a.e2);
+  p.ooff = bs.out_off[i];
+}
+
+// position of the step after p (the caller keeps p at the stream's last step)
+__device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int nchunk, int nbx) {
+  if (p.c + 1 < nchunk) {
+    p.c += 1;
+  } else {
+    p.c = 0;
+    stream_tile(bs, p.g + nbx, p);
+  }
+}
+
+template <int NT, int MF, int YV = 2>
+__global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
+                                                         float* __restrict__ out_all) {
+  constexpr int BM = 256, BN = 64, WM = 64, WN = BN;
+  constexpr int BK = SPLIT_BK;
+  constexpr int KY = BK * BN / 256;
+  constexpr int FM = WM / MF, FN = WN / MF, NH = MF == 16 ? 1 : 2;
+  typedef SplitMma<MF> Mma;
+  // Ysf and alphaS as in k_recon_direct: step m's split f2 values in Ysf[m & 1]
+  // (fragment order) and its rank factors in alphaS[m & 1]
+  __shared__ uint4 Ysf[2][NT * FN * NH * 64];
+  __shared__ double alphaS[2][256];
+
+  // this workgroup's tiles: first, first + nbx, ... below lim
+  const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3;
+  const int per = (int)bs.per_xcd;
+  const int total = (int)bs.tile_start[bs.nbox];
+  const int lim = min(per, total - xcd * per);
+  if (l >= lim) return;
+  const int ntile = (lim - l + nbx - 1) / nbx;
+
+  const BoxArg a = uniform_box(bs.box[0]);  // factor pointers, K and lengths are common
+  const int K = a.K, len0 = a.len0, len2 = a.len2;
+  const int nchunk = (K + BK - 1) / BK;
+  const int S = ntile * nchunk;
+  const int nch = rfl(bs.nch);
+  const int plane = a.len1 * 64;  // bytes per rank chunk of one term
+  // f2 and the pre-split f1 are read through buffer resources: a uniform
+  // (SGPR) byte offset for the rank row and a 32-bit per-lane offset, so no
+  // per-lane 64-bit address arithmetic (the host keeps both below 2 GB)
+  const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(a.A3), (short)0, K * len2 * 8, kBufferFlags);
+  const __amdgpu_buffer_rsrc_t pbuf = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<unsigned*>(bs.P2), (short)0, (int)(NT * nch * plane), kBufferFlags);
+  const double* __restrict__ A1 = a.A1;
+  const double* __restrict__ coef = a.coef;
+  const float sc = (float)a.scale;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave * WM;
+  const int lr = lane & (MF - 1), lg = lane / MF;
+  const int ny = tid % BN;
+  const int kby = __builtin_amdgcn_readfirstlane(tid / BN) * KY;
+
+  // Loads are unconditional at clamped addresses and their raw values are
+  // kept until use, as in k_recon_direct; rows past e1 read row o1, and f2
+  // values and rank factors outside the box or past K are zeroed when written
+  // to LDS.
+  s8_t av[NT][FM][NH];
+  auto load_a = [&](int t, const StreamPos& p) {
+    const int soff = (t * nch + p.c) * plane;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int jj = p.j0 + wr + MF * i + lr;
+      const int off = (p.o1 + (jj < p.e1 ? jj : 0)) * 64;
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+        av[t][i][h] = __builtin_bit_cast(
+            s8_t, __builtin_amdgcn_raw_buffer_load_b128(pbuf, off + (NH * h + lg) * 16, soff, 0));
+    }
+  };
+  // f2 staging, YV = 2: lane l of wave w reads columns 2(l%32), 2(l%32)+1
+  // of ranks 8w + 4(l/32) .. +3 with 16-byte loads (four per chunk; the
+  // second column past e2, or past the end of f2, is never used). YV = 1:
+  // thread t reads column t%64 of ranks 8(t/64) .. +7 (eight 8-byte loads).
+  const int yp = tid & 31, yh = (tid >> 5) & 1;
+  auto ld_y = [&](double (&yv)[KY], const StreamPos& p) {
+    if constexpr (YV == 2) {
+      const int cb = (p.o2 + min(p.col0 + 2 * yp, p.e2 - 1)) * 8;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int r = min(p.c * BK + kby + 4 * yh + kk, K - 1);
+        const d2_t v = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(ybuf, r * len2 * 8 + cb, 0, 0));
+        yv[2 * kk] = v[0];
+        yv[2 * kk + 1] = v[1];
+      }
+    } else {
+      const int yoff = (p.o2 + min(p.col0 + ny, p.e2 - 1)) * 8;
+#pragma unroll
+      for (int kk = 0; kk < KY; ++kk) {
+        const int r = min(p.c * BK + kby + kk, K - 1);
+        yv[kk] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ybuf, yoff, r * len2 * 8, 0));
+      }
+    }
+  };
+  auto ld_al = [&](double (&v)[2], const StreamPos& p) {
+    const int r = min(p.c * BK + min(tid, BK - 1), K - 1);
+    v[0] = coef[r];
+    v[1] = A1[(size_t)(p.o0 + p.ib) + (size_t)r * len0];
+  };
+  auto pt_al = [&](int ab, const double (&v)[2], const StreamPos& p) {
+    alphaS[ab][tid] = (tid < BK && p.c * BK + tid < K) ? v[0] * v[1] : 0.0;
+  };
+  // No masks here: ranks past K have zero rank factors (and zero pre-split
+  // f1), and the columns past e2 (clamped loads, finite values) only feed
+  // output columns that are never stored.
+  auto store_y = [&](const double (&yv)[KY], int yb, int ab, const StreamPos& p) {
+    if constexpr (YV == 2) {
+      // half a 16-byte piece (4 ranks) per column and term
+      const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
+      uint2* Yh = reinterpret_cast<uint2*>(Ysf[yb]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        unsigned pk[NT][2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          unsigned u0[NT], u1[NT];
+          const int kk = 2 * e;
+          split_fp32<NT>((float)(alphaS[ab][kby + 4 * yh + kk] * yv[2 * kk + q]), u0);
+          split_fp32<NT>((float)(alphaS[ab][kby + 4 * yh + kk + 1] * yv[2 * kk + 2 + q]), u1);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) pk[t][e] = pack_hi(u0[t], u1[t]);
+        }
+        const int n = 2 * yp + q;
+        const int piece = ((n / MF) * NH + hh) * 64 + lgw * MF + (n % MF);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Yh[(t * FN * NH * 64 + piece) * 2 + yh] = make_uint2(pk[t][0], pk[t][1]);
+      }
+      return;
+    }
+#pragma unroll
+    for (int g = 0; g < KY / 8; ++g) {
+      unsigned pk[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = g * 8 + 2 * q;
+        unsigned u0[NT], u1[NT];
+        split_fp32<NT>((float)(alphaS[ab][kby + kk] * yv[kk]), u0);
+        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * yv[kk + 1]), u1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+      }
+      const int sl = (kby >> 3) + g;
+      const int hh = sl / (64 / MF), lgw = sl % (64 / MF);
+      const int piece = ((ny / MF) * NH + hh) * 64 + lgw * MF + (ny % MF);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        Ysf[yb][t * FN * NH * 64 + piece] = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+    }
+  };
+
+  typename Mma::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
+
+  // results of a finished tile; a tile that lies inside its box (the common
+  // case, a uniform test) is stored without per-element tests
+  auto epilogue = [&](const StreamPos& p) {
+    float* __restrict__ out = out_all + p.ooff + (size_t)p.ib * p.e1 * p.e2;
+    if (p.j0 + BM <= p.e1 && p.col0 + BN <= p.e2) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int v = 0; v < Mma::NV; ++v) {
+          float* __restrict__ rp = out + (size_t)(p.j0 + wr + i * MF + Mma::drow(lane, v)) * p.e2 +
+                                   p.col0 + Mma::dcol(lane);
+#pragma unroll
+          for (int j = 0; j < FN; ++j) __builtin_nontemporal_store(sc * acc[i][j][v], rp + j * MF);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int v = 0; v < Mma::NV; ++v) {
+            const int jj = p.j0 + wr + i * MF + Mma::drow(lane, v);
+            const int col = p.col0 + j * MF + Mma::dcol(lane);
+            if (jj < p.e1 && col < p.e2)
+              __builtin_nontemporal_store(sc * acc[i][j][v], &out[(size_t)jj * p.e2 + col]);
+          }
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
+  };
+
+  // p[0..3]: positions of steps s .. s+3 (clamped to the last step S-1)
+  StreamPos p0, p1, p2, p3;
+  p0.c = 0;
+  stream_tile(bs, xcd * per + l, p0);
+  p1 = p0;
+  if (S > 1) stream_next(bs, p1, nchunk, nbx);
+  p2 = p1;
+  if (S > 2) stream_next(bs, p2, nchunk, nbx);
+  p3 = p2;
+  if (S > 3) stream_next(bs, p3, nchunk, nbx);
+
+  double yr[2][KY], al[2][2];
+  // In step s every wave loads the raw f2 values of step s+2 and the rank
+  // factors of step s+3 into one register set, reads Ysf[s & 1] for the
+  // MFMAs, loads the left operand of step s+1 as each term's MFMAs finish,
+  // writes step s+1 (raw values loaded in step s-1, other set) into
+  // Ysf[(s+1) & 1] and the factors of step s+2 into alphaS[s & 1]; both
+  // buffers were last read before the barrier that ended step s-1.
+  auto step = [&](int s, const double (&ys)[KY], double (&yl)[KY], const double (&as)[2],
+                  double (&aload)[2]) {
+    const int yb = s & 1;
+    ld_y(yl, p2);
+    ld_al(aload, p3);
     s8_t bv[NT][FN][NH];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -689,22 +1095,35 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
                     __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
                     acc[i][j], 0, 0, 0);
             }
-      load_a(ta, cn);
+      load_a(ta, p1);
     }
-  }
+    store_y(ys, yb ^ 1, yb ^ 1, p1);
+    pt_al(yb, as, p2);
+    if (p0.c == nchunk - 1) epilogue(p0);
+    __syncthreads();
+    p0 = p1;
+    p1 = p2;
+    p2 = p3;
+    if (s + 4 < S) stream_next(bs, p3, nchunk, nbx);
+  };
 
-  const float sc = (float)a.scale;
-  const size_t obase = (size_t)ib * a.e1;
+  ld_al(al[0], p0);
+  ld_y(yr[0], p0);
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int j = 0; j < FN; ++j)
-#pragma unroll
-      for (int v = 0; v < Mma::NV; ++v) {
-        const int jj = j0 + wr + i * MF + Mma::drow(lane, v);
-        const int col = col0 + j * MF + Mma::dcol(lane);
-        if (jj < a.e1 && col < a.e2) out[(obase + jj) * a.e2 + col] = sc * acc[i][j][v];
-      }
+  for (int t = 0; t < NT; ++t) load_a(t, p0);
+  pt_al(0, al[0], p0);
+  ld_al(al[1], p1);
+  __syncthreads();
+  store_y(yr[0], 0, 0, p0);
+  pt_al(1, al[1], p1);
+  ld_y(yr[0], p1);
+  ld_al(al[0], p2);
+  __syncthreads();
+  // the positions advance inside step: step s sees p0 = step s
+  for (int s = 0; s < S; s += 2) {
+    step(s, yr[0], yr[1], al[0], al[1]);
+    if (s + 1 < S) step(s + 1, yr[1], yr[0], al[1], al[0]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -723,6 +1142,47 @@ static void fill_tiles(BoxSet* bs, int bm, int bn, bool per_i = false) {
   }
   bs->tile_start[bs->nbox] = acc;
   bs->per_xcd = (acc + 7) / 8;
+}
+
+// Workgroups of k_recon_stream<NT, MF> resident at once on the current device
+// (occupancy per CU times CUs, cached per device); 0 if the query fails.
+template <int NT, int MF>
+static int stream_slots() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  const int v = cache[dev].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_recon_stream<NT, MF>), 256, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int n = per_cu * cus;
+  if (n > 0) cache[dev].store(n, std::memory_order_relaxed);
+  return n;
+}
+
+// Persistent launch: nbx workgroups per XCD, at most one per resident slot
+// and one per tile of the XCD's range. Tile numbers and buffer offsets are
+// 32-bit in the kernel; a launch with over 2^31 tiles, or an f2 or pre-split
+// f1 of 2 GB or more, uses the per-tile kernel instead.
+template <int NT, int MF, int YV = 2>
+static void launch_stream(hipStream_t s, BoxSet& bs, float* out) {
+  const long long total = bs.tile_start[bs.nbox];
+  const BoxArg& a = bs.box[0];
+  const long long ybytes = (long long)a.K * a.len2 * 8;
+  const long long pbytes = (long long)NT * bs.nch * a.len1 * 64;
+  if (total >= (1LL << 31) - (1LL << 20) || ybytes >= (1LL << 31) || pbytes >= (1LL << 31)) {
+    dim3 grid((unsigned)(8 * bs.per_xcd));
+    hipLaunchKernelGGL((k_recon_direct<NT, 64, MF, 0>), grid, dim3(256), 0, s, bs, out);
+    return;
+  }
+  int slots = stream_slots<NT, MF>();
+  if (slots < 8) slots = 8 * 64;
+  const long long nbx = std::max(1LL, std::min((long long)(slots / 8), bs.per_xcd));
+  hipLaunchKernelGGL((k_recon_stream<NT, MF, YV>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s, bs,
+                     (int)nbx, out);
 }
 
 template <typename T>
@@ -795,18 +1255,30 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
   LS_P(8, 128, 128, 64, 64, 1, 32)
   LS_P(9, 128, 64, 64, 32, 1, 32)
 #undef LS_P
-#define LS_D(ID, MF_)                                                                         \
+#define LS_D(ID, MF_, PIPE_)                                                                  \
   if (tile == ID) {                                                                          \
     if (!dry) {                                                                              \
       fill_tiles(&bs, 256, 64, true);                                                        \
       dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
-      hipLaunchKernelGGL((k_recon_direct<NT, 64, MF_>), grid, block, 0, s, bs, (float*)out);  \
+      hipLaunchKernelGGL((k_recon_direct<NT, 64, MF_, PIPE_>), grid, block, 0, s, bs,         \
+                         (float*)out);                                                       \
     }                                                                                        \
     return true;                                                                             \
   }
-  LS_D(10, 16)
-  LS_D(11, 32)
+  LS_D(10, 16, 0)
+  LS_D(11, 32, 0)
+  LS_D(12, 16, 1)
+  LS_D(13, 32, 1)
 #undef LS_D
+  if (tile >= 14 && tile <= 16) {
+    if (!dry) {
+      fill_tiles(&bs, 256, 64, true);
+      if (tile == 14) launch_stream<NT, 16>(s, bs, (float*)out);
+      else if (tile == 15) launch_stream<NT, 32>(s, bs, (float*)out);
+      else launch_stream<NT, 16, 1>(s, bs, (float*)out);
+    }
+    return true;
+  }
   return false;
 }
 
@@ -822,7 +1294,7 @@ static size_t presplit_bytes(int precision, int K, int len1) {
 }
 
 static int n_tiles(int precision) {
-  return precision == LS_F32 ? 8 : (precision == LS_F64 ? 5 : 11);
+  return precision == LS_F32 ? 8 : (precision == LS_F64 ? 5 : 16);
 }
 
 static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
@@ -837,12 +1309,12 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 
 // Tile picked when the caller passes tile = 0 (measured on 256^3 boxes,
 // K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
-// workspace 256x64 with the left operand read straight into registers).
+// workspace the persistent stream kernel, 256x64 tiles, 16x16 MFMA).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
   const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
   if (split && have_ws && big >= 256) {
-    if (e1 >= 256) return 10;
+    if (e1 >= 256) return 14;
     if (e1 >= 128) return 9;
   }
   if (big >= 256) {
