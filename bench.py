@@ -16,6 +16,7 @@ Prints ONE JSON line (rank 0). Runs on one GPU; --gpus > 1 is refused.
 """
 import argparse
 import json
+import statistics
 import os
 import sys
 import time
@@ -329,9 +330,11 @@ def main():
             device_step(prec, quad(), evs[i])
         torch.cuda.synchronize()
         eager = time.perf_counter() - t0
-        asm_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-        en_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-        recon_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+        # per-phase times: median over the steps (an event pair also times a
+        # host stall before its launch, which the median leaves out)
+        asm_ms = statistics.median(e[0].elapsed_time(e[1]) for e in evs)
+        en_ms = statistics.median(e[1].elapsed_time(e[2]) for e in evs)
+        recon_ms = statistics.median(e[2].elapsed_time(e[3]) for e in evs)
         # the whole device step captured once and replayed: one replay per step
         qt = quad()
         side = torch.cuda.Stream()
@@ -383,18 +386,24 @@ def main():
     best = min(gated, key=lambda p: results[p]["ms_per_step"]) if gated else "f64"
     rb = results[best]
 
-    def launch_ms(fn, reps=5):
+    def launch_ms(fn, reps=5, trials=3):
         """Average duration of back-to-back launches (the queue stays full, so
-        no host gap enters), HIP events on the launch stream."""
+        no host gap enters), HIP events on the launch stream; the smallest of
+        a few trials, so that a stall of the host thread while it enqueues
+        (which leaves the GPU idle between the events) is not counted."""
         fn()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        best = None
+        for _ in range(trials):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps
+            best = t if best is None else min(best, t)
+        return best
 
     qt0 = quad()
     m0 = L.kernel_vectors(spec, qt0, pos)
