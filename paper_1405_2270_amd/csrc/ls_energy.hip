@@ -48,7 +48,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // (its k index l/16 then stands for cell c0 + 4(l/16) + j): each factor row is
 // read once from HBM in whole 128-byte lines. The cells are split into
 // kGramChunks chunks; the partial Grams are summed in a fixed order.
-constexpr int kGramChunks = 16;
+constexpr int kGramChunks = 64;
 typedef double gram_d4_t __attribute__((ext_vector_type(4)));
 typedef float gram_f4_t __attribute__((ext_vector_type(4)));
 
