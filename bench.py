@@ -28,7 +28,8 @@ PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
 HBM_PEAK_GBS = 8000.0
 # reconstruction sources whose hash a traffic summary in profiles/ must match
 RECON_SOURCES = ("paper_1405_2270_amd/csrc/ls_recon.hip", "paper_1405_2270_amd/csrc/ls_recon_tile.hpp",
-                 "paper_1405_2270_amd/csrc/ls_common.hpp", "include/latsum.h")
+                 "paper_1405_2270_amd/csrc/ls_split_tile.hpp", "paper_1405_2270_amd/csrc/ls_common.hpp",
+                 "include/latsum.h")
 TRAFFIC_SUMMARY = "profiles/traffic_recon_box_L32_n128_16boxes.md"
 
 
@@ -66,7 +67,7 @@ def recorded_traffic(precision):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--steps", type=int, default=30)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--precisions", default="f64,f32,bf16x6,bf16x3")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -115,10 +116,12 @@ def kernels_once():
     print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))
 
 
-def bench_batch(L, T, count, steps, warmup):
+def bench_batch(L, T, count, steps, warmup, precisions=("f64", "f32", "bf16x6")):
     """Batched workload: `count` box systems in one persistent launch (graph
-    replay), FP32 reconstruction of each system's central unit cell, FP64
-    energies. Tile picked by the library's autotuner."""
+    replay), reconstruction of each system's central unit cell in each
+    precision, FP64 energies. Tile picked by the library's autotuner. The
+    reduced precisions report their largest error against the FP64 batch
+    (per system max|x - x64| / max|x64|)."""
     import numpy as np
     import torch
     from workloads import config4
@@ -130,30 +133,40 @@ def bench_batch(L, T, count, steps, warmup):
                           quad=L.quadrature("S", q["M"], q["C0"], q["s"]),
                           pos=T(s.pos), Z=T(s.Z), D=[T(x) for x in s.density.D], d=T(s.density.d),
                           box=tuple(int(v) for v in s.boxes[0])))
-    B = L.Batch(items, "f32")
-    tile, tune_ms = B.autotune()
-    for _ in range(warmup):
-        B.run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        B.run()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    sec, err, ph = B.report(phases=True)
     nvals = sum(int(np.prod(s.boxes[0][3:])) for s in systems)
     flops = sum(2.0 * int(np.prod(s.boxes[0][3:])) * s.K for s in systems)
-    B.close()
-    return {"systems": count, "precision": "f32", "tile": tile, "error_flag": err,
-            "ms_per_run": round(ms, 4), "values": nvals, "values_per_s": nvals / (ms / 1e3),
-            "recon_gflop": round(flops / 1e9, 1),
-            "p50_ms": round(float(np.percentile(sec, 50)) * 1e3, 4),
-            "p99_ms": round(float(np.percentile(sec, 99)) * 1e3, 4),
-            "max_ms": round(float(np.max(sec)) * 1e3, 4),
-            "phase_ms": {"fold": round(ph[0] * 1e3, 4), "vectors": round(ph[1] * 1e3, 4),
-                         "tiles": round(ph[2] * 1e3, 4)}}
+    res, ref = {}, None
+    for prec in precisions:
+        B = L.Batch(items, prec)
+        tile, tune_ms = B.autotune()
+        for _ in range(warmup):
+            B.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            B.run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        sec, err, ph = B.report(phases=True)
+        r = {"tile": tile, "error_flag": err, "ms_per_run": round(ms, 4),
+             "values_per_s": nvals / (ms / 1e3),
+             "p50_ms": round(float(np.percentile(sec, 50)) * 1e3, 4),
+             "p99_ms": round(float(np.percentile(sec, 99)) * 1e3, 4),
+             "max_ms": round(float(np.max(sec)) * 1e3, 4),
+             "phase_ms": {"fold": round(ph[0] * 1e3, 4), "vectors": round(ph[1] * 1e3, 4),
+                          "tiles": round(ph[2] * 1e3, 4)}}
+        if prec == "f64":
+            ref = [o.clone() for o in B.out]
+        elif ref is not None:
+            r["rel_inf_vs_f64"] = max(float((o.double() - x).abs().max() / x.abs().max())
+                                      for o, x in zip(B.out, ref))
+        res[prec] = r
+        B.close()
+        del B
+    return {"systems": count, "values": nvals, "recon_gflop": round(flops / 1e9, 1),
+            "precisions": res}
 
 
 def bench_periodic(L, T, steps, warmup):

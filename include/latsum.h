@@ -267,14 +267,16 @@ typedef struct {
   const double* Z_dev;   /* [M0] */
   ls_canon rho;          /* density, rho.len[l] = N_l, rho.K <= 8 */
   ls_box box;            /* sub-box, e[l] <= min(n, 256) */
-  void* out_dev;         /* [e0][e1][e2]: double (LS_F64) or float (LS_F32) */
+  void* out_dev;         /* [e0][e1][e2]: double (LS_F64), else float */
   double* E_dev;         /* energy <P, rho> */
 } ls_system;
 
 typedef struct ls_batch* ls_batch_t;
 
 /* Plan a batch; *ws_bytes receives the device workspace size.
- * precision: LS_F64 or LS_F32 (reconstruction; everything else is FP64).
+ * precision: LS_F64, LS_F32, LS_BF16X3 or LS_BF16X6, the reconstruction's
+ * (split-bf16: both operands split inside the tile, FP32 accumulation and
+ * output); everything else is FP64.
  * Errors: LS_EINVAL (system index in the message), LS_EUNSUPPORTED. */
 ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
                           ls_batch_t* batch, size_t* ws_bytes);

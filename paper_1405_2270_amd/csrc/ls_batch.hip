@@ -31,7 +31,7 @@
 #include <cstring>
 #include <vector>
 
-#include "ls_recon_tile.hpp"
+#include "ls_split_tile.hpp"
 
 namespace ls {
 
@@ -305,9 +305,11 @@ __device__ void energy_task(const SysDev& S, double* sbuf) {
   __syncthreads();
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int BK>
+// NT = 0: FP64 / FP32 tiles (recon_tile<T>); NT = 2, 3: split-bf16 tiles with
+// NT terms (split_tile, FP32 output, MFMA shape MF).
+template <typename T, int BM, int BN, int WM, int WN, int BK, int NT = 0, int MF = 16>
 __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
-  constexpr int RB = recon_smem_bytes<T, BM, BN, BK>();
+  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1>() : recon_smem_bytes<T, BM, BN, BK>();
   constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
   __shared__ int s_task, s_flag;
@@ -358,7 +360,11 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
       a.e2 = S.e[2];
       a.scale = 1.0 / (S.h * S.h * S.h);
       const int tm = tk.a / S.tiles_n, tn = tk.a - tm * S.tiles_n;
-      recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
+      if constexpr (NT == 0)
+        recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
+      else
+        split_tile<NT, BM, BN, WM, WN, 1, MF>(a, tm * BM, tn * BN, reinterpret_cast<float*>(S.out),
+                                              smem);
       __syncthreads();
       if (threadIdx.x == 0) {
         const unsigned long long now = wall_clock64();
@@ -412,9 +418,29 @@ static bool batch_tile(int tile, TileCfg* c) {
   return false;
 }
 
+// split-bf16 tiles: the in-kernel split of k_recon_split (tiles 1..4 there)
+template <int NT>
+static bool batch_tile_split(int tile, TileCfg* c) {
+#define LS_BS(ID, BM_, BN_, WM_, WN_, MF_)                                 \
+  if (tile == ID) {                                                      \
+    c->bm = BM_;                                                         \
+    c->bn = BN_;                                                         \
+    c->fn = (const void*)&k_batch<float, BM_, BN_, WM_, WN_, 16, NT, MF_>; \
+    return true;                                                         \
+  }
+  LS_BS(1, 128, 128, 64, 64, 16)
+  LS_BS(2, 128, 128, 64, 64, 32)
+  LS_BS(3, 128, 64, 64, 32, 32)
+  LS_BS(4, 64, 128, 32, 64, 32)
+#undef LS_BS
+  return false;
+}
+
 static bool get_tile(int precision, int tile, TileCfg* c) {
   if (precision == LS_F64) return batch_tile<double>(tile, c);
   if (precision == LS_F32) return batch_tile<float>(tile, c);
+  if (precision == LS_BF16X3) return batch_tile_split<2>(tile, c);
+  if (precision == LS_BF16X6) return batch_tile_split<3>(tile, c);
   return false;
 }
 constexpr int kBatchTiles = 4;
@@ -590,8 +616,8 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   clear_error();
   LS_REQUIRE(systems != nullptr && batch != nullptr && ws_bytes != nullptr, "null pointer");
   LS_REQUIRE(count >= 1 && count <= (1 << 20), "count must be in [1, 2^20]");
-  if (precision != LS_F64 && precision != LS_F32) {
-    set_error("batches support LS_F64 and LS_F32 reconstruction");
+  if (precision < LS_F64 || precision > LS_BF16X6) {
+    set_error("unknown batch precision %d", precision);
     return LS_EUNSUPPORTED;
   }
   ls_batch* B = new ls_batch();
