@@ -24,7 +24,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+PEAKS_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0, "f16x3": 2500.0}
 HBM_PEAK_GBS = 8000.0
 # reconstruction sources whose hash a traffic summary in profiles/ must match
 RECON_SOURCES = ("paper_1405_2270_amd/csrc/ls_recon.hip", "paper_1405_2270_amd/csrc/ls_recon_tile.hpp",
@@ -69,7 +69,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=30)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--precisions", default="f64,f32,bf16x6,bf16x3")
+    p.add_argument("--precisions", default="f64,f32,bf16x6,bf16x3,f16x3")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forces", action="store_true")
     p.add_argument("--cpu-sample-edge", type=int, default=160)
@@ -108,7 +108,7 @@ def kernels_once():
     E = L.energy(F, coef, [T(x) for x in s.density.D], T(s.density.d), "f64")
     boxes = [tuple(int(v) for v in b) for b in s.boxes]
     nv = sum(b[3] * b[4] * b[5] for b in boxes)
-    for prec in ("f64", "f32", "bf16x6"):
+    for prec in ("f64", "f32", "bf16x6", "f16x3"):
         out = torch.empty(nv, dtype=torch.float64 if prec == "f64" else torch.float32, device=dev)
         L.reconstruct_into(F, coef, boxes, out, 1.0 / s.h ** 3, prec)
         del out
@@ -172,7 +172,7 @@ def bench_batch(L, T, count, steps, warmup, precisions=("f64", "f32", "bf16x6"))
 def bench_periodic(L, T, steps, warmup):
     """Periodic workload: 64 charges, n=256, 64 images per axis, R=60 (K=3840):
     fused periodic assembly -> energy -> reconstruction of the 256^3 cell, for
-    FP64, FP32 and BF16x6 reconstruction."""
+    FP64, FP32, BF16x6 and FP16x3 reconstruction."""
     import torch
     from workloads import config3
     s = config3()
@@ -184,8 +184,14 @@ def bench_periodic(L, T, steps, warmup):
     box = [tuple(int(v) for v in s.boxes[0])]
     res = {}
     outs = {}
-    rws = torch.empty(3 * ((s.K + 31) // 32) * s.n * 64, dtype=torch.uint8, device="cuda")
-    for prec in ("f64", "f32", "bf16x6"):
+    import ctypes
+    F0, c0 = L.assemble(spec, L.quadrature("S", q["M"], q["C0"], q["s"]), pos, Z)
+    canon = L.api._canon(F0, c0)
+    need = max(L.api.lib().ls_reconstruct_workspace(ctypes.byref(canon), L._lib.PRECISIONS[p])
+               for p in ("bf16x6", "f16x3"))
+    rws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    del F0, c0, canon
+    for prec in ("f64", "f32", "bf16x6", "f16x3"):
         def step():
             qt = L.quadrature("S", q["M"], q["C0"], q["s"])
             F, coef = L.assemble(spec, qt, pos, Z)
@@ -205,7 +211,7 @@ def bench_periodic(L, T, steps, warmup):
         outs[prec] = V
         res[prec] = {"ms_per_step": round(ms, 4), "values_per_s": s.n ** 3 / (ms / 1e3)}
     Vabs = L.reconstruct(F, coef.abs(), box, 1.0 / s.h ** 3, "f64")[0]
-    for prec in ("f32", "bf16x6"):
+    for prec in ("f32", "bf16x6", "f16x3"):
         err = float((outs[prec].double() - outs["f64"]).abs().max())
         res[prec]["rel_inf"] = err / float(outs["f64"].abs().max())
         res[prec]["rel_mag"] = err / float(Vabs.abs().max())
@@ -264,7 +270,9 @@ def measured_peaks(L, dev):
     for name, prec, shape, iters in (("f64_16x16x4", "f64", 0, 1000), ("f32_16x16x4", "f32", 0, 1000),
                                      ("f32_32x32x2", "f32", 1, 1000),
                                      ("bf16_16x16x32", "bf16x6", 0, 2000),
-                                     ("bf16_32x32x16", "bf16x6", 1, 1000)):
+                                     ("bf16_32x32x16", "bf16x6", 1, 1000),
+                                     ("f16_16x16x32", "f16x3", 0, 2000),
+                                     ("f16_32x32x16", "f16x3", 1, 1000)):
         fl = [0.0]
 
         def run():
@@ -303,10 +311,16 @@ def main():
     lib = L.api.lib()
     ews = torch.empty(lib.ls_energy_workspace(K, 8), dtype=torch.uint8, device=dev)
     N = sysm.L[1] * sysm.n
-    # reconstruction workspace (pre-split f1 of the split-bf16 precisions)
-    rws = torch.empty(3 * ((K + 31) // 32) * N * 64, dtype=torch.uint8, device=dev)
-    outs = {"f64": torch.empty(nvals, dtype=torch.float64, device=dev)}
     precs = [p for p in args.precisions.split(",") if p]
+    # reconstruction workspace (pre-split f1 and scales of the split
+    # precisions), sized by the library for the largest need
+    import ctypes
+    Fq, cq = L.assemble(spec, L.quadrature("S", q["M"], q["C0"], q["s"]), pos, Z)
+    cn = L.api._canon(Fq, cq)
+    rws = torch.empty(max([1] + [lib.ls_reconstruct_workspace(ctypes.byref(cn), L._lib.PRECISIONS[p])
+                                 for p in precs]), dtype=torch.uint8, device=dev)
+    del Fq, cq, cn
+    outs = {"f64": torch.empty(nvals, dtype=torch.float64, device=dev)}
     for p in precs:
         if p != "f64":
             outs[p] = torch.empty(nvals, dtype=torch.float32, device=dev)
@@ -447,11 +461,12 @@ def main():
     # back-to-back calls of ls_reconstruct (which include the pre-split of f1
     # for the split precisions). Split-bf16 runs 6 (x6) or 3 (x3) bf16 products
     # per product of the algorithm: its peak is the bf16 dense peak over that.
-    nprod = {"f64": 1, "f32": 1, "bf16x6": 6, "bf16x3": 3}[best]
+    nprod = {"f64": 1, "f32": 1, "bf16x6": 6, "bf16x3": 3, "f16x3": 3}[best]
     achieved = flops / (recon_launch_ms[best] / 1e3) / 1e12
     peak = PEAKS_TFLOPS[best] / nprod
     mkey = {"f64": "mfma_f64_16x16x4_TFLOPs", "f32": "mfma_f32_32x32x2_TFLOPs",
-            "bf16x6": "mfma_bf16_32x32x16_TFLOPs", "bf16x3": "mfma_bf16_32x32x16_TFLOPs"}[best]
+            "bf16x6": "mfma_bf16_32x32x16_TFLOPs", "bf16x3": "mfma_bf16_32x32x16_TFLOPs",
+            "f16x3": "mfma_f16_32x32x16_TFLOPs"}[best]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": recorded_traffic(best),

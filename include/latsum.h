@@ -56,7 +56,10 @@ typedef enum {
   LS_F64 = 0,     /* FP64 operands, FP64 MFMA, FP64 output */
   LS_F32 = 1,     /* operands rounded to FP32, FP32 MFMA, FP32 output */
   LS_BF16X3 = 2,  /* operands split into 2 bf16 terms, 3 bf16 MFMA products, FP32 accumulate/output */
-  LS_BF16X6 = 3   /* operands split into 3 bf16 terms, 6 bf16 MFMA products, FP32 accumulate/output */
+  LS_BF16X6 = 3,  /* operands split into 3 bf16 terms, 6 bf16 MFMA products, FP32 accumulate/output */
+  LS_F16X3 = 4    /* operands scaled per rank by powers of two and split into 2 FP16 terms,
+                     3 FP16 MFMA products, FP32 accumulate/output (reconstruction only; needs
+                     the workspace) */
 } ls_precision;
 
 typedef enum {
@@ -164,16 +167,24 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * C-order; element type double for LS_F64, float otherwise.
  * boxes: host [nbox]. tile: 0 = automatic, otherwise a tile id from
  * ls_reconstruct_tiles (used by the autotuner).
- * ws_dev, ws_bytes: device workspace, caller-owned, used by the split-bf16
+ * ws_dev, ws_bytes: device workspace, caller-owned, used by the split
  * precisions only: tiles 6 and above of LS_BF16X3 / LS_BF16X6 first split f1
  * into bf16 terms there (ls_reconstruct_workspace bytes); tile 0 uses them
  * when the workspace is large enough and the boxes are large (the persistent
  * kernel, one workgroup per resident slot, for boxes of 256 or more values of
- * j), and otherwise tiles that split both operands inside the kernel. NULL / 0
- * is valid for every other precision and tile.
+ * j), and otherwise tiles that split both operands inside the kernel.
+ * LS_F16X3 always needs it (tiles 1 and 2, persistent kernel with 16x16 or
+ * 32x32 MFMA): the per-rank scales 2^(13 - e_r), e_r = floor(log2 max|f1[r]|),
+ * one scale 2^g for the other operand (the largest |coef_r f0 f2| / 2^(13-e_r)
+ * times 2^g is below 2^14, so no FP16 term overflows), and f1 scaled and split
+ * into two FP16 terms are formed there first; the output is multiplied by
+ * 2^-g (results below the FP32 range then flush to zero, as they would in any
+ * FP32 output). NULL / 0 is valid for every other precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
- * LS_EUNSUPPORTED (tile id not valid for the precision), LS_EWORKSPACE
- * (tile 6 or above of a split precision with a missing or short workspace).
+ * LS_EUNSUPPORTED (tile id not valid for the precision; LS_F16X3 with over
+ * 2^31 tiles in a group of boxes or an operand of 2 GB or more), LS_EWORKSPACE
+ * (tile 6 or above of a bf16 split precision, or LS_F16X3, with a missing or
+ * short workspace).
  */
 ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
                          int32_t precision, int32_t tile, void* out_dev, void* ws_dev,
@@ -312,8 +323,9 @@ ls_status ls_probe_copy(const void* src_dev, void* dst_dev, size_t bytes, hipStr
 /* MFMA issue loop: `blocks` workgroups of four waves, each wave issuing
  * iters x 8 (16x16 shapes) or iters x 4 (32x32 shapes) independent MFMAs of
  * the precision's instruction, shape 0: F64 v_mfma_f64_16x16x4f64, F32
- * v_mfma_f32_16x16x4f32, BF16X3/BF16X6 v_mfma_f32_16x16x32_bf16; shape 1: F32
- * v_mfma_f32_32x32x2f32, BF16X3/BF16X6 v_mfma_f32_32x32x16_bf16. Writes one
+ * v_mfma_f32_16x16x4f32, BF16X3/BF16X6 v_mfma_f32_16x16x32_bf16, F16X3
+ * v_mfma_f32_16x16x32_f16; shape 1: F32 v_mfma_f32_32x32x2f32, BF16X3/BF16X6
+ * v_mfma_f32_32x32x16_bf16, F16X3 v_mfma_f32_32x32x16_f16. Writes one
  * float per thread to out_dev[blocks * 256] (device, caller-owned); *flops
  * (host) receives the floating-point operations of the launch. Timing is the
  * caller's. Errors: LS_EINVAL for null pointers, an unknown precision or

@@ -10,10 +10,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblatsum.so")
 
 LS_OK, LS_EINVAL, LS_EHIP, LS_EUNSUPPORTED, LS_EWORKSPACE = 0, -1, -2, -3, -4
-LS_F64, LS_F32, LS_BF16X3, LS_BF16X6 = 0, 1, 2, 3
+LS_F64, LS_F32, LS_BF16X3, LS_BF16X6, LS_F16X3 = 0, 1, 2, 3, 4
 LS_RULE_U, LS_RULE_S = 0, 1
 
-PRECISIONS = {"f64": LS_F64, "f32": LS_F32, "bf16x3": LS_BF16X3, "bf16x6": LS_BF16X6}
+PRECISIONS = {"f64": LS_F64, "f32": LS_F32, "bf16x3": LS_BF16X3, "bf16x6": LS_BF16X6,
+              "f16x3": LS_F16X3}
 
 c_double_p = ctypes.POINTER(ctypes.c_double)
 c_int32_p = ctypes.POINTER(ctypes.c_int32)

@@ -3,7 +3,7 @@
 // hardware-counter readings calibrate the traffic counters of the other
 // kernels, and an MFMA issue loop per precision, whose rate gives the
 // attainable matrix-core throughput at the clock the chip holds under load.
-#include "ls_recon_tile.hpp"
+#include "ls_split_tile.hpp"
 
 namespace ls {
 
@@ -40,6 +40,25 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int iters, float* __restrict
     for (int it = 0; it < iters; ++it)
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, z, acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) r += acc[u][v];
+  } else if constexpr (SHAPE == 1 && P == LS_F16X3) {
+    h8_t x, z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      x[e] = (_Float16)(1.0f + 0.125f * ((lane + e) & 7));
+      z[e] = (_Float16)(0.5f + 0.125f * ((lane * 3 + e) & 7));
+    }
+    f16v_probe_t acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[u][v] = 0.0f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_f16(x, z, acc[u], 0, 0, 0);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -82,6 +101,21 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int iters, float* __restrict
     for (int it = 0; it < iters; ++it)
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, z, acc[u], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r += acc[u][0] + acc[u][1] + acc[u][2] + acc[u][3];
+  } else if constexpr (P == LS_F16X3) {
+    h8_t x, z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      x[e] = (_Float16)(1.0f + 0.125f * ((lane + e) & 7));
+      z[e] = (_Float16)(0.5f + 0.125f * ((lane * 3 + e) & 7));
+    }
+    f4_t acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = f4_t{0, 0, 0, 0};
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(x, z, acc[u], 0, 0, 0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) r += acc[u][0] + acc[u][1] + acc[u][2] + acc[u][3];
   } else {
@@ -153,6 +187,15 @@ extern "C" ls_status ls_probe_mfma(int32_t precision, int32_t shape, int32_t blo
         per = 8 * 2.0 * 16 * 16 * 32;
       } else {
         hipLaunchKernelGGL((k_probe_mfma<LS_BF16X3, 1>), g, b, 0, stream, iters, out_dev);
+        per = 4 * 2.0 * 32 * 32 * 16;
+      }
+      break;
+    case LS_F16X3:
+      if (shape == 0) {
+        hipLaunchKernelGGL((k_probe_mfma<LS_F16X3, 0>), g, b, 0, stream, iters, out_dev);
+        per = 8 * 2.0 * 16 * 16 * 32;
+      } else {
+        hipLaunchKernelGGL((k_probe_mfma<LS_F16X3, 1>), g, b, 0, stream, iters, out_dev);
         per = 4 * 2.0 * 32 * 32 * 16;
       }
       break;

@@ -44,6 +44,8 @@ struct BoxSet {
   long long per_xcd;                          // tiles per XCD range
   const unsigned* P2;                         // pre-split f1 (tiles 6..9 of the split precisions)
   int nch;                                    // rank chunks of 32 in P2
+  const double* coefS;                        // LS_F16X3: coef_r 2^(g - 13 + e_r)
+  const int* gexp;                            // LS_F16X3: g
 };
 
 __device__ __forceinline__ bool locate(const BoxSet& bs, int* b, int* tm, int* tn) {
@@ -129,6 +131,100 @@ __global__ __launch_bounds__(64) void k_presplit(const double* __restrict__ f, i
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
+    uint4* dst = reinterpret_cast<uint4*>(P + (((size_t)t * nch + c) * len + x) * 16);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      dst[s] = make_uint4(pk[t][4 * s], pk[t][4 * s + 1], pk[t][4 * s + 2], pk[t][4 * s + 3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LS_F16X3: per-rank power-of-two scaling and two FP16 terms per operand
+// ---------------------------------------------------------------------------
+// FP16 holds 11 significant bits, so two terms keep 22 bits of an FP32 value
+// (products x0y0 + x0y1 + x1y0, error of order 2^-21 |xy|), but only 5 exponent
+// bits: the operands are scaled first. Rank r of f1 is multiplied by
+// 2^(13 - e_r), e_r = floor(log2 max_x |f1[r][x]|), so its largest term lies in
+// [2^13, 2^14); the scale cancels in every product f1[r][j] Y[r][k] when Y
+// carries 2^-(13 - e_r). One more power of two, 2^g, lifts every Y value as far
+// as the largest allows: g = 13 - floor(log2 B), B = max_r |coef_r| max|f0[r]|
+// max|f2[r]| 2^(e_r - 13), so |Y| < 2^14; the output is multiplied by 2^-g.
+// Both operands then use the FP16 normal range down to 2^-14 (2^-28 below
+// their largest values), and values under 2^-24 of it flush to zero.
+
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// one workgroup per rank: e_r and the rank's bound b_r = |coef_r| max|f0[r]|
+// max|f2[r]| 2^(e_r - 13)
+__global__ __launch_bounds__(256) void k_rank_scales(const double* __restrict__ f0,
+                                                     const double* __restrict__ f1,
+                                                     const double* __restrict__ f2,
+                                                     const double* __restrict__ coef, int len0,
+                                                     int len1, int len2, int* __restrict__ rexp,
+                                                     double* __restrict__ rb) {
+  __shared__ double sh[4];
+  const int r = blockIdx.x;
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  for (int x = threadIdx.x; x < len0; x += 256) m0 = fmax(m0, fabs(f0[(size_t)r * len0 + x]));
+  for (int x = threadIdx.x; x < len1; x += 256) m1 = fmax(m1, fabs(f1[(size_t)r * len1 + x]));
+  for (int x = threadIdx.x; x < len2; x += 256) m2 = fmax(m2, fabs(f2[(size_t)r * len2 + x]));
+  m0 = block_max256(m0, sh);
+  m1 = block_max256(m1, sh);
+  m2 = block_max256(m2, sh);
+  if (threadIdx.x == 0) {
+    const int e = (m1 > 0.0 && isfinite(m1)) ? ilogb(m1) : 0;
+    rexp[r] = e;
+    rb[r] = fabs(coef[r]) * m0 * m2 * ldexp(1.0, e - 13);
+  }
+}
+
+// one workgroup: g from the largest bound, then coefS[r] = coef[r] 2^(g-13+e_r)
+__global__ __launch_bounds__(256) void k_global_scale(const double* __restrict__ coef, int K,
+                                                      const int* __restrict__ rexp,
+                                                      const double* __restrict__ rb,
+                                                      double* __restrict__ coefS,
+                                                      int* __restrict__ gexp) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int r = threadIdx.x; r < K; r += 256) m = fmax(m, rb[r]);
+  m = block_max256(m, sh);
+  const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
+  for (int r = threadIdx.x; r < K; r += 256) coefS[r] = coef[r] * ldexp(1.0, g - 13 + rexp[r]);
+  if (threadIdx.x == 0) *gexp = g;
+}
+
+// as k_presplit<2>, with rank r scaled by 2^(13 - e_r) and FP16 terms
+__global__ __launch_bounds__(64) void k_presplit_f16(const double* __restrict__ f, int K, int len,
+                                                     int nch, const int* __restrict__ rexp,
+                                                     unsigned* __restrict__ P) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (x >= len) return;
+  double v[32];
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    const int r = min(32 * c + q, K - 1);
+    v[q] = f[(size_t)r * len + x];
+  }
+  unsigned pk[2][16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r0 = 32 * c + 2 * q;
+    unsigned u0[2], u1[2];
+    split_f16(r0 < K ? (float)ldexp(v[2 * q], 13 - rexp[min(r0, K - 1)]) : 0.0f, u0);
+    split_f16(r0 + 1 < K ? (float)ldexp(v[2 * q + 1], 13 - rexp[min(r0 + 1, K - 1)]) : 0.0f, u1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
     uint4* dst = reinterpret_cast<uint4*>(P + (((size_t)t * nch + c) * len + x) * 16);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -601,9 +697,13 @@ __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int 
   }
 }
 
-template <int NT, int MF, int YV = 2>
+// FMT = 0: bf16 terms (split_fp32); FMT = 1: LS_F16X3, two FP16 terms of
+// operands pre-scaled by powers of two (the rank factors come from bs.coefS,
+// which carries the scales of both operands; the output is scaled by 2^-g).
+template <int NT, int MF, int YV = 2, int FMT = 0>
 __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
                                                          float* __restrict__ out_all) {
+  static_assert(FMT == 0 || NT == 2, "FP16 operands have two terms");
   constexpr int BM = 256, BN = 64, WM = 64, WN = BN;
   constexpr int BK = SPLIT_BK;
   constexpr int KY = BK * BN / 256;
@@ -636,8 +736,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   const __amdgpu_buffer_rsrc_t pbuf = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<unsigned*>(bs.P2), (short)0, (int)(NT * nch * plane), kBufferFlags);
   const double* __restrict__ A1 = a.A1;
-  const double* __restrict__ coef = a.coef;
-  const float sc = (float)a.scale;
+  const double* __restrict__ coef = FMT ? bs.coefS : a.coef;
+  const float sc = FMT ? (float)(a.scale * ldexp(1.0, -rfl(*bs.gexp))) : (float)a.scale;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave * WM;
@@ -694,6 +794,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   auto pt_al = [&](int ab, const double (&v)[2], const StreamPos& p) {
     alphaS[ab][tid] = (tid < BK && p.c * BK + tid < K) ? v[0] * v[1] : 0.0;
   };
+  auto split_val = [](float x, unsigned (&u)[NT]) {
+    if constexpr (FMT == 1)
+      split_f16(x, u);
+    else
+      split_fp32<NT>(x, u);
+  };
   // No masks here: ranks past K have zero rank factors (and zero pre-split
   // f1), and the columns past e2 (clamped loads, finite values) only feed
   // output columns that are never stored.
@@ -709,8 +815,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
         for (int e = 0; e < 2; ++e) {
           unsigned u0[NT], u1[NT];
           const int kk = 2 * e;
-          split_fp32<NT>((float)(alphaS[ab][kby + 4 * yh + kk] * yv[2 * kk + q]), u0);
-          split_fp32<NT>((float)(alphaS[ab][kby + 4 * yh + kk + 1] * yv[2 * kk + 2 + q]), u1);
+          split_val((float)(alphaS[ab][kby + 4 * yh + kk] * yv[2 * kk + q]), u0);
+          split_val((float)(alphaS[ab][kby + 4 * yh + kk + 1] * yv[2 * kk + 2 + q]), u1);
 #pragma unroll
           for (int t = 0; t < NT; ++t) pk[t][e] = pack_hi(u0[t], u1[t]);
         }
@@ -728,8 +834,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        split_fp32<NT>((float)(alphaS[ab][kby + kk] * yv[kk]), u0);
-        split_fp32<NT>((float)(alphaS[ab][kby + kk + 1] * yv[kk + 1]), u1);
+        split_val((float)(alphaS[ab][kby + kk] * yv[kk]), u0);
+        split_val((float)(alphaS[ab][kby + kk + 1] * yv[kk + 1]), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -826,7 +932,15 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
           for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
-              if constexpr (MF == 16)
+              if constexpr (FMT == 1 && MF == 16)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+              else if constexpr (FMT == 1)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+              else if constexpr (MF == 16)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
                     acc[i][j], 0, 0, 0);
@@ -886,7 +1000,7 @@ static void fill_tiles(BoxSet* bs, int bm, int bn, bool per_i = false) {
 
 // Workgroups of k_recon_stream<NT, MF> resident at once on the current device
 // (occupancy per CU times CUs, cached per device); 0 if the query fails.
-template <int NT, int MF>
+template <int NT, int MF, int YV = 2, int FMT = 0>
 static int stream_slots() {
   static std::atomic<int> cache[64];
   int dev = 0;
@@ -895,7 +1009,7 @@ static int stream_slots() {
   if (v > 0) return v;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(&k_recon_stream<NT, MF>), 256, 0) != hipSuccess ||
+          &per_cu, reinterpret_cast<const void*>(&k_recon_stream<NT, MF, YV, FMT>), 256, 0) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   const int n = per_cu * cus;
@@ -907,22 +1021,27 @@ static int stream_slots() {
 // and one per tile of the XCD's range. Tile numbers and buffer offsets are
 // 32-bit in the kernel; a launch with over 2^31 tiles, or an f2 or pre-split
 // f1 of 2 GB or more, uses the per-tile kernel instead.
-template <int NT, int MF, int YV = 2>
-static void launch_stream(hipStream_t s, BoxSet& bs, float* out) {
+template <int NT, int MF, int YV = 2, int FMT = 0>
+static bool launch_stream(hipStream_t s, BoxSet& bs, float* out) {
   const long long total = bs.tile_start[bs.nbox];
   const BoxArg& a = bs.box[0];
   const long long ybytes = (long long)a.K * a.len2 * 8;
   const long long pbytes = (long long)NT * bs.nch * a.len1 * 64;
   if (total >= (1LL << 31) - (1LL << 20) || ybytes >= (1LL << 31) || pbytes >= (1LL << 31)) {
-    dim3 grid((unsigned)(8 * bs.per_xcd));
-    hipLaunchKernelGGL((k_recon_direct<NT, 64, MF, 0>), grid, dim3(256), 0, s, bs, out);
-    return;
+    if constexpr (FMT == 1) {
+      return false;  // no per-tile FP16 kernel
+    } else {
+      dim3 grid((unsigned)(8 * bs.per_xcd));
+      hipLaunchKernelGGL((k_recon_direct<NT, 64, MF, 0>), grid, dim3(256), 0, s, bs, out);
+      return true;
+    }
   }
-  int slots = stream_slots<NT, MF>();
+  int slots = stream_slots<NT, MF, YV, FMT>();
   if (slots < 8) slots = 8 * 64;
   const long long nbx = std::max(1LL, std::min((long long)(slots / 8), bs.per_xcd));
-  hipLaunchKernelGGL((k_recon_stream<NT, MF, YV>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s, bs,
-                     (int)nbx, out);
+  hipLaunchKernelGGL((k_recon_stream<NT, MF, YV, FMT>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s,
+                     bs, (int)nbx, out);
+  return true;
 }
 
 template <typename T>
@@ -1022,19 +1141,54 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
   return false;
 }
 
+// LS_F16X3: tile 1 = persistent kernel with 16x16 MFMA, 2 = with 32x32; false
+// when the launch exceeds the persistent kernel's 32-bit limits
+static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
+  if (tile != 1 && tile != 2) return false;
+  if (dry) return true;
+  fill_tiles(&bs, 256, 64, true);
+  return tile == 1 ? launch_stream<2, 16, 2, 1>(s, bs, (float*)out)
+                   : launch_stream<2, 32, 2, 1>(s, bs, (float*)out);
+}
+
 // tiles of the split precisions that read f1 pre-split from the workspace
 static bool presplit_tile(int precision, int tile) {
-  return (precision == LS_BF16X3 || precision == LS_BF16X6) && tile >= 6;
+  return ((precision == LS_BF16X3 || precision == LS_BF16X6) && tile >= 6) || precision == LS_F16X3;
+}
+
+static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// LS_F16X3 workspace: pre-split f1 (two FP16 terms) | e_r (int) | b_r (double)
+// | coefS (double) | g (int)
+struct F16Layout {
+  size_t p, rexp, rb, coefS, gexp, total;
+};
+static F16Layout f16_layout(int K, int len1) {
+  F16Layout L;
+  const size_t nch = (size_t)((K + SPLIT_BK - 1) / SPLIT_BK);
+  L.p = 0;
+  L.rexp = align256(2 * nch * (size_t)len1 * 64);
+  L.rb = L.rexp + align256((size_t)K * 4);
+  L.coefS = L.rb + align256((size_t)K * 8);
+  L.gexp = L.coefS + align256((size_t)K * 8);
+  L.total = L.gexp + 256;
+  return L;
 }
 
 static size_t presplit_bytes(int precision, int K, int len1) {
+  if (precision == LS_F16X3) return f16_layout(K, len1).total;
   if (precision != LS_BF16X3 && precision != LS_BF16X6) return 0;
   const size_t nt = precision == LS_BF16X6 ? 3 : 2;
   return nt * (size_t)((K + SPLIT_BK - 1) / SPLIT_BK) * (size_t)len1 * 64;
 }
 
 static int n_tiles(int precision) {
-  return precision == LS_F32 ? 8 : (precision == LS_F64 ? 5 : 16);
+  switch (precision) {
+    case LS_F64: return 5;
+    case LS_F32: return 8;
+    case LS_F16X3: return 2;
+    default: return 16;
+  }
 }
 
 static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
@@ -1043,6 +1197,7 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
     case LS_F32: return launch_fp<float>(tile, s, bs, out, dry);
     case LS_BF16X3: return launch_bf<2>(tile, s, bs, out, dry);
     case LS_BF16X6: return launch_bf<3>(tile, s, bs, out, dry);
+    case LS_F16X3: return launch_f16(tile, s, bs, out, dry);
     default: return false;
   }
 }
@@ -1051,6 +1206,7 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 // K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
 // workspace the persistent stream kernel, 256x64 tiles, 16x16 MFMA).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
+  if (precision == LS_F16X3) return 2;  // 32x32 shape (measured faster at K = 96..768)
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
   const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
   if (split && have_ws && big >= 256) {
@@ -1076,7 +1232,7 @@ static int auto_tile(int precision, long long M, long long Nc, int e1, bool have
 using namespace ls;
 
 extern "C" int32_t ls_reconstruct_tiles(int32_t precision) {
-  if (precision < LS_F64 || precision > LS_BF16X6) return 0;
+  if (precision < LS_F64 || precision > LS_F16X3) return 0;
   return n_tiles(precision);
 }
 
@@ -1094,7 +1250,7 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
   LS_REQUIRE(P->f[0] && P->f[1] && P->f[2] && P->coef, "null factor pointer");
   LS_REQUIRE(nbox >= 1, "nbox must be >= 1");
   LS_REQUIRE(std::isfinite(scale), "scale must be finite");
-  LS_REQUIRE(precision >= LS_F64 && precision <= LS_BF16X6, "unknown precision %d", precision);
+  LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
   if (tile < 0 || tile > n_tiles(precision)) {
     set_error("tile %d not valid for precision %d", tile, precision);
     return LS_EUNSUPPORTED;
@@ -1124,7 +1280,20 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     return LS_EWORKSPACE;
   }
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
-  if (pre) {
+  const F16Layout fl = f16_layout(P->K, P->len[1]);
+  char* wsb = (char*)ws_dev;
+  if (pre && precision == LS_F16X3) {
+    hipLaunchKernelGGL(k_rank_scales, dim3(P->K), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
+                       P->coef, P->len[0], P->len[1], P->len[2], (int*)(wsb + fl.rexp),
+                       (double*)(wsb + fl.rb));
+    hipLaunchKernelGGL(k_global_scale, dim3(1), dim3(256), 0, stream, P->coef, P->K,
+                       (const int*)(wsb + fl.rexp), (const double*)(wsb + fl.rb),
+                       (double*)(wsb + fl.coefS), (int*)(wsb + fl.gexp));
+    hipLaunchKernelGGL(k_presplit_f16, dim3((P->len[1] + 63) / 64, nch), dim3(64), 0, stream,
+                       P->f[1], P->K, P->len[1], nch, (const int*)(wsb + fl.rexp), (unsigned*)ws_dev);
+    ls_status st = launch_status("ls_reconstruct (scales and pre-split)");
+    if (st != LS_OK) return st;
+  } else if (pre) {
     dim3 grid((P->len[1] + 63) / 64, nch);
     if (precision == LS_BF16X6)
       hipLaunchKernelGGL(k_presplit<3>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
@@ -1141,6 +1310,8 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     bs.nbox = (nbox - b0) < kBoxesPerLaunch ? (nbox - b0) : kBoxesPerLaunch;
     bs.P2 = pre ? (const unsigned*)ws_dev : nullptr;
     bs.nch = nch;
+    bs.coefS = precision == LS_F16X3 ? (const double*)(wsb + fl.coefS) : nullptr;
+    bs.gexp = precision == LS_F16X3 ? (const int*)(wsb + fl.gexp) : nullptr;
     long long local = 0;
     for (int i = 0; i < bs.nbox; ++i) {
       const ls_box& bx = boxes[b0 + i];
@@ -1164,7 +1335,10 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
       local += (long long)bx.e[0] * bx.e[1] * bx.e[2];
     }
     char* out = (char*)out_dev + off * (precision == LS_F64 ? 8 : 4);
-    dispatch(precision, t, stream, bs, out, false);
+    if (!dispatch(precision, t, stream, bs, out, false)) {
+      set_error("boxes %d.. exceed the limits of the persistent kernel (2^31 tiles, 2 GB operands)", b0);
+      return LS_EUNSUPPORTED;
+    }
     ls_status st = launch_status("ls_reconstruct");
     if (st != LS_OK) return st;
     off += local;

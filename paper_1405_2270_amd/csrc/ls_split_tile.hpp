@@ -53,6 +53,19 @@ __device__ __forceinline__ int lds_swz(int row) {
   return ((r >> 1) ^ (r >> 3)) & 3;
 }
 
+// FP16 two-term split of an FP32 value (LS_F16X3, operands pre-scaled below
+// 2^14 in magnitude): t0 = x rounded to FP16, t1 = the remainder x - t0 (exact
+// in FP32) rounded to FP16, so |x - t0 - t1| <= 2^-22 |x| for normal terms.
+// Returned in the high halves of 32-bit words, like split_fp32, so that
+// pack_hi applies.
+__device__ __forceinline__ void split_f16(float x, unsigned (&u)[2]) {
+  const _Float16 h0 = (_Float16)x;
+  const _Float16 h1 = (_Float16)(x - (float)h0);
+  u[0] = (unsigned)__builtin_bit_cast(unsigned short, h0) << 16;
+  u[1] = (unsigned)__builtin_bit_cast(unsigned short, h1) << 16;
+}
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ unsigned pack_hi(unsigned even, unsigned odd) {
   return (odd & 0xffff0000u) | (even >> 16);
 }

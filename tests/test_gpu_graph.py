@@ -22,7 +22,7 @@ def _t(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("precision,tile", [("f64", 0), ("f32", 0), ("bf16x6", 0), ("bf16x6", 10), ("bf16x6", 14)])
+@pytest.mark.parametrize("precision,tile", [("f64", 0), ("f32", 0), ("bf16x6", 0), ("bf16x6", 10), ("bf16x6", 14), ("f16x3", 0)])
 def test_graph_replay_matches_eager(L, precision, tile):
     s = small_box(140590, n=32, L=(4, 3, 4), M0=4, nbox=2)
     q = s.quad

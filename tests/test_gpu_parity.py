@@ -6,8 +6,9 @@ Error measures (both stated for every potential/energy check):
             is the scale rounding errors follow when charges cancel.
 Gates: FP64 path 1e-12 (rel_mag, and rel_inf where charges do not cancel;
 factor and master rows 1e-12 of each row's maximum),
-mixed FP32 / split-bf16x6 1e-6 (rel_mag), split-bf16x3 3e-5 (rel_mag, two bf16
-terms carry ~16 bits), forces 1e-5 normwise for the FP32 Grams.
+mixed FP32 / split-bf16x6 / scaled FP16x3 1e-6 (rel_mag), split-bf16x3 3e-5
+(rel_mag, two bf16 terms carry ~16 bits), forces 1e-5 normwise for the FP32
+Grams.
 """
 import numpy as np
 import pytest
@@ -152,11 +153,11 @@ def _errors(got, ref, ref_abs):
     return err / np.max(np.abs(ref)), err / np.max(np.abs(ref_abs))
 
 
-PREC_GATES = {"f64": 1e-12, "f32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5}
+PREC_GATES = {"f64": 1e-12, "f32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5, "f16x3": 1e-6}
 
 
 @pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
-@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3", "f16x3"])
 def test_reconstruct(L, name, maker, precision):
     sysm = maker()
     t, w, qt = _quads(sysm, L)
@@ -320,7 +321,7 @@ def test_config2_sampled(L):
         coef_o = (sysm.Z[:, None] * w[None, :]).ravel()
         ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
         ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
-        for precision in ("f64", "f32", "bf16x6"):
+        for precision in ("f64", "f32", "bf16x6", "f16x3"):
             V = L.reconstruct(F, coef, [b], 1.0 / h3, precision)[0]
             got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
             rel_inf, rel_mag = _errors(got.double().cpu().numpy(), ref, ref_abs)

@@ -9,8 +9,9 @@ both store paths of the stream kernel (tiles inside the box, unmasked; tiles
 cut by the box edge in rows or columns, masked), box offsets that are not a
 multiple of 4 and rows that are not 16-byte aligned, and several boxes per
 launch, so that a workgroup's stream crosses from one box to the next. The
-stream kernel is also checked against the oracle at sampled points of a
-256^3 box and of a box with a cut column tile."""
+stream kernel (BF16x6, and FP16x3 with both MFMA shapes) is also checked
+against the oracle at sampled points of a 256^3 box and of a box with a cut
+column tile."""
 import numpy as np
 import pytest
 import torch
@@ -73,7 +74,8 @@ def test_tiles_agree_bitwise(setup, ref_tile, tiles):
         del got
 
 
-def test_stream_matches_oracle_sampled(setup):
+@pytest.mark.parametrize("precision,tile", [("bf16x6", 14), ("f16x3", 1), ("f16x3", 2)])
+def test_stream_matches_oracle_sampled(setup, precision, tile):
     L, s, F, coef = setup
     q = s.quad
     t, w = rule_s(q["M"], q["C0"], q["s"])
@@ -81,7 +83,7 @@ def test_stream_matches_oracle_sampled(setup):
     h3 = (s.b / s.n) ** 3
     rng = np.random.default_rng(11)
     boxes = _boxes(s)
-    outs = L.reconstruct(F, coef, boxes, 1.0 / h3, "bf16x6", 14)
+    outs = L.reconstruct(F, coef, boxes, 1.0 / h3, precision, tile)
     coef_o = (s.Z[:, None] * w[None, :]).ravel()
     for b, V in zip(boxes[:2], outs[:2]):
         sel_local = [np.sort(rng.choice(b[3 + l], min(5, b[3 + l]), replace=False)) for l in range(3)]
@@ -92,4 +94,4 @@ def test_stream_matches_oracle_sampled(setup):
         ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
         got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
         err = np.max(np.abs(got.double().cpu().numpy() - ref))
-        assert err / np.max(np.abs(ref_abs)) < 1e-6, (b, err)
+        assert err / np.max(np.abs(ref_abs)) < 1e-6, (precision, tile, b, err)
