@@ -1206,7 +1206,7 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 // K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
 // workspace the persistent stream kernel, 256x64 tiles, 16x16 MFMA).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
-  if (precision == LS_F16X3) return 2;  // 32x32 shape (measured faster at K = 96..768)
+  if (precision == LS_F16X3) return 1;  // 16x16 shape (measured faster at K = 384, 768)
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
   const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
   if (split && have_ws && big >= 256) {

@@ -59,6 +59,10 @@ __device__ __forceinline__ int lds_swz(int row) {
 // Returned in the high halves of 32-bit words, like split_fp32, so that
 // pack_hi applies.
 __device__ __forceinline__ void split_f16(float x, unsigned (&u)[2]) {
+  // keep x an FP32 register value: the compiler would otherwise merge the
+  // caller's double -> float rounding with this float -> FP16 one into a
+  // software double -> FP16 conversion (two dozen instructions per value)
+  asm("" : "+v"(x));
   const _Float16 h0 = (_Float16)x;
   const _Float16 h1 = (_Float16)(x - (float)h0);
   u[0] = (unsigned)__builtin_bit_cast(unsigned short, h0) << 16;
