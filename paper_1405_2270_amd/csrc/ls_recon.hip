@@ -700,7 +700,9 @@ __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int 
 // FMT = 0: bf16 terms (split_fp32); FMT = 1: LS_F16X3, two FP16 terms of
 // operands pre-scaled by powers of two (the rank factors come from bs.coefS,
 // which carries the scales of both operands; the output is scaled by 2^-g).
-template <int NT, int MF, int YV = 2, int FMT = 0>
+// OPT = 1: the rank factors are loaded and written to LDS by wave 0 alone (the
+// other waves issue no load for them: fewer vector-memory instructions).
+template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
                                                          float* __restrict__ out_all) {
   static_assert(FMT == 0 || NT == 2, "FP16 operands have two terms");
@@ -786,13 +788,16 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       }
     }
   };
+  const bool wave0 = __builtin_amdgcn_readfirstlane(wave) == 0;
   auto ld_al = [&](double (&v)[2], const StreamPos& p) {
-    const int r = min(p.c * BK + min(tid, BK - 1), K - 1);
-    v[0] = coef[r];
-    v[1] = A1[(size_t)(p.o0 + p.ib) + (size_t)r * len0];
+    if (!(OPT & 1) || wave0) {
+      const int r = min(p.c * BK + min(tid, BK - 1), K - 1);
+      v[0] = coef[r];
+      v[1] = A1[(size_t)(p.o0 + p.ib) + (size_t)r * len0];
+    }
   };
   auto pt_al = [&](int ab, const double (&v)[2], const StreamPos& p) {
-    alphaS[ab][tid] = (tid < BK && p.c * BK + tid < K) ? v[0] * v[1] : 0.0;
+    if (!(OPT & 1) || wave0) alphaS[ab][tid] = (tid < BK && p.c * BK + tid < K) ? v[0] * v[1] : 0.0;
   };
   auto split_val = [](float x, unsigned (&u)[NT]) {
     if constexpr (FMT == 1)
@@ -1021,7 +1026,7 @@ static int stream_slots() {
 // and one per tile of the XCD's range. Tile numbers and buffer offsets are
 // 32-bit in the kernel; a launch with over 2^31 tiles, or an f2 or pre-split
 // f1 of 2 GB or more, uses the per-tile kernel instead.
-template <int NT, int MF, int YV = 2, int FMT = 0>
+template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 static bool launch_stream(hipStream_t s, BoxSet& bs, float* out) {
   const long long total = bs.tile_start[bs.nbox];
   const BoxArg& a = bs.box[0];
@@ -1039,7 +1044,7 @@ static bool launch_stream(hipStream_t s, BoxSet& bs, float* out) {
   int slots = stream_slots<NT, MF, YV, FMT>();
   if (slots < 8) slots = 8 * 64;
   const long long nbx = std::max(1LL, std::min((long long)(slots / 8), bs.per_xcd));
-  hipLaunchKernelGGL((k_recon_stream<NT, MF, YV, FMT>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_recon_stream<NT, MF, YV, FMT, OPT>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s,
                      bs, (int)nbx, out);
   return true;
 }
@@ -1141,14 +1146,19 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
   return false;
 }
 
-// LS_F16X3: tile 1 = persistent kernel with 16x16 MFMA, 2 = with 32x32; false
+// LS_F16X3: tile 1 = persistent kernel with 16x16 MFMA, 2 = with 32x32 (both
+// with the rank factors from wave 0), 3 = 16x16 with every wave loading them
+// (the same results bit for bit); false
 // when the launch exceeds the persistent kernel's 32-bit limits
 static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
-  if (tile != 1 && tile != 2) return false;
+  if (tile < 1 || tile > 3) return false;
   if (dry) return true;
   fill_tiles(&bs, 256, 64, true);
-  return tile == 1 ? launch_stream<2, 16, 2, 1>(s, bs, (float*)out)
-                   : launch_stream<2, 32, 2, 1>(s, bs, (float*)out);
+  switch (tile) {
+    case 1: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
+    case 2: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
+    default: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);
+  }
 }
 
 // tiles of the split precisions that read f1 pre-split from the workspace
@@ -1186,7 +1196,7 @@ static int n_tiles(int precision) {
   switch (precision) {
     case LS_F64: return 5;
     case LS_F32: return 8;
-    case LS_F16X3: return 2;
+    case LS_F16X3: return 3;
     default: return 16;
   }
 }

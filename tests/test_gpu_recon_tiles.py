@@ -53,15 +53,16 @@ def _boxes(s):
     ]
 
 
-@pytest.mark.parametrize("ref_tile,tiles", [(10, (12, 14, 16)), (11, (13, 15))])
-def test_tiles_agree_bitwise(setup, ref_tile, tiles):
+@pytest.mark.parametrize("precision,ref_tile,tiles", [("bf16x6", 10, (12, 14, 16)), ("bf16x6", 11, (13, 15)),
+                                                       ("f16x3", 1, (3,))])
+def test_tiles_agree_bitwise(setup, precision, ref_tile, tiles):
     L, s, F, coef = setup
     boxes = _boxes(s)
     scale = 1.0 / (s.b / (s.n)) ** 3
-    ref = L.reconstruct(F, coef, boxes, scale, "bf16x6", ref_tile)
+    ref = L.reconstruct(F, coef, boxes, scale, precision, ref_tile)
     torch.cuda.synchronize()
     for tile in tiles:
-        got = L.reconstruct(F, coef, boxes, scale, "bf16x6", tile)
+        got = L.reconstruct(F, coef, boxes, scale, precision, tile)
         torch.cuda.synchronize()
         for b, (x, y) in enumerate(zip(got, ref)):
             assert x.shape == y.shape
@@ -70,7 +71,7 @@ def test_tiles_agree_bitwise(setup, ref_tile, tiles):
                 d = (x - y).abs()
                 print("tile", tile, "box", boxes[b], "max diff", float(d.max()),
                       "at", np.unravel_index(int(d.argmax()), tuple(x.shape)))
-            assert same, (tile, boxes[b])
+            assert same, (precision, tile, boxes[b])
         del got
 
 
