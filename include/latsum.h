@@ -179,7 +179,10 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * times 2^g is below 2^14, so no FP16 term overflows), and f1 scaled and split
  * into two FP16 terms are formed there first; the output is multiplied by
  * 2^-g (results below the FP32 range then flush to zero, as they would in any
- * FP32 output). NULL / 0 is valid for every other precision and tile.
+ * FP32 output). The rank factors coef_r f0 2^(g - 13 + e_r) are formed in
+ * FP64, so factor rows whose largest entries differ by more than about 10^290
+ * between the axes of one rank are outside its range. NULL / 0 is valid for
+ * every other precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
  * LS_EUNSUPPORTED (tile id not valid for the precision; LS_F16X3 with over
  * 2^31 tiles in a group of boxes or an operand of 2 GB or more), LS_EWORKSPACE
