@@ -173,11 +173,13 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * when the workspace is large enough and the boxes are large (the persistent
  * kernel, one workgroup per resident slot, for boxes of 256 or more values of
  * j), and otherwise tiles that split both operands inside the kernel.
- * LS_F16X3 always needs it (tiles 1..3, persistent kernel with 16x16 or
- * 32x32 MFMA): the per-rank scales 2^(13 - e_r), e_r = floor(log2 max|f1[r]|),
- * one scale 2^g for the other operand (the largest |coef_r f0 f2| / 2^(13-e_r)
- * times 2^g is below 2^14, so no FP16 term overflows), and f1 scaled and split
- * into two FP16 terms are formed there first; the output is multiplied by
+ * LS_F16X3 always needs it (tiles 1..6, persistent kernel with 16x16 or
+ * 32x32 MFMA; tiles 1..3 stage f2 from an FP32 copy, 4..6 from FP64): the
+ * per-rank scales 2^(13 - e_r), e_r = floor(log2 max|f1[r]|), one scale 2^g
+ * for the other operand (the largest |coef_r f0 f2| / 2^(13-e_r) times 2^g is
+ * below 2^14, so no FP16 term overflows), f1 scaled and split into two FP16
+ * terms, and f2[r] 2^(-floor(log2 max|f2[r]|)) rounded to FP32 are formed
+ * there first; the output is multiplied by
  * 2^-g (results below the FP32 range then flush to zero, as they would in any
  * FP32 output). The rank factors coef_r f0 2^(g - 13 + e_r) are formed in
  * FP64, so factor rows whose largest entries differ by more than about 10^290
@@ -192,7 +194,7 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
 ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
                          int32_t precision, int32_t tile, void* out_dev, void* ws_dev,
                          size_t ws_bytes, hipStream_t stream);
-/* Workspace bytes of ls_reconstruct for a precision (0 unless split-bf16). */
+/* Workspace bytes of ls_reconstruct for a precision (0 for LS_F64, LS_F32). */
 size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision);
 
 /* Number of reconstruction tile variants for a precision (for autotuning). */

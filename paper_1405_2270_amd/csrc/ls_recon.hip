@@ -23,6 +23,7 @@
 // (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
 // f64 one (checked on gfx950).
 #include <atomic>
+#include <type_traits>
 
 #include "ls_split_tile.hpp"
 
@@ -46,6 +47,8 @@ struct BoxSet {
   int nch;                                    // rank chunks of 32 in P2
   const double* coefS;                        // LS_F16X3: coef_r 2^(g - 13 + e_r)
   const int* gexp;                            // LS_F16X3: g
+  const double* coefS32;                      // LS_F16X3: coefS_r 2^(e2_r)
+  const float* f2f;                           // LS_F16X3: f2 2^(-e2_r) rounded to FP32
 };
 
 __device__ __forceinline__ bool locate(const BoxSet& bs, int* b, int* tm, int* tn) {
@@ -161,14 +164,17 @@ __device__ __forceinline__ double block_max256(double v, double* sh) {
   return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// one workgroup per rank: e_r and the rank's bound b_r = |coef_r| max|f0[r]|
-// max|f2[r]| 2^(e_r - 13)
+// one workgroup per rank: e_r, the rank's bound b_r = |coef_r| max|f0[r]|
+// max|f2[r]| 2^(e_r - 13), and f2[r] rounded to FP32 (the FP16 split of the
+// other operand keeps 22 bits; f2 in FP32 halves the bytes the kernel loads)
 __global__ __launch_bounds__(256) void k_rank_scales(const double* __restrict__ f0,
                                                      const double* __restrict__ f1,
                                                      const double* __restrict__ f2,
                                                      const double* __restrict__ coef, int len0,
                                                      int len1, int len2, int* __restrict__ rexp,
-                                                     double* __restrict__ rb) {
+                                                     int* __restrict__ rexp2,
+                                                     double* __restrict__ rb,
+                                                     float* __restrict__ f2f) {
   __shared__ double sh[4];
   const int r = blockIdx.x;
   double m0 = 0.0, m1 = 0.0, m2 = 0.0;
@@ -178,25 +184,39 @@ __global__ __launch_bounds__(256) void k_rank_scales(const double* __restrict__ 
   m0 = block_max256(m0, sh);
   m1 = block_max256(m1, sh);
   m2 = block_max256(m2, sh);
+  const int e2 = (m2 > 0.0 && isfinite(m2)) ? ilogb(m2) : 0;
+  // the FP16 kernel's copy of f2, each rank scaled into [1, 2) at its largest
+  // entry, so the FP32 rounding loses nothing to the exponent range above
+  // 2^-126 of that entry
+  for (int x = threadIdx.x; x < len2; x += 256)
+    f2f[(size_t)r * len2 + x] = (float)ldexp(f2[(size_t)r * len2 + x], -e2);
   if (threadIdx.x == 0) {
     const int e = (m1 > 0.0 && isfinite(m1)) ? ilogb(m1) : 0;
     rexp[r] = e;
+    rexp2[r] = e2;
     rb[r] = fabs(coef[r]) * m0 * m2 * ldexp(1.0, e - 13);
   }
 }
 
 // one workgroup: g from the largest bound, then coefS[r] = coef[r] 2^(g-13+e_r)
+// and, for the FP32 copy of f2, coefS32[r] = coefS[r] 2^(e2_r)
 __global__ __launch_bounds__(256) void k_global_scale(const double* __restrict__ coef, int K,
                                                       const int* __restrict__ rexp,
+                                                      const int* __restrict__ rexp2,
                                                       const double* __restrict__ rb,
                                                       double* __restrict__ coefS,
+                                                      double* __restrict__ coefS32,
                                                       int* __restrict__ gexp) {
   __shared__ double sh[4];
   double m = 0.0;
   for (int r = threadIdx.x; r < K; r += 256) m = fmax(m, rb[r]);
   m = block_max256(m, sh);
   const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
-  for (int r = threadIdx.x; r < K; r += 256) coefS[r] = coef[r] * ldexp(1.0, g - 13 + rexp[r]);
+  for (int r = threadIdx.x; r < K; r += 256) {
+    const double c = coef[r] * ldexp(1.0, g - 13 + rexp[r]);
+    coefS[r] = c;
+    coefS32[r] = ldexp(c, rexp2[r]);
+  }
   if (threadIdx.x == 0) *gexp = g;
 }
 
@@ -706,6 +726,9 @@ template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
                                                          float* __restrict__ out_all) {
   static_assert(FMT == 0 || NT == 2, "FP16 operands have two terms");
+  static_assert(YV != 3 || FMT == 1, "the FP32 copy of f2 exists for LS_F16X3");
+  // raw f2 values held in registers: FP64, or FP32 with YV = 3
+  typedef typename std::conditional<YV == 3, float, double>::type yt;
   constexpr int BM = 256, BN = 64, WM = 64, WN = BN;
   constexpr int BK = SPLIT_BK;
   constexpr int KY = BK * BN / 256;
@@ -735,10 +758,12 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // per-lane 64-bit address arithmetic (the host keeps both below 2 GB)
   const __amdgpu_buffer_rsrc_t ybuf = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<double*>(a.A3), (short)0, K * len2 * 8, kBufferFlags);
+  const __amdgpu_buffer_rsrc_t y32buf = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(bs.f2f), (short)0, YV == 3 ? K * len2 * 4 : 0, kBufferFlags);
   const __amdgpu_buffer_rsrc_t pbuf = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<unsigned*>(bs.P2), (short)0, (int)(NT * nch * plane), kBufferFlags);
   const double* __restrict__ A1 = a.A1;
-  const double* __restrict__ coef = FMT ? bs.coefS : a.coef;
+  const double* __restrict__ coef = FMT ? (YV == 3 ? bs.coefS32 : bs.coefS) : a.coef;
   const float sc = FMT ? (float)(a.scale * ldexp(1.0, -rfl(*bs.gexp))) : (float)a.scale;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -769,8 +794,21 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // second column past e2, or past the end of f2, is never used). YV = 1:
   // thread t reads column t%64 of ranks 8(t/64) .. +7 (eight 8-byte loads).
   const int yp = tid & 31, yh = (tid >> 5) & 1;
-  auto ld_y = [&](double (&yv)[KY], const StreamPos& p) {
-    if constexpr (YV == 2) {
+  // YV = 3: lane l of wave w reads FP32 columns 4(l%16) .. +3 of ranks
+  // 8w + 2(l/16) and the next (two 16-byte loads) and writes one 32-bit word
+  // (a rank pair) per column and term
+  const int cg = lane & 15, yq = lane >> 4;
+  auto ld_y = [&](yt (&yv)[KY], const StreamPos& p) {
+    if constexpr (YV == 3) {
+      const int cb = (p.o2 + min(p.col0 + 4 * cg, p.e2 - 1)) * 4;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int r = min(p.c * BK + kby + 2 * yq + e, K - 1);
+        const f4_t v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(y32buf, r * len2 * 4 + cb, 0, 0));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yv[4 * e + q] = v[q];
+      }
+    } else if constexpr (YV == 2) {
       const int cb = (p.o2 + min(p.col0 + 2 * yp, p.e2 - 1)) * 8;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -808,7 +846,22 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // No masks here: ranks past K have zero rank factors (and zero pre-split
   // f1), and the columns past e2 (clamped loads, finite values) only feed
   // output columns that are never stored.
-  auto store_y = [&](const double (&yv)[KY], int yb, int ab, const StreamPos& p) {
+  auto store_y = [&](const yt (&yv)[KY], int yb, int ab, const StreamPos& p) {
+    if constexpr (YV == 3) {
+      const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
+      unsigned* Yw = reinterpret_cast<unsigned*>(Ysf[yb]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        unsigned u0[NT], u1[NT];
+        split_val((float)(alphaS[ab][kby + 2 * yq] * (double)yv[q]), u0);
+        split_val((float)(alphaS[ab][kby + 2 * yq + 1] * (double)yv[4 + q]), u1);
+        const int n = 4 * cg + q;
+        const int piece = ((n / MF) * NH + hh) * 64 + lgw * MF + (n % MF);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * 64 + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
+      }
+      return;
+    }
     if constexpr (YV == 2) {
       // half a 16-byte piece (4 ranks) per column and term
       const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
@@ -907,14 +960,15 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   p3 = p2;
   if (S > 3) stream_next(bs, p3, nchunk, nbx);
 
-  double yr[2][KY], al[2][2];
+  yt yr[2][KY];
+  double al[2][2];
   // In step s every wave loads the raw f2 values of step s+2 and the rank
   // factors of step s+3 into one register set, reads Ysf[s & 1] for the
   // MFMAs, loads the left operand of step s+1 as each term's MFMAs finish,
   // writes step s+1 (raw values loaded in step s-1, other set) into
   // Ysf[(s+1) & 1] and the factors of step s+2 into alphaS[s & 1]; both
   // buffers were last read before the barrier that ended step s-1.
-  auto step = [&](int s, const double (&ys)[KY], double (&yl)[KY], const double (&as)[2],
+  auto step = [&](int s, const yt (&ys)[KY], yt (&yl)[KY], const double (&as)[2],
                   double (&aload)[2]) {
     const int yb = s & 1;
     ld_y(yl, p2);
@@ -1005,7 +1059,7 @@ static void fill_tiles(BoxSet* bs, int bm, int bn, bool per_i = false) {
 
 // Workgroups of k_recon_stream<NT, MF> resident at once on the current device
 // (occupancy per CU times CUs, cached per device); 0 if the query fails.
-template <int NT, int MF, int YV = 2, int FMT = 0>
+template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 static int stream_slots() {
   static std::atomic<int> cache[64];
   int dev = 0;
@@ -1014,7 +1068,7 @@ static int stream_slots() {
   if (v > 0) return v;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(&k_recon_stream<NT, MF, YV, FMT>), 256, 0) != hipSuccess ||
+          &per_cu, reinterpret_cast<const void*>(&k_recon_stream<NT, MF, YV, FMT, OPT>), 256, 0) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   const int n = per_cu * cus;
@@ -1041,7 +1095,7 @@ static bool launch_stream(hipStream_t s, BoxSet& bs, float* out) {
       return true;
     }
   }
-  int slots = stream_slots<NT, MF, YV, FMT>();
+  int slots = stream_slots<NT, MF, YV, FMT, OPT>();
   if (slots < 8) slots = 8 * 64;
   const long long nbx = std::max(1LL, std::min((long long)(slots / 8), bs.per_xcd));
   hipLaunchKernelGGL((k_recon_stream<NT, MF, YV, FMT, OPT>), dim3((unsigned)(8 * nbx)), dim3(256), 0, s,
@@ -1146,17 +1200,21 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
   return false;
 }
 
-// LS_F16X3: tile 1 = persistent kernel with 16x16 MFMA, 2 = with 32x32 (both
-// with the rank factors from wave 0), 3 = 16x16 with every wave loading them
-// (the same results bit for bit); false
-// when the launch exceeds the persistent kernel's 32-bit limits
+// LS_F16X3, all on the persistent kernel: tiles 1-3 stage f2 from its FP32
+// copy in the workspace, tiles 4-6 from the FP64 factor itself. Within each
+// group: 16x16 MFMA, 32x32 MFMA (both with the rank factors loaded by wave 0),
+// and 16x16 with every wave loading them (the same results as the first, bit
+// for bit). False when the launch exceeds the persistent kernel's 32-bit limits.
 static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
-  if (tile < 1 || tile > 3) return false;
+  if (tile < 1 || tile > 6) return false;
   if (dry) return true;
   fill_tiles(&bs, 256, 64, true);
   switch (tile) {
-    case 1: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
-    case 2: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
+    case 1: return launch_stream<2, 16, 3, 1, 1>(s, bs, (float*)out);
+    case 2: return launch_stream<2, 32, 3, 1, 1>(s, bs, (float*)out);
+    case 3: return launch_stream<2, 16, 3, 1, 0>(s, bs, (float*)out);
+    case 4: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
+    case 5: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
     default: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);
   }
 }
@@ -1169,11 +1227,12 @@ static bool presplit_tile(int precision, int tile) {
 static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
 // LS_F16X3 workspace: pre-split f1 (two FP16 terms) | e_r (int) | b_r (double)
-// | coefS (double) | g (int)
+// | coefS (double) | g (int) | e2_r (int) | coefS32 (double) | f2 2^(-e2_r)
+// rounded to FP32 (K x len2)
 struct F16Layout {
-  size_t p, rexp, rb, coefS, gexp, total;
+  size_t p, rexp, rb, coefS, gexp, rexp2, coefS32, f2f, total;
 };
-static F16Layout f16_layout(int K, int len1) {
+static F16Layout f16_layout(int K, int len1, int len2) {
   F16Layout L;
   const size_t nch = (size_t)((K + SPLIT_BK - 1) / SPLIT_BK);
   L.p = 0;
@@ -1181,12 +1240,15 @@ static F16Layout f16_layout(int K, int len1) {
   L.rb = L.rexp + align256((size_t)K * 4);
   L.coefS = L.rb + align256((size_t)K * 8);
   L.gexp = L.coefS + align256((size_t)K * 8);
-  L.total = L.gexp + 256;
+  L.rexp2 = L.gexp + 256;
+  L.coefS32 = L.rexp2 + align256((size_t)K * 4);
+  L.f2f = L.coefS32 + align256((size_t)K * 8);
+  L.total = L.f2f + align256((size_t)K * len2 * 4);
   return L;
 }
 
-static size_t presplit_bytes(int precision, int K, int len1) {
-  if (precision == LS_F16X3) return f16_layout(K, len1).total;
+static size_t presplit_bytes(int precision, int K, int len1, int len2) {
+  if (precision == LS_F16X3) return f16_layout(K, len1, len2).total;
   if (precision != LS_BF16X3 && precision != LS_BF16X6) return 0;
   const size_t nt = precision == LS_BF16X6 ? 3 : 2;
   return nt * (size_t)((K + SPLIT_BK - 1) / SPLIT_BK) * (size_t)len1 * 64;
@@ -1196,7 +1258,7 @@ static int n_tiles(int precision) {
   switch (precision) {
     case LS_F64: return 5;
     case LS_F32: return 8;
-    case LS_F16X3: return 3;
+    case LS_F16X3: return 6;
     default: return 16;
   }
 }
@@ -1216,7 +1278,7 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 // K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
 // workspace the persistent stream kernel, 256x64 tiles, 16x16 MFMA).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
-  if (precision == LS_F16X3) return 1;  // 16x16 shape (measured faster at K = 384, 768)
+  if (precision == LS_F16X3) return 1;  // 16x16 shape, FP32 f2 (measured fastest at K = 384, 768)
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
   const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
   if (split && have_ws && big >= 256) {
@@ -1248,7 +1310,7 @@ extern "C" int32_t ls_reconstruct_tiles(int32_t precision) {
 
 extern "C" size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision) {
   if (P == nullptr || P->K < 1 || P->len[1] < 1) return 0;
-  return presplit_bytes(precision, P->K, P->len[1]);
+  return presplit_bytes(precision, P->K, P->len[1], P->len[2]);
 }
 
 extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox,
@@ -1274,7 +1336,7 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     }
     LS_REQUIRE((long long)boxes[b].e[0] * boxes[b].e[1] < (1LL << 31), "box %d too large", b);
   }
-  const size_t need = presplit_bytes(precision, P->K, P->len[1]);
+  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
   const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
   const int t = tile ? tile
                      : auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1],
@@ -1290,15 +1352,16 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     return LS_EWORKSPACE;
   }
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
-  const F16Layout fl = f16_layout(P->K, P->len[1]);
+  const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
   if (pre && precision == LS_F16X3) {
     hipLaunchKernelGGL(k_rank_scales, dim3(P->K), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
                        P->coef, P->len[0], P->len[1], P->len[2], (int*)(wsb + fl.rexp),
-                       (double*)(wsb + fl.rb));
+                       (int*)(wsb + fl.rexp2), (double*)(wsb + fl.rb), (float*)(wsb + fl.f2f));
     hipLaunchKernelGGL(k_global_scale, dim3(1), dim3(256), 0, stream, P->coef, P->K,
-                       (const int*)(wsb + fl.rexp), (const double*)(wsb + fl.rb),
-                       (double*)(wsb + fl.coefS), (int*)(wsb + fl.gexp));
+                       (const int*)(wsb + fl.rexp), (const int*)(wsb + fl.rexp2),
+                       (const double*)(wsb + fl.rb), (double*)(wsb + fl.coefS),
+                       (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
     hipLaunchKernelGGL(k_presplit_f16, dim3((P->len[1] + 63) / 64, nch), dim3(64), 0, stream,
                        P->f[1], P->K, P->len[1], nch, (const int*)(wsb + fl.rexp), (unsigned*)ws_dev);
     ls_status st = launch_status("ls_reconstruct (scales and pre-split)");
@@ -1322,6 +1385,8 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     bs.nch = nch;
     bs.coefS = precision == LS_F16X3 ? (const double*)(wsb + fl.coefS) : nullptr;
     bs.gexp = precision == LS_F16X3 ? (const int*)(wsb + fl.gexp) : nullptr;
+    bs.coefS32 = precision == LS_F16X3 ? (const double*)(wsb + fl.coefS32) : nullptr;
+    bs.f2f = precision == LS_F16X3 ? (const float*)(wsb + fl.f2f) : nullptr;
     long long local = 0;
     for (int i = 0; i < bs.nbox; ++i) {
       const ls_box& bx = boxes[b0 + i];

@@ -386,22 +386,30 @@ def test_config5_forces_sampled(L):
             assert abs(fd - F64[nu, l]) < 1e-5 * np.max(np.abs(F64)), (nu, l, fd, F64[nu, l])
 
 
-def test_f16x3_wide_dynamic_range(L):
+@pytest.mark.parametrize("f2_shift", [0, 50])
+def test_f16x3_wide_dynamic_range(L, f2_shift):
     # random factors whose rank rows span 10^-9 .. 10^9 per axis and
     # coefficients 10^-5 .. 10^5 of both signs (rank products over 10^40 apart,
     # far beyond the FP16 range, results still inside FP32): the per-rank
     # power-of-two scaling must keep every FP16 term finite and the result
     # within the mixed-precision gate of the FP64 path (itself checked
-    # against the oracle above); boxes with ragged edges and one single cell
+    # against the oracle above); boxes with ragged edges and one single cell.
+    # f2_shift = 50 moves the f2 rows of alternate ranks to 10^50 and 10^-50
+    # times their size (outside FP32) and the coefficients by the inverse, so
+    # the tiles that stage f2 from an FP32 copy must scale it per rank too.
     rng = np.random.default_rng(61)
     K, lens = 100, (37, 290, 70)
     F = [torch.as_tensor(rng.random((K, n)) * 10.0 ** rng.uniform(-9, 9, (K, 1)), device=dev)
          for n in lens]
     coef = torch.as_tensor(rng.choice([-1.0, 1.0], K) * 10.0 ** rng.uniform(-5, 5, K), device=dev)
+    if f2_shift:
+        sh = torch.as_tensor(np.where(np.arange(K) % 2 == 0, 10.0, 0.1) ** f2_shift, device=dev)
+        F[2] = F[2] * sh[:, None]
+        coef = coef / sh
     boxes = [(3, 17, 5, 30, 270, 61), (0, 0, 0, 1, 1, 1)]
     ref = L.reconstruct(F, coef, boxes, 1.0, "f64")
     ref_abs = L.reconstruct([f.abs() for f in F], coef.abs(), boxes, 1.0, "f64")
-    for tile in (0, 1, 2, 3):
+    for tile in range(L.reconstruct_tiles("f16x3") + 1):
         got = L.reconstruct(F, coef, boxes, 1.0, "f16x3", tile)
         for b, (g, r, ra) in enumerate(zip(got, ref, ref_abs)):
             assert torch.isfinite(g).all(), (tile, b)

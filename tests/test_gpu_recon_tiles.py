@@ -54,7 +54,7 @@ def _boxes(s):
 
 
 @pytest.mark.parametrize("precision,ref_tile,tiles", [("bf16x6", 10, (12, 14, 16)), ("bf16x6", 11, (13, 15)),
-                                                       ("f16x3", 1, (3,))])
+                                                       ("f16x3", 1, (3,)), ("f16x3", 4, (6,))])
 def test_tiles_agree_bitwise(setup, precision, ref_tile, tiles):
     L, s, F, coef = setup
     boxes = _boxes(s)
@@ -75,7 +75,8 @@ def test_tiles_agree_bitwise(setup, precision, ref_tile, tiles):
         del got
 
 
-@pytest.mark.parametrize("precision,tile", [("bf16x6", 14), ("f16x3", 1), ("f16x3", 2)])
+@pytest.mark.parametrize("precision,tile", [("bf16x6", 14), ("f16x3", 1), ("f16x3", 2), ("f16x3", 4),
+                                            ("f16x3", 5)])
 def test_stream_matches_oracle_sampled(setup, precision, tile):
     L, s, F, coef = setup
     q = s.quad
