@@ -72,7 +72,7 @@ def parse():
     p.add_argument("--precisions", default="f64,f32,bf16x6,bf16x3,f16x3")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-forces", action="store_true")
-    p.add_argument("--cpu-sample-edge", type=int, default=160)
+    p.add_argument("--cpu-sample-edge", type=int, default=208)
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-periodic", action="store_true")
     p.add_argument("--batch-count", type=int, default=512)
