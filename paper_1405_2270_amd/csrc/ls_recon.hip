@@ -164,68 +164,77 @@ __device__ __forceinline__ double block_max256(double v, double* sh) {
   return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// one workgroup per rank: e_r, the rank's bound b_r = |coef_r| max|f0[r]|
-// max|f2[r]| 2^(e_r - 13), and f2[r] rounded to FP32 (the FP16 split of the
-// other operand keeps 22 bits; f2 in FP32 halves the bytes the kernel loads)
-__global__ __launch_bounds__(256) void k_rank_scales(const double* __restrict__ f0,
-                                                     const double* __restrict__ f1,
-                                                     const double* __restrict__ f2,
-                                                     const double* __restrict__ coef, int len0,
-                                                     int len1, int len2, int* __restrict__ rexp,
-                                                     int* __restrict__ rexp2,
-                                                     double* __restrict__ rb,
-                                                     float* __restrict__ f2f) {
+// one workgroup per rank and axis: rmax[axis][r] = max_x |f_axis[r][x]|
+// (four independent loads per thread in flight)
+__global__ __launch_bounds__(256) void k_rank_max(const double* __restrict__ f0,
+                                                  const double* __restrict__ f1,
+                                                  const double* __restrict__ f2, int K, int len0,
+                                                  int len1, int len2, double* __restrict__ rmax) {
   __shared__ double sh[4];
-  const int r = blockIdx.x;
-  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-  for (int x = threadIdx.x; x < len0; x += 256) m0 = fmax(m0, fabs(f0[(size_t)r * len0 + x]));
-  for (int x = threadIdx.x; x < len1; x += 256) m1 = fmax(m1, fabs(f1[(size_t)r * len1 + x]));
-  for (int x = threadIdx.x; x < len2; x += 256) m2 = fmax(m2, fabs(f2[(size_t)r * len2 + x]));
-  m0 = block_max256(m0, sh);
-  m1 = block_max256(m1, sh);
-  m2 = block_max256(m2, sh);
-  const int e2 = (m2 > 0.0 && isfinite(m2)) ? ilogb(m2) : 0;
-  // the FP16 kernel's copy of f2, each rank scaled into [1, 2) at its largest
-  // entry, so the FP32 rounding loses nothing to the exponent range above
-  // 2^-126 of that entry
-  for (int x = threadIdx.x; x < len2; x += 256)
-    f2f[(size_t)r * len2 + x] = (float)ldexp(f2[(size_t)r * len2 + x], -e2);
-  if (threadIdx.x == 0) {
-    const int e = (m1 > 0.0 && isfinite(m1)) ? ilogb(m1) : 0;
-    rexp[r] = e;
-    rexp2[r] = e2;
-    rb[r] = fabs(coef[r]) * m0 * m2 * ldexp(1.0, e - 13);
-  }
+  const int r = blockIdx.x, ax = blockIdx.y;
+  const int len = ax == 0 ? len0 : (ax == 1 ? len1 : len2);
+  const double* __restrict__ row = (ax == 0 ? f0 : (ax == 1 ? f1 : f2)) + (size_t)r * len;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  int x = threadIdx.x;
+  for (; x + 768 < len; x += 1024)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) m[u] = fmax(m[u], fabs(row[x + 256 * u]));
+  for (; x < len; x += 256) m[0] = fmax(m[0], fabs(row[x]));
+  const double v = block_max256(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), sh);
+  if (threadIdx.x == 0) rmax[(size_t)ax * K + r] = v;
 }
 
-// one workgroup: g from the largest bound, then coefS[r] = coef[r] 2^(g-13+e_r)
-// and, for the FP32 copy of f2, coefS32[r] = coefS[r] 2^(e2_r)
-__global__ __launch_bounds__(256) void k_global_scale(const double* __restrict__ coef, int K,
-                                                      const int* __restrict__ rexp,
-                                                      const int* __restrict__ rexp2,
-                                                      const double* __restrict__ rb,
-                                                      double* __restrict__ coefS,
-                                                      double* __restrict__ coefS32,
-                                                      int* __restrict__ gexp) {
-  __shared__ double sh[4];
-  double m = 0.0;
-  for (int r = threadIdx.x; r < K; r += 256) m = fmax(m, rb[r]);
-  m = block_max256(m, sh);
-  const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
-  for (int r = threadIdx.x; r < K; r += 256) {
-    const double c = coef[r] * ldexp(1.0, g - 13 + rexp[r]);
-    coefS[r] = c;
-    coefS32[r] = ldexp(c, rexp2[r]);
-  }
-  if (threadIdx.x == 0) *gexp = g;
-}
+// floor(log2 m) for a row maximum m, 0 for a zero or non-finite row
+__device__ __forceinline__ int row_exp(double m) { return (m > 0.0 && isfinite(m)) ? ilogb(m) : 0; }
 
-// as k_presplit<2>, with rank r scaled by 2^(13 - e_r) and FP16 terms
-__global__ __launch_bounds__(64) void k_presplit_f16(const double* __restrict__ f, int K, int len,
-                                                     int nch, const int* __restrict__ rexp,
-                                                     unsigned* __restrict__ P) {
+// With e_r = row_exp(max|f1[r]|) and e2_r = row_exp(max|f2[r]|) from rmax:
+// blockIdx.y < nch: as k_presplit<2>, with rank r of f1 scaled by
+// 2^(13 - e_r) and FP16 terms; nch <= y < nch + n8: ranks 8 (y - nch) .. +7 of
+// f2 scaled by 2^-e2_r and rounded to FP32 (the FP16 split of the other
+// operand keeps 22 bits; f2 in FP32 halves the bytes the kernel loads for it);
+// y = nch + n8, x = 0 (one wave): g from the largest bound b_r = |coef_r|
+// max|f0[r]| max|f2[r]| 2^(e_r - 13), coefS[r] = coef[r] 2^(g - 13 + e_r) and,
+// for the FP32 copy of f2, coefS32[r] = coefS[r] 2^(e2_r).
+__global__ __launch_bounds__(64) void k_prep_f16(const double* __restrict__ f,
+                                                 const double* __restrict__ f2,
+                                                 const double* __restrict__ coef,
+                                                 const double* __restrict__ rmax, int K, int len,
+                                                 int len2, int nch, int n8,
+                                                 unsigned* __restrict__ P, float* __restrict__ f2f,
+                                                 double* __restrict__ coefS,
+                                                 double* __restrict__ coefS32,
+                                                 int* __restrict__ gexp) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int c = blockIdx.y;
+  const double* __restrict__ m1 = rmax + K;
+  const double* __restrict__ m2 = rmax + 2 * (size_t)K;
+  if (c == nch + n8) {
+    if (blockIdx.x != 0) return;
+    double m = 0.0;
+    for (int r = threadIdx.x; r < K; r += 64)
+      m = fmax(m, fabs(coef[r]) * rmax[r] * m2[r] * ldexp(1.0, row_exp(m1[r]) - 13));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
+    for (int r = threadIdx.x; r < K; r += 64) {
+      const double cs = coef[r] * ldexp(1.0, g - 13 + row_exp(m1[r]));
+      coefS[r] = cs;
+      coefS32[r] = ldexp(cs, row_exp(m2[r]));
+    }
+    if (threadIdx.x == 0) *gexp = g;
+    return;
+  }
+  if (c >= nch) {
+    if (x >= len2) return;
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = f2[(size_t)min(8 * (c - nch) + q, K - 1) * len2 + x];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = 8 * (c - nch) + q;
+      if (r < K) f2f[(size_t)r * len2 + x] = (float)ldexp(v[q], -row_exp(m2[r]));
+    }
+    return;
+  }
   if (x >= len) return;
   double v[32];
 #pragma unroll
@@ -238,8 +247,8 @@ __global__ __launch_bounds__(64) void k_presplit_f16(const double* __restrict__ 
   for (int q = 0; q < 16; ++q) {
     const int r0 = 32 * c + 2 * q;
     unsigned u0[2], u1[2];
-    split_f16(r0 < K ? (float)ldexp(v[2 * q], 13 - rexp[min(r0, K - 1)]) : 0.0f, u0);
-    split_f16(r0 + 1 < K ? (float)ldexp(v[2 * q + 1], 13 - rexp[min(r0 + 1, K - 1)]) : 0.0f, u1);
+    split_f16(r0 < K ? (float)ldexp(v[2 * q], 13 - row_exp(m1[min(r0, K - 1)])) : 0.0f, u0);
+    split_f16(r0 + 1 < K ? (float)ldexp(v[2 * q + 1], 13 - row_exp(m1[min(r0 + 1, K - 1)])) : 0.0f, u1);
 #pragma unroll
     for (int t = 0; t < 2; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
   }
@@ -686,6 +695,7 @@ struct StreamPos {
   long long ooff;  // element offset of the tile's box in the output
 };
 
+template <int BN>
 __device__ __forceinline__ void stream_tile(const BoxSet& bs, int g, StreamPos& p) {
   int i = 0;
   while (i + 1 < bs.nbox && bs.tile_start[i + 1] <= g) ++i;
@@ -698,7 +708,7 @@ __device__ __forceinline__ void stream_tile(const BoxSet& bs, int g, StreamPos& 
   p.g = g;
   p.ib = rfl(ib);
   p.j0 = rfl((tmi - ib * jtn) * 256);
-  p.col0 = rfl((local - tmi * tn) * 64);
+  p.col0 = rfl((local - tmi * tn) * BN);
   p.o0 = rfl(a.o0);
   p.o1 = rfl(a.o1);
   p.o2 = rfl(a.o2);
@@ -708,20 +718,25 @@ __device__ __forceinline__ void stream_tile(const BoxSet& bs, int g, StreamPos& 
 }
 
 // position of the step after p (the caller keeps p at the stream's last step)
+template <int BN>
 __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int nchunk, int nbx) {
   if (p.c + 1 < nchunk) {
     p.c += 1;
   } else {
     p.c = 0;
-    stream_tile(bs, p.g + nbx, p);
+    stream_tile<BN>(bs, p.g + nbx, p);
   }
 }
 
 // FMT = 0: bf16 terms (split_fp32); FMT = 1: LS_F16X3, two FP16 terms of
 // operands pre-scaled by powers of two (the rank factors come from bs.coefS,
 // which carries the scales of both operands; the output is scaled by 2^-g).
-// OPT = 1: the rank factors are loaded and written to LDS by wave 0 alone (the
-// other waves issue no load for them: fewer vector-memory instructions).
+// OPT bit 0: the rank factors are loaded and written to LDS by wave 0 alone
+// (the other waves issue no load for them: fewer vector-memory instructions).
+// OPT bit 2: tiles of 128 columns (FP16x3 with the FP32 copy of f2, 16x16
+// MFMA): each wave computes 64 x 128 outputs, so every f1 fragment it loads
+// serves twice the columns; the f2 fragments are read from LDS per column
+// fragment inside the MFMA loop to bound the live registers.
 template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
                                                          float* __restrict__ out_all) {
@@ -729,7 +744,11 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   static_assert(YV != 3 || FMT == 1, "the FP32 copy of f2 exists for LS_F16X3");
   // raw f2 values held in registers: FP64, or FP32 with YV = 3
   typedef typename std::conditional<YV == 3, float, double>::type yt;
-  constexpr int BM = 256, BN = 64, WM = 64, WN = BN;
+  constexpr int BM = 256, BN = (OPT & 4) ? 128 : 64, WM = 64, WN = BN;
+  // raw f2 values are loaded one step ahead with wide tiles (one register
+  // set; the step's MFMAs cover the latency), two steps ahead otherwise
+  constexpr bool SH = BN == 128;
+  static_assert(BN == 64 || (FMT == 1 && YV == 3), "wide tiles: FP16x3 with the FP32 copy of f2");
   constexpr int BK = SPLIT_BK;
   constexpr int KY = BK * BN / 256;
   constexpr int FM = WM / MF, FN = WN / MF, NH = MF == 16 ? 1 : 2;
@@ -794,19 +813,24 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // second column past e2, or past the end of f2, is never used). YV = 1:
   // thread t reads column t%64 of ranks 8(t/64) .. +7 (eight 8-byte loads).
   const int yp = tid & 31, yh = (tid >> 5) & 1;
-  // YV = 3: lane l of wave w reads FP32 columns 4(l%16) .. +3 of ranks
-  // 8w + 2(l/16) and the next (two 16-byte loads) and writes one 32-bit word
-  // (a rank pair) per column and term
+  // YV = 3: lane l of wave w reads FP32 columns 64 hc + 4(l%16) .. +3 of
+  // ranks 8w + 2(l/16) and the next (two 16-byte loads per 64 columns) and
+  // writes one 32-bit word (a rank pair) per column and term
   const int cg = lane & 15, yq = lane >> 4;
+  const int kw = __builtin_amdgcn_readfirstlane(wave) * 8;
+  constexpr int NHC = BN / 64;
   auto ld_y = [&](yt (&yv)[KY], const StreamPos& p) {
     if constexpr (YV == 3) {
-      const int cb = (p.o2 + min(p.col0 + 4 * cg, p.e2 - 1)) * 4;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int r = min(p.c * BK + kby + 2 * yq + e, K - 1);
-        const f4_t v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(y32buf, r * len2 * 4 + cb, 0, 0));
+      for (int hc = 0; hc < NHC; ++hc) {
+        const int cb = (p.o2 + min(p.col0 + 64 * hc + 4 * cg, p.e2 - 1)) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) yv[4 * e + q] = v[q];
+        for (int e = 0; e < 2; ++e) {
+          const int r = min(p.c * BK + kw + 2 * yq + e, K - 1);
+          const f4_t v = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(y32buf, r * len2 * 4 + cb, 0, 0));
+#pragma unroll
+          for (int q = 0; q < 4; ++q) yv[8 * hc + 4 * e + q] = v[q];
+        }
       }
     } else if constexpr (YV == 2) {
       const int cb = (p.o2 + min(p.col0 + 2 * yp, p.e2 - 1)) * 8;
@@ -851,15 +875,17 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
       unsigned* Yw = reinterpret_cast<unsigned*>(Ysf[yb]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        unsigned u0[NT], u1[NT];
-        split_val((float)(alphaS[ab][kby + 2 * yq] * (double)yv[q]), u0);
-        split_val((float)(alphaS[ab][kby + 2 * yq + 1] * (double)yv[4 + q]), u1);
-        const int n = 4 * cg + q;
-        const int piece = ((n / MF) * NH + hh) * 64 + lgw * MF + (n % MF);
+      for (int hc = 0; hc < NHC; ++hc)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * 64 + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
-      }
+        for (int q = 0; q < 4; ++q) {
+          unsigned u0[NT], u1[NT];
+          split_val((float)(alphaS[ab][kw + 2 * yq] * (double)yv[8 * hc + q]), u0);
+          split_val((float)(alphaS[ab][kw + 2 * yq + 1] * (double)yv[8 * hc + 4 + q]), u1);
+          const int n = 64 * hc + 4 * cg + q;
+          const int piece = ((n / MF) * NH + hh) * 64 + lgw * MF + (n % MF);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * 64 + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
+        }
       return;
     }
     if constexpr (YV == 2) {
@@ -952,13 +978,13 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // p[0..3]: positions of steps s .. s+3 (clamped to the last step S-1)
   StreamPos p0, p1, p2, p3;
   p0.c = 0;
-  stream_tile(bs, xcd * per + l, p0);
+  stream_tile<BN>(bs, xcd * per + l, p0);
   p1 = p0;
-  if (S > 1) stream_next(bs, p1, nchunk, nbx);
+  if (S > 1) stream_next<BN>(bs, p1, nchunk, nbx);
   p2 = p1;
-  if (S > 2) stream_next(bs, p2, nchunk, nbx);
+  if (S > 2) stream_next<BN>(bs, p2, nchunk, nbx);
   p3 = p2;
-  if (S > 3) stream_next(bs, p3, nchunk, nbx);
+  if (S > 3) stream_next<BN>(bs, p3, nchunk, nbx);
 
   yt yr[2][KY];
   double al[2][2];
@@ -967,57 +993,98 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // MFMAs, loads the left operand of step s+1 as each term's MFMAs finish,
   // writes step s+1 (raw values loaded in step s-1, other set) into
   // Ysf[(s+1) & 1] and the factors of step s+2 into alphaS[s & 1]; both
-  // buffers were last read before the barrier that ended step s-1.
+  // buffers were last read before the barrier that ended step s-1. With wide
+  // tiles the raw f2 values loaded in step s are those of step s+1, written
+  // at its end.
   auto step = [&](int s, const yt (&ys)[KY], yt (&yl)[KY], const double (&as)[2],
                   double (&aload)[2]) {
     const int yb = s & 1;
-    ld_y(yl, p2);
+    if constexpr (SH)
+      ld_y(yl, p1);
+    else
+      ld_y(yl, p2);
     ld_al(aload, p3);
-    s8_t bv[NT][FN][NH];
+    if constexpr (BN == 128) {
+      // per column fragment: its f2 terms from LDS, then every product with
+      // it (the products of each accumulator in the same order as below)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+      for (int ta = NT - 1; ta >= 0; --ta) {
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
+        for (int j = 0; j < FN; ++j) {
+          s8_t bj[NT][NH];
 #pragma unroll
-        for (int h = 0; h < NH; ++h)
-          bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
+          for (int tb = NT - 1 - ta; tb >= 0; --tb)
 #pragma unroll
-    for (int ta = NT - 1; ta >= 0; --ta) {
+            for (int h = 0; h < NH; ++h)
+              bj[tb][h] = __builtin_bit_cast(s8_t, Ysf[yb][((tb * FN + j) * NH + h) * 64 + lane]);
 #pragma unroll
-      for (int tb = NT - 1 - ta; tb >= 0; --tb)
+          for (int tb = NT - 1 - ta; tb >= 0; --tb)
 #pragma unroll
-        for (int h = 0; h < NH; ++h)
+            for (int h = 0; h < NH; ++h)
 #pragma unroll
-          for (int i = 0; i < FM; ++i)
+              for (int i = 0; i < FM; ++i) {
+                if constexpr (MF == 16)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8_t, av[ta][i][h]),
+                                                                     __builtin_bit_cast(h8_t, bj[tb][h]),
+                                                                     acc[i][j], 0, 0, 0);
+                else
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8_t, av[ta][i][h]),
+                                                                     __builtin_bit_cast(h8_t, bj[tb][h]),
+                                                                     acc[i][j], 0, 0, 0);
+              }
+        }
+        load_a(ta, p1);
+      }
+    } else {
+      s8_t bv[NT][FN][NH];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) {
-              if constexpr (FMT == 1 && MF == 16)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                    __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
-                    acc[i][j], 0, 0, 0);
-              else if constexpr (FMT == 1)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                    __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
-                    acc[i][j], 0, 0, 0);
-              else if constexpr (MF == 16)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
-                    acc[i][j], 0, 0, 0);
-              else
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
-                    acc[i][j], 0, 0, 0);
-            }
-      load_a(ta, p1);
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+            bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
+#pragma unroll
+      for (int ta = NT - 1; ta >= 0; --ta) {
+#pragma unroll
+        for (int tb = NT - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+              for (int j = 0; j < FN; ++j) {
+                if constexpr (FMT == 1 && MF == 16)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                      __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+                else if constexpr (FMT == 1)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                      __builtin_bit_cast(h8_t, av[ta][i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+                else if constexpr (MF == 16)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+                else
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                      __builtin_bit_cast(bf8_t, av[ta][i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
+                      acc[i][j], 0, 0, 0);
+              }
+        load_a(ta, p1);
+      }
     }
-    store_y(ys, yb ^ 1, yb ^ 1, p1);
+    if constexpr (SH)
+      store_y(yl, yb ^ 1, yb ^ 1, p1);
+    else
+      store_y(ys, yb ^ 1, yb ^ 1, p1);
     pt_al(yb, as, p2);
     if (p0.c == nchunk - 1) epilogue(p0);
     __syncthreads();
     p0 = p1;
     p1 = p2;
     p2 = p3;
-    if (s + 4 < S) stream_next(bs, p3, nchunk, nbx);
+    if (s + 4 < S) stream_next<BN>(bs, p3, nchunk, nbx);
   };
 
   ld_al(al[0], p0);
@@ -1029,7 +1096,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   __syncthreads();
   store_y(yr[0], 0, 0, p0);
   pt_al(1, al[1], p1);
-  ld_y(yr[0], p1);
+  if constexpr (!SH) ld_y(yr[0], p1);
   ld_al(al[0], p2);
   __syncthreads();
   // the positions advance inside step: step s sees p0 = step s
@@ -1200,22 +1267,27 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
   return false;
 }
 
-// LS_F16X3, all on the persistent kernel: tiles 1-3 stage f2 from its FP32
-// copy in the workspace, tiles 4-6 from the FP64 factor itself. Within each
-// group: 16x16 MFMA, 32x32 MFMA (both with the rank factors loaded by wave 0),
-// and 16x16 with every wave loading them (the same results as the first, bit
-// for bit). False when the launch exceeds the persistent kernel's 32-bit limits.
+// LS_F16X3, all on the persistent kernel with the rank factors loaded by
+// wave 0 unless stated. f2 from its FP32 copy in the workspace: tile 1 =
+// 16x16 MFMA with 128-column tiles, 2 = 16x16 with 64-column tiles, 3 = 32x32
+// with 64-column tiles, 4 = tile 2 with every wave loading the rank factors.
+// f2 from the FP64 factor: 5 = 16x16, 6 = 32x32, 7 = 16x16 with every wave
+// loading the rank factors (64-column tiles). Tiles 1, 2 and 4 give the same
+// results bit for bit, and so do 5 and 7. False when the launch exceeds the
+// persistent kernel's 32-bit limits.
 static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
-  if (tile < 1 || tile > 6) return false;
+  if (tile < 1 || tile > 8) return false;
   if (dry) return true;
-  fill_tiles(&bs, 256, 64, true);
+  fill_tiles(&bs, 256, (tile == 1 || tile == 8) ? 128 : 64, true);
   switch (tile) {
-    case 1: return launch_stream<2, 16, 3, 1, 1>(s, bs, (float*)out);
-    case 2: return launch_stream<2, 32, 3, 1, 1>(s, bs, (float*)out);
-    case 3: return launch_stream<2, 16, 3, 1, 0>(s, bs, (float*)out);
-    case 4: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
-    case 5: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
-    default: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);
+    case 1: return launch_stream<2, 16, 3, 1, 5>(s, bs, (float*)out);
+    case 2: return launch_stream<2, 16, 3, 1, 1>(s, bs, (float*)out);
+    case 3: return launch_stream<2, 32, 3, 1, 1>(s, bs, (float*)out);
+    case 4: return launch_stream<2, 16, 3, 1, 0>(s, bs, (float*)out);
+    case 5: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
+    case 6: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
+    case 7: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);
+    default: return launch_stream<2, 32, 3, 1, 5>(s, bs, (float*)out);
   }
 }
 
@@ -1226,22 +1298,20 @@ static bool presplit_tile(int precision, int tile) {
 
 static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
-// LS_F16X3 workspace: pre-split f1 (two FP16 terms) | e_r (int) | b_r (double)
-// | coefS (double) | g (int) | e2_r (int) | coefS32 (double) | f2 2^(-e2_r)
-// rounded to FP32 (K x len2)
+// LS_F16X3 workspace: pre-split f1 (two FP16 terms) | row maxima of f0, f1,
+// f2 (3 x K double) | coefS (double) | g (int) | coefS32 (double) | f2
+// 2^(-e2_r) rounded to FP32 (K x len2)
 struct F16Layout {
-  size_t p, rexp, rb, coefS, gexp, rexp2, coefS32, f2f, total;
+  size_t p, rmax, coefS, gexp, coefS32, f2f, total;
 };
 static F16Layout f16_layout(int K, int len1, int len2) {
   F16Layout L;
   const size_t nch = (size_t)((K + SPLIT_BK - 1) / SPLIT_BK);
   L.p = 0;
-  L.rexp = align256(2 * nch * (size_t)len1 * 64);
-  L.rb = L.rexp + align256((size_t)K * 4);
-  L.coefS = L.rb + align256((size_t)K * 8);
+  L.rmax = align256(2 * nch * (size_t)len1 * 64);
+  L.coefS = L.rmax + align256((size_t)K * 24);
   L.gexp = L.coefS + align256((size_t)K * 8);
-  L.rexp2 = L.gexp + 256;
-  L.coefS32 = L.rexp2 + align256((size_t)K * 4);
+  L.coefS32 = L.gexp + 256;
   L.f2f = L.coefS32 + align256((size_t)K * 8);
   L.total = L.f2f + align256((size_t)K * len2 * 4);
   return L;
@@ -1258,7 +1328,7 @@ static int n_tiles(int precision) {
   switch (precision) {
     case LS_F64: return 5;
     case LS_F32: return 8;
-    case LS_F16X3: return 6;
+    case LS_F16X3: return 8;
     default: return 16;
   }
 }
@@ -1278,7 +1348,9 @@ static bool dispatch(int precision, int tile, hipStream_t s, BoxSet& bs, void* o
 // K = 384: FP64 64x64, FP32 128x128 with rank chunk 16, split-bf16 with a
 // workspace the persistent stream kernel, 256x64 tiles, 16x16 MFMA).
 static int auto_tile(int precision, long long M, long long Nc, int e1, bool have_ws) {
-  if (precision == LS_F16X3) return 1;  // 16x16 shape, FP32 f2 (measured fastest at K = 384, 768)
+  // FP16x3: 16x16 shape, FP32 f2, 128-column tiles unless the boxes are
+  // narrower (measured fastest at K = 384, 768 on 256^3 boxes)
+  if (precision == LS_F16X3) return Nc >= 128 ? 1 : 2;
   const long long big = ((M + 127) / 128) * ((Nc + 127) / 128);
   const bool split = precision == LS_BF16X3 || precision == LS_BF16X6;
   if (split && have_ws && big >= 256) {
@@ -1355,15 +1427,13 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
   const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
   if (pre && precision == LS_F16X3) {
-    hipLaunchKernelGGL(k_rank_scales, dim3(P->K), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
-                       P->coef, P->len[0], P->len[1], P->len[2], (int*)(wsb + fl.rexp),
-                       (int*)(wsb + fl.rexp2), (double*)(wsb + fl.rb), (float*)(wsb + fl.f2f));
-    hipLaunchKernelGGL(k_global_scale, dim3(1), dim3(256), 0, stream, P->coef, P->K,
-                       (const int*)(wsb + fl.rexp), (const int*)(wsb + fl.rexp2),
-                       (const double*)(wsb + fl.rb), (double*)(wsb + fl.coefS),
-                       (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
-    hipLaunchKernelGGL(k_presplit_f16, dim3((P->len[1] + 63) / 64, nch), dim3(64), 0, stream,
-                       P->f[1], P->K, P->len[1], nch, (const int*)(wsb + fl.rexp), (unsigned*)ws_dev);
+    hipLaunchKernelGGL(k_rank_max, dim3(P->K, 3), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
+                       P->K, P->len[0], P->len[1], P->len[2], (double*)(wsb + fl.rmax));
+    const int n8 = (P->K + 7) / 8;
+    hipLaunchKernelGGL(k_prep_f16, dim3((std::max(P->len[1], P->len[2]) + 63) / 64, nch + n8 + 1), dim3(64),
+                       0, stream, P->f[1], P->f[2], P->coef, (const double*)(wsb + fl.rmax), P->K,
+                       P->len[1], P->len[2], nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f),
+                       (double*)(wsb + fl.coefS), (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
     ls_status st = launch_status("ls_reconstruct (scales and pre-split)");
     if (st != LS_OK) return st;
   } else if (pre) {

@@ -77,6 +77,6 @@ def test_invalid_host_arguments(lib):
     assert lib.ls_assemble(None, None, 1, None, None, None, 0, 0, None, None, None, None,
                            None) == _lib.LS_EINVAL
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
-    assert lib.ls_reconstruct_tiles(4) == 6 and lib.ls_reconstruct_workspace(None, 4) == 0
+    assert lib.ls_reconstruct_tiles(4) == 8 and lib.ls_reconstruct_workspace(None, 4) == 0
     assert lib.ls_reconstruct_workspace(None, 2) == 0
     assert lib.ls_energy_workspace(10, 8) >= 3 * 10 * 8 * 8

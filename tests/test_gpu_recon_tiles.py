@@ -1,17 +1,21 @@
-"""Split-bf16 reconstruction kernels at full size (lattice of the 4096^3 grid,
-K = 384, 256^3 boxes).
+"""Split-precision reconstruction kernels at full size (lattice of the 4096^3
+grid, K = 384, 256^3 boxes).
 
-The per-tile kernels (16x16 shape: tiles 10 and 12; 32x32 shape: 11 and 13)
-and the persistent stream kernels (14 and 16 with the 16x16 shape, 15 with the
-32x32 one) issue the same MFMAs in the same order for every output element,
-so within a shape their results must agree bit for bit. The boxes cover
-both store paths of the stream kernel (tiles inside the box, unmasked; tiles
-cut by the box edge in rows or columns, masked), box offsets that are not a
-multiple of 4 and rows that are not 16-byte aligned, and several boxes per
-launch, so that a workgroup's stream crosses from one box to the next. The
-stream kernel (BF16x6, and FP16x3 with both MFMA shapes) is also checked
-against the oracle at sampled points of a 256^3 box and of a box with a cut
-column tile."""
+BF16x6: the per-tile kernels (16x16 shape: tiles 10 and 12; 32x32 shape: 11
+and 13) and the persistent stream kernels (14 and 16 with the 16x16 shape, 15
+with the 32x32 one) issue the same MFMAs in the same order for every output
+element, so within a shape their results must agree bit for bit. FP16x3: the
+stream kernel with 128-column tiles (1), with 64-column tiles (2) and with
+every wave loading the rank factors (4) must agree bit for bit, and so must
+the two 16x16 kernels that read f2 in FP64 (5, 7). The boxes cover both store
+paths of the stream kernel (tiles inside the box, unmasked; tiles cut by the
+box edge in rows or columns, masked; columns cut inside a 128-column tile),
+box offsets that are not a multiple of 4 and rows that are not 16-byte
+aligned, and several boxes per launch, so that a workgroup's stream crosses
+from one box to the next. The stream kernels (BF16x6, and FP16x3 with both
+MFMA shapes, both tile widths and both f2 sources) are also checked against
+the oracle at sampled points of a 256^3 box and of a box with a cut column
+tile."""
 import numpy as np
 import pytest
 import torch
@@ -54,7 +58,8 @@ def _boxes(s):
 
 
 @pytest.mark.parametrize("precision,ref_tile,tiles", [("bf16x6", 10, (12, 14, 16)), ("bf16x6", 11, (13, 15)),
-                                                       ("f16x3", 1, (3,)), ("f16x3", 4, (6,))])
+                                                       ("f16x3", 1, (2, 4)), ("f16x3", 3, (8,)),
+                                                       ("f16x3", 5, (7,))])
 def test_tiles_agree_bitwise(setup, precision, ref_tile, tiles):
     L, s, F, coef = setup
     boxes = _boxes(s)
@@ -75,8 +80,8 @@ def test_tiles_agree_bitwise(setup, precision, ref_tile, tiles):
         del got
 
 
-@pytest.mark.parametrize("precision,tile", [("bf16x6", 14), ("f16x3", 1), ("f16x3", 2), ("f16x3", 4),
-                                            ("f16x3", 5)])
+@pytest.mark.parametrize("precision,tile", [("bf16x6", 14), ("f16x3", 1), ("f16x3", 2), ("f16x3", 3),
+                                            ("f16x3", 5), ("f16x3", 6), ("f16x3", 8)])
 def test_stream_matches_oracle_sampled(setup, precision, tile):
     L, s, F, coef = setup
     q = s.quad
