@@ -173,8 +173,8 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
  * when the workspace is large enough and the boxes are large (the persistent
  * kernel, one workgroup per resident slot, for boxes of 256 or more values of
  * j), and otherwise tiles that split both operands inside the kernel.
- * LS_F16X3 always needs it (tiles 1..7, persistent kernel with 16x16 or
- * 32x32 MFMA; tiles 1..4 stage f2 from an FP32 copy, 5..7 from FP64; tile 0
+ * LS_F16X3 always needs it (tiles 1..8, persistent kernel with 16x16 or
+ * 32x32 MFMA; tiles 1..4 and 8 stage f2 from an FP32 copy, 5..7 from FP64; tile 0
  * takes tile 1, 128-column tiles, for boxes of 128 or more values of k,
  * else tile 2): the
  * per-rank scales 2^(13 - e_r), e_r = floor(log2 max|f1[r]|), one scale 2^g

@@ -46,8 +46,9 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // r). Lane l loads four consecutive cells c0 + 4(l/16) + j of its row r0 + l%16
 // and of density row l%16, one 32-byte run per row, and issues one MFMA per j
 // (its k index l/16 then stands for cell c0 + 4(l/16) + j): each factor row is
-// read once from HBM in whole 128-byte lines. The cells are split into
-// kGramChunks chunks; the partial Grams are summed in a fixed order.
+// read once from HBM in whole 128-byte lines (two 16-byte loads per lane when
+// the rows are 16-byte aligned). The cells are split into kGramChunks chunks;
+// the partial Grams are summed in a fixed order.
 constexpr int kGramChunks = 64;
 typedef double gram_d4_t __attribute__((ext_vector_type(4)));
 typedef float gram_f4_t __attribute__((ext_vector_type(4)));
@@ -96,18 +97,29 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ f0
   const double* fr = f + (size_t)(rok ? r0 + row : 0) * N;
   const double* dr = D + (size_t)(sok ? row : 0) * N;
   const double fs = rok ? 1.0 : 0.0, ds = sok ? 1.0 : 0.0;
+  // rows start 16-byte aligned when N is even (c is a multiple of 4)
+  const bool vec = (N & 1) == 0;
   typename G::acc_t acc = {0, 0, 0, 0};
 #pragma unroll 4
   for (int c0 = c_beg; c0 < c_end; c0 += 16) {
     const int c = c0 + 4 * kq;
     double fv[4], dv[4];
-    // unconditional loads at clamped cells (always in range), masked after
+    if (vec && c + 3 < c_end) {
+      const double2 f01 = *reinterpret_cast<const double2*>(fr + c);
+      const double2 f23 = *reinterpret_cast<const double2*>(fr + c + 2);
+      const double2 d01 = *reinterpret_cast<const double2*>(dr + c);
+      const double2 d23 = *reinterpret_cast<const double2*>(dr + c + 2);
+      fv[0] = f01.x * fs; fv[1] = f01.y * fs; fv[2] = f23.x * fs; fv[3] = f23.y * fs;
+      dv[0] = d01.x * ds; dv[1] = d01.y * ds; dv[2] = d23.x * ds; dv[3] = d23.y * ds;
+    } else {
+      // loads at clamped cells (always in range), masked after
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = min(c + j, c_end - 1);
-      const double m = (c + j < c_end) ? 1.0 : 0.0;
-      fv[j] = fr[cc] * (fs * m);
-      dv[j] = dr[cc] * (ds * m);
+      for (int j = 0; j < 4; ++j) {
+        const int cc = min(c + j, c_end - 1);
+        const double m = (c + j < c_end) ? 1.0 : 0.0;
+        fv[j] = fr[cc] * (fs * m);
+        dv[j] = dr[cc] * (ds * m);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc = G::mma((T)dv[j], (T)fv[j], acc);
@@ -121,34 +133,48 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ f0
   }
 }
 
-// G[l][r][s] = sum over the chunks q (ascending) of part[q][l][r][s]
-__global__ __launch_bounds__(256) void k_gram_sum(const double* __restrict__ part, int n,
-                                                   double* __restrict__ G) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+// Workgroup b takes the pairs i = 64 b + t (t < 64) of the n = K * Krho pairs
+// (r, s): wave l sums the kGramChunks partials of G_l[i] in chunk order and
+// stores G; wave 0 then adds the 64 terms coef[r] d[s] G0 G1 G2 (a fixed
+// shuffle tree) into bsum[b].
+__global__ __launch_bounds__(192) void k_energy_terms(const double* __restrict__ part, int n,
+                                                      int Krho, const double* __restrict__ coef,
+                                                      const double* __restrict__ d,
+                                                      double* __restrict__ G,
+                                                      double* __restrict__ bsum) {
+  __shared__ double g[3][64];
+  const int t = threadIdx.x & 63, l = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + t;
   double acc = 0.0;
+  if (i < n) {
+    // all partial loads in flight at once, then added in chunk order
+    double v[kGramChunks];
 #pragma unroll
-  for (int q = 0; q < kGramChunks; ++q) acc += part[(size_t)q * n + i];
-  G[i] = acc;
+    for (int q = 0; q < kGramChunks; ++q) v[q] = part[((size_t)q * 3 + l) * n + i];
+#pragma unroll
+    for (int q = 0; q < kGramChunks; ++q) acc += v[q];
+    G[(size_t)l * n + i] = acc;
+  }
+  g[l][t] = acc;
+  __syncthreads();
+  if (l == 0) {
+    double v = 0.0;
+    if (i < n) {
+      const int r = i / Krho, s = i - r * Krho;
+      v = coef[r] * d[s] * g[0][t] * g[1][t] * g[2][t];
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (t == 0) bsum[blockIdx.x] = v;
+  }
 }
 
-// E = sum_r coef[r] sum_s d[s] G0[r][s] G1[r][s] G2[r][s]
-__global__ __launch_bounds__(256) void k_energy_reduce(const double* __restrict__ G,
-                                                        const double* __restrict__ coef,
-                                                        const double* __restrict__ d, int K,
-                                                        int Krho, double* __restrict__ E) {
-  __shared__ double sh[256];
-  double acc = 0.0;
-  for (int r = threadIdx.x; r < K; r += 256) {
-    double v = 0.0;
-    for (int s = 0; s < Krho; ++s) {
-      const size_t i0 = (size_t)r * Krho + s;
-      v += d[s] * G[i0] * G[(size_t)K * Krho + i0] * G[2 * (size_t)K * Krho + i0];
-    }
-    acc += coef[r] * v;
-  }
-  const double tot = block_sum256(acc, sh);
-  if (threadIdx.x == 0) *E = tot;
+// one wave: E = the workgroup sums of k_energy_terms added in workgroup order
+__global__ __launch_bounds__(64) void k_energy_sum(const double* __restrict__ bsum, int nb,
+                                                   double* __restrict__ E) {
+  if (threadIdx.x != 0) return;
+  double e = 0.0;
+  for (int b = 0; b < nb; ++b) e += bsum[b];
+  *E = e;
 }
 
 // Phi[(l*Krho + s)*W + i + X] = sum_{k in images} D_l[s][i + k n],  i in [-X, X + n - 1)
@@ -304,11 +330,17 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 using namespace ls;
 
-// workspace: G [3][K][Krho] | partial Grams [kGramChunks][3][K][Krho]
-extern "C" size_t ls_energy_workspace(int32_t K, int32_t Krho) {
-  if (K < 1 || Krho < 1) return 0;
+// workspace: G [3][K][Krho] | partial Grams [kGramChunks][3][K][Krho] |
+// per-workgroup sums of k_energy_terms [ceil(K Krho / 64)]
+static size_t energy_bsum_offset(int K, int Krho) {
   return align256((size_t)3 * K * Krho * sizeof(double)) +
          align256((size_t)kGramChunks * 3 * K * Krho * sizeof(double));
+}
+static int energy_blocks(int K, int Krho) { return (int)(((size_t)K * Krho + 63) / 64); }
+
+extern "C" size_t ls_energy_workspace(int32_t K, int32_t Krho) {
+  if (K < 1 || Krho < 1) return 0;
+  return energy_bsum_offset(K, Krho) + align256((size_t)energy_blocks(K, Krho) * sizeof(double));
 }
 
 extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t precision,
@@ -335,6 +367,9 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
   }
   double* G = (double*)ws_dev;
   double* part = (double*)((char*)ws_dev + align256((size_t)3 * P->K * rho->K * sizeof(double)));
+  const size_t boff = energy_bsum_offset(P->K, rho->K);
+  const int nblk = energy_blocks(P->K, rho->K);
+  double* bsum = (double*)((char*)ws_dev + boff);
   const int Nmax = std::max(P->len[0], std::max(P->len[1], P->len[2]));
   const int chunk = ((Nmax + kGramChunks - 1) / kGramChunks + 15) / 16 * 16;
   // chunks past the end of a shorter axis still write their (zero) partials
@@ -349,13 +384,12 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
                        P->len[1], P->len[2], chunk, part);
   ls_status st = launch_status("ls_energy (gram)");
   if (st != LS_OK) return st;
-  const int n = 3 * P->K * rho->K;
-  hipLaunchKernelGGL(k_gram_sum, dim3((n + 255) / 256), dim3(256), 0, stream, part, n, G);
-  st = launch_status("ls_energy (gram sum)");
+  hipLaunchKernelGGL(k_energy_terms, dim3(nblk), dim3(192), 0, stream, part, P->K * rho->K, rho->K,
+                     P->coef, rho->coef, G, bsum);
+  st = launch_status("ls_energy (terms)");
   if (st != LS_OK) return st;
-  hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, stream, G, P->coef, rho->coef, P->K,
-                     rho->K, E_dev);
-  return launch_status("ls_energy (reduce)");
+  hipLaunchKernelGGL(k_energy_sum, dim3(1), dim3(64), 0, stream, bsum, nblk, E_dev);
+  return launch_status("ls_energy (sum)");
 }
 
 // workspace: Phi [3][Krho][W] | Gv [3][K][Krho] | Gd [3][K][Krho] | Eatom [M0]

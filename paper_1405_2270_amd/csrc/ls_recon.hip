@@ -737,6 +737,10 @@ __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int 
 // MFMA): each wave computes 64 x 128 outputs, so every f1 fragment it loads
 // serves twice the columns; the f2 fragments are read from LDS per column
 // fragment inside the MFMA loop to bound the live registers.
+// OPT bit 4 (FP32 f2): each 64-slot fragment of the split f2 in LDS is
+// followed by one unused 16-byte slot, so the 32-bit words one write
+// instruction stores (four columns apart) fall in distinct banks; a fragment
+// is still read as 64 consecutive slots.
 template <int NT, int MF, int YV = 2, int FMT = 0, int OPT = 0>
 __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
                                                          float* __restrict__ out_all) {
@@ -755,7 +759,9 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   typedef SplitMma<MF> Mma;
   // Ysf and alphaS as in k_recon_direct: step m's split f2 values in Ysf[m & 1]
   // (fragment order) and its rank factors in alphaS[m & 1]
-  __shared__ uint4 Ysf[2][NT * FN * NH * 64];
+  constexpr int YP = (OPT & 16) ? 65 : 64;  // LDS slots per f2 fragment
+  static_assert(YP == 64 || YV == 3, "padded fragments with the FP32 copy of f2");
+  __shared__ uint4 Ysf[2][NT * FN * NH * YP];
   __shared__ double alphaS[2][256];
 
   // this workgroup's tiles: first, first + nbx, ... below lim
@@ -882,9 +888,9 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
           split_val((float)(alphaS[ab][kw + 2 * yq] * (double)yv[8 * hc + q]), u0);
           split_val((float)(alphaS[ab][kw + 2 * yq + 1] * (double)yv[8 * hc + 4 + q]), u1);
           const int n = 64 * hc + 4 * cg + q;
-          const int piece = ((n / MF) * NH + hh) * 64 + lgw * MF + (n % MF);
+          const int piece = ((n / MF) * NH + hh) * YP + lgw * MF + (n % MF);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * 64 + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
+          for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * YP + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
         }
       return;
     }
@@ -1016,7 +1022,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
           for (int tb = NT - 1 - ta; tb >= 0; --tb)
 #pragma unroll
             for (int h = 0; h < NH; ++h)
-              bj[tb][h] = __builtin_bit_cast(s8_t, Ysf[yb][((tb * FN + j) * NH + h) * 64 + lane]);
+              bj[tb][h] = __builtin_bit_cast(s8_t, Ysf[yb][((tb * FN + j) * NH + h) * YP + lane]);
 #pragma unroll
           for (int tb = NT - 1 - ta; tb >= 0; --tb)
 #pragma unroll
@@ -1043,7 +1049,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
         for (int j = 0; j < FN; ++j)
 #pragma unroll
           for (int h = 0; h < NH; ++h)
-            bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * 64 + lane]);
+            bv[t][j][h] = __builtin_bit_cast(s8_t, Ysf[yb][((t * FN + j) * NH + h) * YP + lane]);
 #pragma unroll
       for (int ta = NT - 1; ta >= 0; --ta) {
 #pragma unroll
@@ -1269,21 +1275,22 @@ static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
 
 // LS_F16X3, all on the persistent kernel with the rank factors loaded by
 // wave 0 unless stated. f2 from its FP32 copy in the workspace: tile 1 =
-// 16x16 MFMA with 128-column tiles, 2 = 16x16 with 64-column tiles, 3 = 32x32
-// with 64-column tiles, 4 = tile 2 with every wave loading the rank factors.
+// 16x16 MFMA with 128-column tiles, 2 = 16x16 with 64-column tiles (both with
+// padded f2 fragments in LDS), 3 = 32x32 with 64-column tiles, 4 = tile 2
+// with every wave loading the rank factors, 8 = 32x32 with 128-column tiles.
 // f2 from the FP64 factor: 5 = 16x16, 6 = 32x32, 7 = 16x16 with every wave
 // loading the rank factors (64-column tiles). Tiles 1, 2 and 4 give the same
-// results bit for bit, and so do 5 and 7. False when the launch exceeds the
-// persistent kernel's 32-bit limits.
+// results bit for bit, and so do 3 and 8, and 5 and 7. False when the launch
+// exceeds the persistent kernel's 32-bit limits.
 static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
   if (tile < 1 || tile > 8) return false;
   if (dry) return true;
   fill_tiles(&bs, 256, (tile == 1 || tile == 8) ? 128 : 64, true);
   switch (tile) {
-    case 1: return launch_stream<2, 16, 3, 1, 5>(s, bs, (float*)out);
-    case 2: return launch_stream<2, 16, 3, 1, 1>(s, bs, (float*)out);
+    case 1: return launch_stream<2, 16, 3, 1, 21>(s, bs, (float*)out);
+    case 2: return launch_stream<2, 16, 3, 1, 17>(s, bs, (float*)out);
     case 3: return launch_stream<2, 32, 3, 1, 1>(s, bs, (float*)out);
-    case 4: return launch_stream<2, 16, 3, 1, 0>(s, bs, (float*)out);
+    case 4: return launch_stream<2, 16, 3, 1, 16>(s, bs, (float*)out);
     case 5: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
     case 6: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
     case 7: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);

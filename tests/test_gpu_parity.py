@@ -330,6 +330,31 @@ def test_config2_sampled(L):
             torch.cuda.empty_cache()
 
 
+def test_config2_energy_grams_and_repeat(L):
+    # energy at full size (K = 384, N = 4096, 48 workgroups in the final sum):
+    # the Grams left in the workspace and E against a float64 evaluation of
+    # the same definition (eq. scal) from the same factors, and two calls
+    # bitwise equal (the final sum runs in workgroup order)
+    sysm = config2()
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    K, Krho = int(coef.numel()), int(d.numel())
+    ws = torch.empty(L.api.lib().ls_energy_workspace(K, Krho), dtype=torch.uint8, device=dev)
+    E1 = float(L.energy(F, coef, D, d, "f64", ws).cpu())
+    G = ws[:3 * K * Krho * 8].view(torch.float64).view(3, K, Krho).cpu().numpy()
+    E2 = float(L.energy(F, coef, D, d, "f64", ws).cpu())
+    assert E1 == E2
+    Fh = [f.cpu().numpy() for f in F]
+    Dh = [np.asarray(x, np.float64) for x in sysm.density.D]
+    Gr = np.stack([Fh[l] @ Dh[l].T for l in range(3)])
+    assert np.max(np.abs(G - Gr)) <= 1e-12 * np.max(np.abs(Gr))
+    c, dd = coef.cpu().numpy(), np.asarray(sysm.density.d, np.float64)
+    terms = c[:, None] * dd[None, :] * Gr[0] * Gr[1] * Gr[2]
+    assert abs(E1 - terms.sum()) <= 1e-12 * np.abs(terms).sum(), (E1, terms.sum())
+
+
 @pytest.mark.slow
 def test_config3_periodic_sampled(L):
     # periodic workload at full size: factor columns and sampled cell values

@@ -7,7 +7,8 @@ with the 32x32 one) issue the same MFMAs in the same order for every output
 element, so within a shape their results must agree bit for bit. FP16x3: the
 stream kernel with 128-column tiles (1), with 64-column tiles (2) and with
 every wave loading the rank factors (4) must agree bit for bit, and so must
-the two 16x16 kernels that read f2 in FP64 (5, 7). The boxes cover both store
+the 32x32 kernels with 64- and 128-column tiles (3, 8) and the two 16x16
+kernels that read f2 in FP64 (5, 7). The boxes cover both store
 paths of the stream kernel (tiles inside the box, unmasked; tiles cut by the
 box edge in rows or columns, masked; columns cut inside a 128-column tile),
 box offsets that are not a multiple of 4 and rows that are not 16-byte
