@@ -884,13 +884,14 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       for (int hc = 0; hc < NHC; ++hc)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          unsigned u0[NT], u1[NT];
-          split_val((float)(alphaS[ab][kw + 2 * yq] * (double)yv[8 * hc + q]), u0);
-          split_val((float)(alphaS[ab][kw + 2 * yq + 1] * (double)yv[8 * hc + 4 + q]), u1);
+          // the two ranks of this lane's word, split together (packed)
+          unsigned w[NT];
+          split_f16_pair((float)(alphaS[ab][kw + 2 * yq] * (double)yv[8 * hc + q]),
+                         (float)(alphaS[ab][kw + 2 * yq + 1] * (double)yv[8 * hc + 4 + q]), w);
           const int n = 64 * hc + 4 * cg + q;
           const int piece = ((n / MF) * NH + hh) * YP + lgw * MF + (n % MF);
 #pragma unroll
-          for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * YP + piece) * 4 + yq] = pack_hi(u0[t], u1[t]);
+          for (int t = 0; t < NT; ++t) Yw[(t * FN * NH * YP + piece) * 4 + yq] = w[t];
         }
       return;
     }

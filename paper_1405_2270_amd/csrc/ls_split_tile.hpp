@@ -69,6 +69,21 @@ __device__ __forceinline__ void split_f16(float x, unsigned (&u)[2]) {
   u[1] = (unsigned)__builtin_bit_cast(unsigned short, h1) << 16;
 }
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef float fl2_t __attribute__((ext_vector_type(2)));
+
+// split_f16 of two values at once, packed as pack_hi would pack them
+// (w[t] = term t of `even` in the low half, of `odd` in the high half): the
+// same roundings, on the packed FP32 -> FP16 conversion (two values per
+// instruction, no packing step)
+__device__ __forceinline__ void split_f16_pair(float even, float odd, unsigned (&w)[2]) {
+  fl2_t v = {even, odd};
+  asm("" : "+v"(v));  // FP32 register values, as in split_f16
+  const h2_t h0 = __builtin_convertvector(v, h2_t);
+  const h2_t h1 = __builtin_convertvector(v - __builtin_convertvector(h0, fl2_t), h2_t);
+  w[0] = __builtin_bit_cast(unsigned, h0);
+  w[1] = __builtin_bit_cast(unsigned, h1);
+}
 
 __device__ __forceinline__ unsigned pack_hi(unsigned even, unsigned odd) {
   return (odd & 0xffff0000u) | (even >> 16);
