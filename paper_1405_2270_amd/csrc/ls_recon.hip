@@ -880,14 +880,16 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
     if constexpr (YV == 3) {
       const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
       unsigned* Yw = reinterpret_cast<unsigned*>(Ysf[yb]);
+      // the rank factors in FP32 (below 2^14 by the choice of g; one more
+      // rounding of 2^-24 relative, far inside the FP16 terms' 2^-22)
+      const float a0 = (float)alphaS[ab][kw + 2 * yq], a1 = (float)alphaS[ab][kw + 2 * yq + 1];
 #pragma unroll
       for (int hc = 0; hc < NHC; ++hc)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           // the two ranks of this lane's word, split together (packed)
           unsigned w[NT];
-          split_f16_pair((float)(alphaS[ab][kw + 2 * yq] * (double)yv[8 * hc + q]),
-                         (float)(alphaS[ab][kw + 2 * yq + 1] * (double)yv[8 * hc + 4 + q]), w);
+          split_f16_pair(a0 * yv[8 * hc + q], a1 * yv[8 * hc + 4 + q], w);
           const int n = 64 * hc + 4 * cg + q;
           const int piece = ((n / MF) * NH + hh) * YP + lgw * MF + (n % MF);
 #pragma unroll
