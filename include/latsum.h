@@ -196,6 +196,31 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
 ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox, double scale,
                          int32_t precision, int32_t tile, void* out_dev, void* ws_dev,
                          size_t ws_bytes, hipStream_t stream);
+/* The preparation ls_reconstruct makes first in its workspace, as a call of
+ * its own (the same reconstruction of the canonical tensor, Appendix, eq.
+ * CP_form): for LS_F16X3 the row maxima of the factors, the scaled rank
+ * factors, f1 scaled and split into FP16 terms and the scaled FP32 copy of f2;
+ * for LS_BF16X3 / LS_BF16X6 f1 split into bf16 terms (read by the tiles that
+ * use the workspace); nothing for LS_F64 and LS_F32 (returns LS_OK at once).
+ * ws_dev, ws_bytes: device workspace of at least
+ * ls_reconstruct_workspace(P, precision) bytes, caller-owned. Lets a caller
+ * run the preparation beside other work on another stream, or reuse it for
+ * several calls on the same factors. Asynchronous on `stream`.
+ * Errors: LS_EINVAL (null or empty factors, unknown precision), LS_EWORKSPACE
+ * (missing or short workspace).
+ */
+ls_status ls_reconstruct_prepare(const ls_canon* P, int32_t precision, void* ws_dev,
+                                 size_t ws_bytes, hipStream_t stream);
+/* ls_reconstruct without its preparation: ws_dev must hold the preparation of
+ * the same factors (unchanged values) and precision, made by
+ * ls_reconstruct_prepare or by an earlier ls_reconstruct, and complete before
+ * these kernels run (the same stream, or an order the caller sets with
+ * events). Otherwise the values are meaningless (every access still stays
+ * inside the workspace). Arguments, layouts and errors as ls_reconstruct.
+ */
+ls_status ls_reconstruct_prepared(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                  double scale, int32_t precision, int32_t tile, void* out_dev,
+                                  void* ws_dev, size_t ws_bytes, hipStream_t stream);
 /* Workspace bytes of ls_reconstruct for a precision (0 for LS_F64, LS_F32). */
 size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision);
 

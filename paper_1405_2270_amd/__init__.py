@@ -7,11 +7,13 @@ package only marshals torch tensors into its C ABI.
 """
 from .api import (LatticeSpec, QuadTable, quadrature, master_halfwidth, kernel_vectors, assemble,
                   assemble_into,
-                  reconstruct, reconstruct_into, reconstruct_tiles, energy, forces, LatticeEnergy,
+                  reconstruct, reconstruct_into, reconstruct_prepare, reconstruct_tiles, energy, forces,
+                  LatticeEnergy,
                   lattice_energy, Batch, combine, richardson,
                   nuclear_matrix, probe_copy, probe_mfma)
 
 __all__ = ["LatticeSpec", "QuadTable", "quadrature", "master_halfwidth", "kernel_vectors",
-           "assemble", "assemble_into", "reconstruct", "reconstruct_into", "reconstruct_tiles", "energy", "forces",
+           "assemble", "assemble_into", "reconstruct", "reconstruct_into", "reconstruct_prepare",
+           "reconstruct_tiles", "energy", "forces",
            "LatticeEnergy", "lattice_energy", "Batch", "combine", "richardson",
            "nuclear_matrix", "probe_copy", "probe_mfma"]

@@ -69,6 +69,12 @@ _SIGNATURES = {
                                       ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                       ctypes.c_void_p]),
+    "ls_reconstruct_prepared": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                               ctypes.c_void_p]),
+    "ls_reconstruct_prepare": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_size_t, ctypes.c_void_p]),
     "ls_reconstruct_workspace": (ctypes.c_size_t, [ctypes.POINTER(Canon), ctypes.c_int32]),
     "ls_reconstruct_tiles": (ctypes.c_int32, [ctypes.c_int32]),
     "ls_energy_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),

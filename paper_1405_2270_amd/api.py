@@ -164,18 +164,36 @@ def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
     return out
 
 
-def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws=None):
-    """As ``reconstruct`` but into a caller-provided flat tensor."""
+def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws=None,
+                     prepared=False):
+    """As ``reconstruct`` but into a caller-provided flat tensor. ``prepared``:
+    ``ws`` already holds the preparation of these factors for this precision
+    (``reconstruct_prepare``, or an earlier call with the same ``ws``)."""
     boxes = [tuple(int(v) for v in b) for b in boxes]
     prec = _lib.PRECISIONS[precision]
     canon = _canon(F, coef)
+    if prepared and int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec)) > 0 and ws is None:
+        raise ValueError("prepared=True needs the prepared workspace")
     ws, nws = _recon_ws(canon, prec, F[0].device, ws)
     cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
                               for b in boxes])
-    check("ls_reconstruct", lib().ls_reconstruct(ctypes.byref(canon), cb, len(boxes),
-                                                 float(scale), prec, int(tile), _ptr(out),
-                                                 _ptr(ws), nws, _stream()))
+    name = "ls_reconstruct_prepared" if prepared else "ls_reconstruct"
+    check(name, getattr(lib(), name)(ctypes.byref(canon), cb, len(boxes), float(scale), prec,
+                                     int(tile), _ptr(out), _ptr(ws), nws, _stream()))
     return out
+
+
+def reconstruct_prepare(F, coef, precision, ws=None):
+    """The workspace preparation of ``reconstruct`` for these factors and this
+    precision, as a call of its own (enqueued on the current stream). Returns
+    the workspace (allocated when ``ws`` is None or too small; None when the
+    precision needs none)."""
+    prec = _lib.PRECISIONS[precision]
+    canon = _canon(F, coef)
+    ws, nws = _recon_ws(canon, prec, F[0].device, ws)
+    check("ls_reconstruct_prepare", lib().ls_reconstruct_prepare(ctypes.byref(canon), prec, _ptr(ws),
+                                                                 nws, _stream()))
+    return ws
 
 
 def reconstruct_tiles(precision):

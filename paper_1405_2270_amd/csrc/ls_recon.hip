@@ -1395,13 +1395,50 @@ extern "C" size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision)
   return presplit_bytes(precision, P->K, P->len[1], P->len[2]);
 }
 
-extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox,
-                                    double scale, int32_t precision, int32_t tile, void* out_dev,
-                                    void* ws_dev, size_t ws_bytes, hipStream_t stream) {
-  clear_error();
-  LS_REQUIRE(P != nullptr && boxes != nullptr && out_dev != nullptr, "null pointer");
+// What a call with a workspace forms there before its reconstruction
+// kernels: for LS_F16X3 the row maxima, the pre-split f1, the FP32 copy of f2
+// and the scaled rank factors; for the split-bf16 precisions the pre-split f1.
+static ls_status prepare_ws(const ls_canon* P, int precision, void* ws_dev, hipStream_t stream) {
+  const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
+  const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
+  char* wsb = (char*)ws_dev;
+  if (precision == LS_F16X3) {
+    hipLaunchKernelGGL(k_rank_max, dim3(P->K, 3), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
+                       P->K, P->len[0], P->len[1], P->len[2], (double*)(wsb + fl.rmax));
+    const int n8 = (P->K + 7) / 8;
+    hipLaunchKernelGGL(k_prep_f16, dim3((std::max(P->len[1], P->len[2]) + 63) / 64, nch + n8 + 1), dim3(64),
+                       0, stream, P->f[1], P->f[2], P->coef, (const double*)(wsb + fl.rmax), P->K,
+                       P->len[1], P->len[2], nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f),
+                       (double*)(wsb + fl.coefS), (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
+    return launch_status("ls_reconstruct (scales and pre-split)");
+  }
+  dim3 grid((P->len[1] + 63) / 64, nch);
+  if (precision == LS_BF16X6)
+    hipLaunchKernelGGL(k_presplit<3>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
+                       (unsigned*)ws_dev);
+  else
+    hipLaunchKernelGGL(k_presplit<2>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
+                       (unsigned*)ws_dev);
+  return launch_status("ls_reconstruct (pre-split)");
+}
+
+static ls_status check_canon(const ls_canon* P) {
+  LS_REQUIRE(P != nullptr, "null pointer");
   LS_REQUIRE(P->K >= 1, "rank K must be >= 1");
   LS_REQUIRE(P->f[0] && P->f[1] && P->f[2] && P->coef, "null factor pointer");
+  for (int l = 0; l < 3; ++l) LS_REQUIRE(P->len[l] >= 1, "len[%d] must be >= 1", l);
+  return LS_OK;
+}
+
+// ls_reconstruct, or with prepared = true ls_reconstruct_prepared (the
+// workspace already holds the preparation of prepare_ws)
+static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                    double scale, int32_t precision, int32_t tile, void* out_dev,
+                                    void* ws_dev, size_t ws_bytes, hipStream_t stream, bool prepared) {
+  clear_error();
+  ls_status cs = check_canon(P);
+  if (cs != LS_OK) return cs;
+  LS_REQUIRE(boxes != nullptr && out_dev != nullptr, "null pointer");
   LS_REQUIRE(nbox >= 1, "nbox must be >= 1");
   LS_REQUIRE(std::isfinite(scale), "scale must be finite");
   LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
@@ -1411,7 +1448,6 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
   }
   for (int b = 0; b < nbox; ++b) {
     for (int l = 0; l < 3; ++l) {
-      LS_REQUIRE(P->len[l] >= 1, "len[%d] must be >= 1", l);
       LS_REQUIRE(boxes[b].e[l] >= 1 && boxes[b].o[l] >= 0 &&
                      (long long)boxes[b].o[l] + boxes[b].e[l] <= P->len[l],
                  "box %d outside the factors on axis %d", b, l);
@@ -1436,25 +1472,8 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
   const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
-  if (pre && precision == LS_F16X3) {
-    hipLaunchKernelGGL(k_rank_max, dim3(P->K, 3), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
-                       P->K, P->len[0], P->len[1], P->len[2], (double*)(wsb + fl.rmax));
-    const int n8 = (P->K + 7) / 8;
-    hipLaunchKernelGGL(k_prep_f16, dim3((std::max(P->len[1], P->len[2]) + 63) / 64, nch + n8 + 1), dim3(64),
-                       0, stream, P->f[1], P->f[2], P->coef, (const double*)(wsb + fl.rmax), P->K,
-                       P->len[1], P->len[2], nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f),
-                       (double*)(wsb + fl.coefS), (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
-    ls_status st = launch_status("ls_reconstruct (scales and pre-split)");
-    if (st != LS_OK) return st;
-  } else if (pre) {
-    dim3 grid((P->len[1] + 63) / 64, nch);
-    if (precision == LS_BF16X6)
-      hipLaunchKernelGGL(k_presplit<3>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
-                         (unsigned*)ws_dev);
-    else
-      hipLaunchKernelGGL(k_presplit<2>, grid, dim3(64), 0, stream, P->f[1], P->K, P->len[1], nch,
-                         (unsigned*)ws_dev);
-    ls_status st = launch_status("ls_reconstruct (pre-split)");
+  if (pre && !prepared) {
+    ls_status st = prepare_ws(P, precision, ws_dev, stream);
     if (st != LS_OK) return st;
   }
   long long off = 0;  // elements
@@ -1499,4 +1518,34 @@ extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int3
     off += local;
   }
   return LS_OK;
+}
+
+extern "C" ls_status ls_reconstruct(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                    double scale, int32_t precision, int32_t tile, void* out_dev,
+                                    void* ws_dev, size_t ws_bytes, hipStream_t stream) {
+  return reconstruct_common(P, boxes, nbox, scale, precision, tile, out_dev, ws_dev, ws_bytes,
+                            stream, false);
+}
+
+extern "C" ls_status ls_reconstruct_prepared(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                             double scale, int32_t precision, int32_t tile,
+                                             void* out_dev, void* ws_dev, size_t ws_bytes,
+                                             hipStream_t stream) {
+  return reconstruct_common(P, boxes, nbox, scale, precision, tile, out_dev, ws_dev, ws_bytes,
+                            stream, true);
+}
+
+extern "C" ls_status ls_reconstruct_prepare(const ls_canon* P, int32_t precision, void* ws_dev,
+                                            size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  ls_status cs = check_canon(P);
+  if (cs != LS_OK) return cs;
+  LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
+  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  if (need == 0) return LS_OK;  // FP64 and FP32 use no workspace
+  if (ws_dev == nullptr || ws_bytes < need) {
+    set_error("a workspace of %zu bytes is required", need);
+    return LS_EWORKSPACE;
+  }
+  return prepare_ws(P, precision, ws_dev, stream);
 }

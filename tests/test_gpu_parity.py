@@ -180,6 +180,32 @@ def test_reconstruct(L, name, maker, precision):
                 assert rel_inf < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["f64", "bf16x6", "bf16x3", "f16x3"])
+def test_prepared_matches_reconstruct(L, precision):
+    # the preparation as a call of its own (on another stream, joined by an
+    # event), then two prepared calls on different boxes: bit for bit the
+    # results of ls_reconstruct, every tile of the precision
+    sysm = small_box(131, n=12, L=(5, 4, 6), M0=3)
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    N = [f.shape[1] for f in F]
+    boxes_a = [(0, 0, 0, N[0], N[1], N[2]), (3, 5, 7, 20, 30, 41)]
+    boxes_b = [(1, 2, 3, 17, 9, 65)]
+    for tile in range(L.reconstruct_tiles(precision) + 1):
+        refs = [L.reconstruct(F, coef, bx, 1.0, precision, tile) for bx in (boxes_a, boxes_b)]
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ws = L.reconstruct_prepare(F, coef, precision)
+        torch.cuda.current_stream().wait_stream(side)
+        for bx, ref in zip((boxes_a, boxes_b), refs):
+            n = sum(b[3] * b[4] * b[5] for b in bx)
+            out = torch.empty(n, dtype=ref[0].dtype, device=dev)
+            L.reconstruct_into(F, coef, bx, out, 1.0, precision, tile, ws, prepared=True)
+            torch.cuda.synchronize()
+            assert torch.equal(out, torch.cat([r.reshape(-1) for r in ref])), (precision, tile, bx)
+
+
 @pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_energy(L, name, maker, precision):
