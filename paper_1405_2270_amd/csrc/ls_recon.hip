@@ -730,11 +730,12 @@ __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int 
 
 // FMT = 0: bf16 terms (split_fp32); FMT = 1: LS_F16X3, two FP16 terms of
 // operands pre-scaled by powers of two (the rank factors come from bs.coefS,
-// which carries the scales of both operands; the output is scaled by 2^-g).
+// or bs.coefS32 with the FP32 copy of f2 (YV = 3), which carry the scales of
+// both operands; the output is scaled by 2^-g).
 // OPT bit 0: the rank factors are loaded and written to LDS by wave 0 alone
 // (the other waves issue no load for them: fewer vector-memory instructions).
-// OPT bit 2: tiles of 128 columns (FP16x3 with the FP32 copy of f2, 16x16
-// MFMA): each wave computes 64 x 128 outputs, so every f1 fragment it loads
+// OPT bit 2: tiles of 128 columns (FP16x3 with the FP32 copy of f2): each
+// wave computes 64 x 128 outputs, so every f1 fragment it loads
 // serves twice the columns; the f2 fragments are read from LDS per column
 // fragment inside the MFMA loop to bound the live registers.
 // OPT bit 4 (FP32 f2): each 64-slot fragment of the split f2 in LDS is
