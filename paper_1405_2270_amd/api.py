@@ -172,8 +172,9 @@ def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws
     boxes = [tuple(int(v) for v in b) for b in boxes]
     prec = _lib.PRECISIONS[precision]
     canon = _canon(F, coef)
-    if prepared and int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec)) > 0 and ws is None:
-        raise ValueError("prepared=True needs the prepared workspace")
+    need = int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec))
+    if prepared and need > 0 and (ws is None or ws.numel() < need):
+        raise ValueError("prepared=True needs the prepared workspace (%d bytes)" % need)
     ws, nws = _recon_ws(canon, prec, F[0].device, ws)
     cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
                               for b in boxes])

@@ -10,6 +10,8 @@ mixed FP32 / split-bf16x6 / scaled FP16x3 1e-6 (rel_mag), split-bf16x3 3e-5
 (rel_mag, two bf16 terms carry ~16 bits), forces 1e-5 normwise for the FP32
 Grams.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -295,6 +297,19 @@ def test_invalid_arguments_raise(L):
     with pytest.raises(LatsumError):
         L.assemble(L.LatticeSpec(sysm.b, 8, (2, 2, 2), True), qt, _t(sysm.pos), _t(sysm.Z),
                    torch.zeros(1, dtype=torch.float64, device=dev))
+    # the preparation as a call of its own: a short workspace, and an unknown
+    # precision code, are refused before any launch; FP64 needs none
+    from paper_1405_2270_amd import _lib
+    lib = L.api.lib()
+    canon = L.api._canon(F, coef)
+    short = torch.empty(16, dtype=torch.uint8, device=dev)
+    assert lib.ls_reconstruct_prepare(ctypes.byref(canon), _lib.PRECISIONS["f16x3"],
+                                      ctypes.c_void_p(short.data_ptr()), 16, None) == -4
+    assert lib.ls_reconstruct_prepare(ctypes.byref(canon), 9, None, 0, None) == -1
+    assert lib.ls_reconstruct_prepare(ctypes.byref(canon), _lib.PRECISIONS["f64"], None, 0, None) == 0
+    with pytest.raises(ValueError):
+        L.reconstruct_into(F, coef, [(0, 0, 0, 4, 4, 4)], torch.empty(64, device=dev), 1.0,
+                           "f16x3", 0, short, prepared=True)
 
 
 def test_positions_outside_the_cell_stay_exact(L):
