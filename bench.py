@@ -288,8 +288,8 @@ def main():
         kernels_once()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
