@@ -63,7 +63,7 @@ ls_status launch_status(const char* what);
 //  * nearly flat integrand (tau <= 0.35 and |a| tau <= 0.25, hermite_cell):
 //    expand around the cell centre, exp(-(a+s)^2) = exp(-a^2) exp(-2as - s^2),
 //    whose even part in s has the Hermite series sum_m H_2m(a) s^2m/(2m)!, so
-//    integral = exp(-a^2) * sum_m H_2m(a) c^2m / (2m+1)!   (8 terms);
+//    integral = exp(-a^2) * sum_m H_2m(a) c^2m / (2m+1)!   (up to 8 terms);
 //    this avoids the cancelling difference of two nearly equal erf values.
 //  * otherwise the erfc difference on the tail side (or the erf sum across
 //    the origin); there erfc(far)/erfc(near) <= ~0.6, so nothing cancels.
@@ -77,6 +77,13 @@ __device__ __forceinline__ double hermite_series(double tau, double y0) {
   const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
   const double c = 0.5 * tau;
   const double c2 = c * c;
+  // Terms kept (m < mt): by Indritz's inequality |H_n(x)| <= 1.0865
+  // (2^n n!)^(1/2) e^(x^2/2), term m of exp(-a^2) * sum is at most
+  // 1.0865 2^m c^2m / ((2m)!^(1/2) (2m+1)), and these fall by more than 2c^2
+  // from one m to the next; mt is the first m where that bound is below 1e-17
+  // (of the largest cell of the row, about 1 in these units: c <= 0.175 here).
+  const int mt = c < 8.66e-5 ? 2 : c < 2.45e-3 ? 3 : c < 0.0134 ? 4 : c < 0.0378 ? 5
+               : c < 0.0766 ? 6 : c < 0.1279 ? 7 : 8;
   const double two_a = 2.0 * fabs(a);
   // H_0 = 1, H_1 = 2a, H_{k+1} = 2a H_k - 2k H_{k-1}
   double hkm1 = 1.0, hk = two_a;
@@ -91,6 +98,7 @@ __device__ __forceinline__ double hermite_series(double tau, double y0) {
                               1.0 / 1307674368000.0};
 #pragma unroll
   for (int m = 1; m < 8; ++m) {
+    if (m >= mt) break;
     // advance twice: k = 2m-1 -> 2m
     double h2 = two_a * hk - 2.0 * (2 * m - 1) * hkm1;  // H_{2m}
     double h3 = two_a * h2 - 2.0 * (2 * m) * hk;        // H_{2m+1}
