@@ -39,6 +39,13 @@ __global__ __launch_bounds__(256) void k_masters(const double* __restrict__ pos,
   node_offset(pos[c], b, h, n, &p, &delta);
   const double tau = qa.tau[q];
   const double y0 = (double)(jj - X) - delta;
+  // a wave whose cells all lie beyond the support (exactly 0 in every branch
+  // of the cell integral and its derivative) stores the zeros at once
+  if (__all(fabs(y0) > support_halfwidth(tau))) {
+    if (lane < kMasterCellsPerWave && jj < 2 * X)
+      out[((size_t)c * qa.R + q) * (size_t)(2 * X) + jj] = 0.0;
+    return;
+  }
   double v;
   if (deriv) {
     v = cell_derivative(tau, y0);
