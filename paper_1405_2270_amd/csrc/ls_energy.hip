@@ -97,29 +97,53 @@ __global__ __launch_bounds__(256) void k_gram_mfma(const double* __restrict__ f0
   const double* fr = f + (size_t)(rok ? r0 + row : 0) * N;
   const double* dr = D + (size_t)(sok ? row : 0) * N;
   const double fs = rok ? 1.0 : 0.0, ds = sok ? 1.0 : 0.0;
-  // rows start 16-byte aligned when N is even (c is a multiple of 4)
-  const bool vec = (N & 1) == 0;
   typename G::acc_t acc = {0, 0, 0, 0};
-#pragma unroll 4
-  for (int c0 = c_beg; c0 < c_end; c0 += 16) {
-    const int c = c0 + 4 * kq;
-    double fv[4], dv[4];
-    if (vec && c + 3 < c_end) {
+  int c0 = c_beg;
+  // whole 16-cell steps with 16-byte loads when the rows start 16-byte
+  // aligned (N even; c is a multiple of 4), then the rest with masked loads,
+  // in the same order of cells
+  if ((N & 1) == 0) {
+    // four steps at a time: all sixteen loads issued before the MFMAs
+    for (; c0 + 64 <= c_end; c0 += 64) {
+      double2 fa[4][2], da[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + 16 * u + 4 * kq;
+        fa[u][0] = *reinterpret_cast<const double2*>(fr + c);
+        fa[u][1] = *reinterpret_cast<const double2*>(fr + c + 2);
+        da[u][0] = *reinterpret_cast<const double2*>(dr + c);
+        da[u][1] = *reinterpret_cast<const double2*>(dr + c + 2);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double fv[4] = {fa[u][0].x * fs, fa[u][0].y * fs, fa[u][1].x * fs, fa[u][1].y * fs};
+        const double dv[4] = {da[u][0].x * ds, da[u][0].y * ds, da[u][1].x * ds, da[u][1].y * ds};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = G::mma((T)dv[j], (T)fv[j], acc);
+      }
+    }
+    for (; c0 + 16 <= c_end; c0 += 16) {
+      const int c = c0 + 4 * kq;
       const double2 f01 = *reinterpret_cast<const double2*>(fr + c);
       const double2 f23 = *reinterpret_cast<const double2*>(fr + c + 2);
       const double2 d01 = *reinterpret_cast<const double2*>(dr + c);
       const double2 d23 = *reinterpret_cast<const double2*>(dr + c + 2);
-      fv[0] = f01.x * fs; fv[1] = f01.y * fs; fv[2] = f23.x * fs; fv[3] = f23.y * fs;
-      dv[0] = d01.x * ds; dv[1] = d01.y * ds; dv[2] = d23.x * ds; dv[3] = d23.y * ds;
-    } else {
-      // loads at clamped cells (always in range), masked after
+      const double fv[4] = {f01.x * fs, f01.y * fs, f23.x * fs, f23.y * fs};
+      const double dv[4] = {d01.x * ds, d01.y * ds, d23.x * ds, d23.y * ds};
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int cc = min(c + j, c_end - 1);
-        const double m = (c + j < c_end) ? 1.0 : 0.0;
-        fv[j] = fr[cc] * (fs * m);
-        dv[j] = dr[cc] * (ds * m);
-      }
+      for (int j = 0; j < 4; ++j) acc = G::mma((T)dv[j], (T)fv[j], acc);
+    }
+  }
+  for (; c0 < c_end; c0 += 16) {
+    const int c = c0 + 4 * kq;
+    double fv[4], dv[4];
+    // loads at clamped cells (always in range), masked after
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = min(c + j, c_end - 1);
+      const double m = (c + j < c_end) ? 1.0 : 0.0;
+      fv[j] = fr[cc] * (fs * m);
+      dv[j] = dr[cc] * (ds * m);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc = G::mma((T)dv[j], (T)fv[j], acc);
