@@ -877,7 +877,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   // No masks here: ranks past K have zero rank factors (and zero pre-split
   // f1), and the columns past e2 (clamped loads, finite values) only feed
   // output columns that are never stored.
-  auto store_y = [&](const yt (&yv)[KY], int yb, int ab, const StreamPos& p) {
+  auto store_y = [&](const yt (&yv)[KY], int yb, int ab) {
     if constexpr (YV == 3) {
       const int hh = wave / (64 / MF), lgw = wave % (64 / MF);
       unsigned* Yw = reinterpret_cast<unsigned*>(Ysf[yb]);
@@ -1085,9 +1085,9 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       }
     }
     if constexpr (SH)
-      store_y(yl, yb ^ 1, yb ^ 1, p1);
+      store_y(yl, yb ^ 1, yb ^ 1);
     else
-      store_y(ys, yb ^ 1, yb ^ 1, p1);
+      store_y(ys, yb ^ 1, yb ^ 1);
     pt_al(yb, as, p2);
     if (p0.c == nchunk - 1) epilogue(p0);
     __syncthreads();
@@ -1104,7 +1104,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   pt_al(0, al[0], p0);
   ld_al(al[1], p1);
   __syncthreads();
-  store_y(yr[0], 0, 0, p0);
+  store_y(yr[0], 0, 0);
   pt_al(1, al[1], p1);
   if constexpr (!SH) ld_y(yr[0], p1);
   ld_al(al[0], p2);
