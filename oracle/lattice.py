@@ -15,7 +15,10 @@ at the continuous positions a_nu + b k, which reduces to the paper's
 node-centred windows when a_nu is a grid node. The offset of cell g from image
 k is evaluated as (g - k n) h - (a_nu + b/2), which equals
 (-b/2 + g h) - (a_nu + b k) because b = n h, but does not subtract two
-coordinates of lattice size (that would cost log10(L n) digits far out).
+coordinates of lattice size (that would cost log10(L n) digits far out). The
+cell width is passed as h itself rather than formed as the difference of the
+two rounded edges, which matters where a wide Gaussian is nearly flat across
+the cell (Sec. 2.1: cells of size h).
 
 The canonical rank index is r = nu*R + q (atom-major); coef[r] = Z_nu w_q is kept
 apart from the vectors (reading G4, eq. CP_form).
@@ -86,7 +89,7 @@ def direct_factors(geom, t, w, pos, Z, derivative=False):
             for k in geom.images(l):
                 y0 = (g - k * geom.n) * geom.h - a
                 y1 = (g + 1 - k * geom.n) * geom.h - a
-                acc += cell(t[:, None], y0[None, :], y1[None, :])
+                acc += cell(t[:, None], y0[None, :], y1[None, :], geom.h)
             out[nu * R:(nu + 1) * R] = acc
         F.append(out)
     coef = (np.asarray(Z, np.float64)[:, None] * np.asarray(w, np.float64)[None, :]).ravel()
@@ -116,7 +119,7 @@ def master_vectors(geom, t, delta, X, derivative=False):
     j = np.arange(-X, X, dtype=np.float64)
     cell = gauss_cell_integral_dpos if derivative else gauss_cell_integral
     return cell(np.asarray(t)[:, None], ((j - delta) * geom.h)[None, :],
-                ((j + 1.0 - delta) * geom.h)[None, :])
+                ((j + 1.0 - delta) * geom.h)[None, :], geom.h)
 
 
 def assembled_factors(geom, t, w, pos, Z, derivative=False):
@@ -187,7 +190,7 @@ def factor_entries(geom, t, pos, l, g, derivative=False):
         for k in geom.images(l):
             y0 = (g - k * geom.n) * geom.h - a
             y1 = (g + 1 - k * geom.n) * geom.h - a
-            acc += cell(t[:, None], y0[None, :], y1[None, :])
+            acc += cell(t[:, None], y0[None, :], y1[None, :], geom.h)
         out[nu * t.size:(nu + 1) * t.size] = acc
     return out
 

@@ -32,27 +32,34 @@ _GL_X, _GL_W = np.polynomial.legendre.leggauss(20)
 _COND_MAX = 4.0
 
 
-def _gauss_legendre_cell(t, y0, y1):
-    half = 0.5 * (y1 - y0)
+def _gauss_legendre_cell(t, y0, y1, width):
+    half = 0.5 * width
     mid = 0.5 * (y1 + y0)
     y = mid[..., None] + half[..., None] * _GL_X
     f = np.exp(-(t[..., None] * y) ** 2)
     return half * (f @ _GL_W)
 
 
-def gauss_cell_integral(t, y0, y1):
+def gauss_cell_integral(t, y0, y1, width=None):
     """Integral of exp(-t^2 y^2) over [y0, y1] (eq. galten_int), broadcasting.
 
-    t >= 0 and y0 < y1 are required. FP64 throughout.
+    t >= 0 and y0 < y1 are required. FP64 throughout. ``width``: the cell
+    width y1 - y0 when the caller knows it exactly (the grid's h); far from the
+    charge the difference of the two rounded edges loses log10(|y|/h) digits,
+    which matters where the integrand is nearly flat (the t = 0 and
+    Gauss-Legendre branches).
     """
-    t, y0, y1 = np.broadcast_arrays(np.asarray(t, np.float64),
-                                    np.asarray(y0, np.float64),
-                                    np.asarray(y1, np.float64))
+    if width is None:
+        width = np.asarray(y1, np.float64) - np.asarray(y0, np.float64)
+    t, y0, y1, width = np.broadcast_arrays(np.asarray(t, np.float64),
+                                           np.asarray(y0, np.float64),
+                                           np.asarray(y1, np.float64),
+                                           np.asarray(width, np.float64))
     out = np.empty(t.shape, np.float64)
     zero_t = t == 0.0
-    out[zero_t] = (y1 - y0)[zero_t]
+    out[zero_t] = width[zero_t]
     nz = ~zero_t
-    tt, a0, a1 = t[nz], y0[nz], y1[nz]
+    tt, a0, a1, wd = t[nz], y0[nz], y1[nz], width[nz]
     u0, u1 = tt * a0, tt * a1
     right = u0 >= 0.0
     left = u1 <= 0.0
@@ -73,24 +80,28 @@ def gauss_cell_integral(t, y0, y1):
         cond = np.where(underflow, 1.0, big / diff)
     ill = ~(cond <= _COND_MAX)
     if np.any(ill):
-        val[ill] = _gauss_legendre_cell(tt[ill], a0[ill], a1[ill])
+        val[ill] = _gauss_legendre_cell(tt[ill], a0[ill], a1[ill], wd[ill])
     out[nz] = val
     return out
 
 
-def gauss_cell_integral_dpos(t, y0, y1):
+def gauss_cell_integral_dpos(t, y0, y1, width=None):
     """Derivative of the cell integral with respect to the charge position a.
 
     With y = x - a the cell is [x0 - a, x1 - a] = [y0, y1], so
     d/da = exp(-t^2 y0^2) - exp(-t^2 y1^2). It is evaluated as the larger
     exponential times -expm1 of the exponent difference, which does not cancel.
+    ``width`` as in ``gauss_cell_integral``.
     """
-    t, y0, y1 = np.broadcast_arrays(np.asarray(t, np.float64),
-                                    np.asarray(y0, np.float64),
-                                    np.asarray(y1, np.float64))
+    if width is None:
+        width = np.asarray(y1, np.float64) - np.asarray(y0, np.float64)
+    t, y0, y1, width = np.broadcast_arrays(np.asarray(t, np.float64),
+                                           np.asarray(y0, np.float64),
+                                           np.asarray(y1, np.float64),
+                                           np.asarray(width, np.float64))
     t2 = t * t
     # y1^2 - y0^2 = (y1 - y0)(y1 + y0)
-    dsq = (y1 - y0) * (y1 + y0)
+    dsq = width * (y1 + y0)
     near0 = np.abs(y0) <= np.abs(y1)
     out = np.empty(t.shape, np.float64)
     # |y0| <= |y1|: e0 - e1 = e0 * (1 - exp(-t^2 dsq)) = -e0 * expm1(-t^2 dsq)

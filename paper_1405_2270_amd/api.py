@@ -30,6 +30,20 @@ def _dev_f64(x, name):
     return x
 
 
+def _pos_tensor(pos):
+    pos = _dev_f64(pos, "pos")
+    if pos.dim() != 2 or pos.shape[1] != 3 or pos.shape[0] < 1:
+        raise ValueError("pos must have shape [M0][3] with M0 >= 1")
+    return pos
+
+
+def _charges(Z, M0):
+    Z = _dev_f64(Z, "Z")
+    if Z.numel() != M0:
+        raise ValueError(f"Z must hold {M0} charges (got {Z.numel()})")
+    return Z
+
+
 @dataclass(frozen=True)
 class LatticeSpec:
     """Grid and lattice: unit cell edge b, n cells per edge, L images per axis."""
@@ -83,7 +97,7 @@ def master_halfwidth(lat):
 
 def kernel_vectors(lat, quad, pos, derivative=False):
     """Master vectors [M0*3][R][2X] (FP64) for every atom and axis."""
-    pos = _dev_f64(pos, "pos")
+    pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     X = master_halfwidth(lat)
     out = torch.empty((M0 * 3, quad.R, 2 * X), dtype=torch.float64, device=pos.device)
@@ -95,7 +109,7 @@ def kernel_vectors(lat, quad, pos, derivative=False):
 
 def assemble(lat, quad, pos, Z, masters=None, derivative=False):
     """Assembled canonical factors [f0, f1, f2] ([K][N_l] FP64 each) and coef [K]."""
-    pos = _dev_f64(pos, "pos")
+    pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     K = M0 * quad.R
     dev = pos.device
@@ -106,7 +120,7 @@ def assemble(lat, quad, pos, Z, masters=None, derivative=False):
 
 def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
     """As ``assemble`` but into caller-provided factors F and coef."""
-    pos = _dev_f64(pos, "pos")
+    pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     K = M0 * quad.R
     for l in range(3):
@@ -114,13 +128,15 @@ def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
         if tuple(f.shape) != (K, lat.N(l)):
             raise ValueError(f"factor {l} must have shape {(K, lat.N(l))}")
     if not derivative:
-        Z = _dev_f64(Z, "Z")
+        Z = _charges(Z, M0)
         coef = _dev_f64(coef, "coef")
         if coef.numel() != K:
             raise ValueError("coef must have K entries")
+    X = master_halfwidth(lat)
     if masters is not None:
         masters = _dev_f64(masters, "masters")
-    X = master_halfwidth(lat)
+        if masters.numel() != M0 * 3 * quad.R * 2 * X:
+            raise ValueError(f"masters must hold M0*3*R*2X = {M0 * 3 * quad.R * 2 * X} values")
     check("ls_assemble", lib().ls_assemble(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0,
                                            _ptr(pos), _ptr(None if derivative else Z),
                                            _ptr(masters), X, int(derivative), _ptr(F[0]),
@@ -129,18 +145,62 @@ def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
     return F, coef
 
 
-def _canon(F, coef):
-    return Canon(int(F[0].shape[0]), (ctypes.c_int32 * 3)(*[int(f.shape[1]) for f in F]),
+def _canon(F, coef, name="factor"):
+    """Canonical-tensor descriptor of three device factor matrices [K][len_l]
+    and their coefficients [K], all contiguous float64 on one device."""
+    if len(F) != 3:
+        raise ValueError(f"{name}: three factor matrices are required")
+    for l, f in enumerate(F):
+        _dev_f64(f, f"{name}[{l}]")
+        if f.dim() != 2:
+            raise ValueError(f"{name}[{l}] must be a matrix [K][len]")
+    K = int(F[0].shape[0])
+    if any(int(f.shape[0]) != K for f in F):
+        raise ValueError(f"{name}: the factor matrices must have the same number of rows")
+    coef = _dev_f64(coef, f"{name} coefficients")
+    if coef.numel() != K:
+        raise ValueError(f"{name}: {K} coefficients are required (got {coef.numel()})")
+    if any(x.device != F[0].device for x in (F[1], F[2], coef)):
+        raise ValueError(f"{name}: all tensors must be on one device")
+    return Canon(K, (ctypes.c_int32 * 3)(*[int(f.shape[1]) for f in F]),
                  (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F]), coef.data_ptr())
+
+
+def _out_tensor(out, dtype, numel, device, name="out"):
+    """A caller-provided output must be a contiguous device tensor of the
+    precision's element type with room for ``numel`` elements (the library
+    writes through the raw pointer)."""
+    if not isinstance(out, torch.Tensor) or not out.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if out.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} for this precision (got {out.dtype})")
+    if not out.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if out.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    if out.numel() < numel:
+        raise ValueError(f"{name} holds {out.numel()} elements, {numel} are required")
+    return out
+
+
+def _ws_tensor(ws, device, name="workspace"):
+    if ws is None:
+        return None
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous device tensor")
+    if ws.device != device:
+        raise ValueError(f"{name} must be on {device}")
+    return ws
 
 
 def _recon_ws(canon, prec, device, ws):
     need = int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec))
     if need == 0:
         return None, 0
-    if ws is None or ws.numel() < need:
+    ws = _ws_tensor(ws, device)
+    if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=device)
-    return ws, ws.numel()
+    return ws, ws.numel() * ws.element_size()
 
 
 def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
@@ -148,9 +208,7 @@ def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
     (o0, o1, o2, e0, e1, e2). Returns one tensor [e0][e1][e2] per box
     (views of a single allocation). ``ws``: optional uint8 device workspace
     (split-bf16 precisions; allocated here when missing or short)."""
-    for f in F:
-        _dev_f64(f, "factor")
-    _dev_f64(coef, "coef")
+    _canon(F, coef)
     boxes = [tuple(int(v) for v in b) for b in boxes]
     prec = _lib.PRECISIONS[precision]
     dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
@@ -170,10 +228,16 @@ def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws
     ``ws`` already holds the preparation of these factors for this precision
     (``reconstruct_prepare``, or an earlier call with the same ``ws``)."""
     boxes = [tuple(int(v) for v in b) for b in boxes]
+    if any(len(b) != 6 for b in boxes):
+        raise ValueError("a box is (o0, o1, o2, e0, e1, e2)")
     prec = _lib.PRECISIONS[precision]
     canon = _canon(F, coef)
+    dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
+    _out_tensor(out, dtype, sum(max(b[3], 0) * max(b[4], 0) * max(b[5], 0) for b in boxes),
+                F[0].device)
     need = int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec))
-    if prepared and need > 0 and (ws is None or ws.numel() < need):
+    ws = _ws_tensor(ws, F[0].device)
+    if prepared and need > 0 and (ws is None or ws.numel() * ws.element_size() < need):
         raise ValueError("prepared=True needs the prepared workspace (%d bytes)" % need)
     ws, nws = _recon_ws(canon, prec, F[0].device, ws)
     cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
@@ -203,46 +267,47 @@ def reconstruct_tiles(precision):
 
 def energy(F, coef, D, d, precision="f64", ws=None):
     """E = <P, rho> (eq. scal) as a device scalar tensor."""
-    for f in list(F) + list(D):
-        _dev_f64(f, "factor")
+    cP, cR = _canon(F, coef), _canon(D, d, "density")
     K, Krho = int(F[0].shape[0]), int(D[0].shape[0])
     need = int(lib().ls_energy_workspace(K, Krho))
-    if ws is None or ws.numel() < need:
+    ws = _ws_tensor(ws, F[0].device)
+    if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=F[0].device)
     E = torch.empty((), dtype=torch.float64, device=F[0].device)
-    check("ls_energy", lib().ls_energy(ctypes.byref(_canon(F, coef)), ctypes.byref(_canon(D, d)),
-                                       _lib.PRECISIONS[precision], _ptr(E), _ptr(ws), ws.numel(),
-                                       _stream()))
+    check("ls_energy", lib().ls_energy(ctypes.byref(cP), ctypes.byref(cR),
+                                       _lib.PRECISIONS[precision], _ptr(E), _ptr(ws),
+                                       ws.numel() * ws.element_size(), _stream()))
     return E
 
 
 def forces(lat, quad, pos, Z, D, d, precision="f64", ws=None):
     """(F [M0][3], E) with F = -dE/dpos, by the adjoint of the assembled sums."""
-    pos = _dev_f64(pos, "pos")
-    Z = _dev_f64(Z, "Z")
+    pos = _pos_tensor(pos)
     M0 = pos.shape[0]
+    Z = _charges(Z, M0)
+    cR = _canon(D, d, "density")
     need = int(lib().ls_forces_workspace(ctypes.byref(lat.c()), M0, quad.R, int(D[0].shape[0])))
-    if ws is None or ws.numel() < need:
+    ws = _ws_tensor(ws, pos.device)
+    if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=pos.device)
     F = torch.empty((M0, 3), dtype=torch.float64, device=pos.device)
     E = torch.empty((), dtype=torch.float64, device=pos.device)
     check("ls_forces", lib().ls_forces(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0, _ptr(pos),
-                                       _ptr(Z), ctypes.byref(_canon(D, d)),
+                                       _ptr(Z), ctypes.byref(cR),
                                        _lib.PRECISIONS[precision], _ptr(F), _ptr(E), _ptr(ws),
-                                       ws.numel(), _stream()))
+                                       ws.numel() * ws.element_size(), _stream()))
     return F, E
 
 
 def combine(FA, ca, alpha, FB, cb, beta):
     """alpha A + beta B as one canonical tensor (eq. conc): factors [A; B]."""
-    for f in list(FA) + list(FB):
-        _dev_f64(f, "factor")
+    cA, cB = _canon(FA, ca, "A"), _canon(FB, cb, "B")
     Kt = int(FA[0].shape[0] + FB[0].shape[0])
     dev = FA[0].device
     F = [torch.empty((Kt, int(FA[l].shape[1])), dtype=torch.float64, device=dev) for l in range(3)]
     coef = torch.empty(Kt, dtype=torch.float64, device=dev)
-    check("ls_canon_combine", lib().ls_canon_combine(ctypes.byref(_canon(FA, ca)), float(alpha),
-                                                     ctypes.byref(_canon(FB, cb)), float(beta),
+    check("ls_canon_combine", lib().ls_canon_combine(ctypes.byref(cA), float(alpha),
+                                                     ctypes.byref(cB), float(beta),
                                                      _ptr(F[0]), _ptr(F[1]), _ptr(F[2]), _ptr(coef),
                                                      _stream()))
     return F, coef
@@ -264,16 +329,20 @@ def richardson(lat, quad, pos, Z, order="linear"):
 def nuclear_matrix(F, coef, g, ws=None):
     """V[k][m] = <G_k (.) G_m, P> (eq. nuc_pot) for rank-one basis functions
     with samples g[l] (device [Nb][N_l])."""
-    for x in list(F) + list(g):
-        _dev_f64(x, "factor")
+    cP = _canon(F, coef)
     K, Nb = int(F[0].shape[0]), int(g[0].shape[0])
+    for l, x in enumerate(g):
+        _dev_f64(x, f"basis samples [{l}]")
+        if tuple(x.shape) != (Nb, int(F[l].shape[1])):
+            raise ValueError(f"basis samples [{l}] must have shape {(Nb, int(F[l].shape[1]))}")
     need = int(lib().ls_nuclear_workspace(K, Nb))
-    if ws is None or ws.numel() < need:
+    ws = _ws_tensor(ws, F[0].device)
+    if ws is None or ws.numel() * ws.element_size() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=F[0].device)
     V = torch.empty((Nb, Nb), dtype=torch.float64, device=F[0].device)
-    check("ls_nuclear_matrix", lib().ls_nuclear_matrix(ctypes.byref(_canon(F, coef)), Nb, _ptr(g[0]),
+    check("ls_nuclear_matrix", lib().ls_nuclear_matrix(ctypes.byref(cP), Nb, _ptr(g[0]),
                                                        _ptr(g[1]), _ptr(g[2]), _ptr(V), _ptr(ws),
-                                                       ws.numel(), _stream()))
+                                                       ws.numel() * ws.element_size(), _stream()))
     return V
 
 
@@ -330,8 +399,9 @@ class Batch:
             arr[i].lat = sy["lat"].c()
             arr[i].quad = q.c()
             arr[i].M0 = int(sy["pos"].shape[0])
-            arr[i].pos = _dev_f64(sy["pos"], "pos").data_ptr()
-            arr[i].Z = _dev_f64(sy["Z"], "Z").data_ptr()
+            pos_i = _pos_tensor(sy["pos"])
+            arr[i].pos = pos_i.data_ptr()
+            arr[i].Z = _charges(sy["Z"], int(pos_i.shape[0])).data_ptr()
             arr[i].rho = _canon(sy["D"], sy["d"])
             arr[i].box = Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
             arr[i].out = out.data_ptr()
