@@ -294,9 +294,14 @@ def test_invalid_arguments_raise(L):
     bad = L.LatticeSpec(sysm.b, 0, (2, 2, 2))
     with pytest.raises(LatsumError):
         L.kernel_vectors(bad, qt, _t(sysm.pos))
+    # the periodic cell generates every cell integral in registers: the library
+    # refuses stored masters for it (a buffer of the right size, so that the
+    # binding's own size check passes and the refusal is the library's)
+    per = L.LatticeSpec(sysm.b, 8, (2, 2, 2), True)
+    nm = sysm.pos.shape[0] * 3 * qt.R * 2 * L.master_halfwidth(per)
     with pytest.raises(LatsumError):
-        L.assemble(L.LatticeSpec(sysm.b, 8, (2, 2, 2), True), qt, _t(sysm.pos), _t(sysm.Z),
-                   torch.zeros(1, dtype=torch.float64, device=dev))
+        L.assemble(per, qt, _t(sysm.pos), _t(sysm.Z),
+                   torch.zeros(nm, dtype=torch.float64, device=dev))
     # the preparation as a call of its own: a short workspace, and an unknown
     # precision code, are refused before any launch; FP64 needs none
     from paper_1405_2270_amd import _lib
