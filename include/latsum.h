@@ -25,7 +25,8 @@
  *  - Every pointer argument named *_dev is device memory owned by the caller;
  *    struct descriptors and other pointers are host memory read during the
  *    call only. The library allocates no device memory and keeps no pointer
- *    after a call returns.
+ *    after a call returns (its one fixed device array, the scratch of
+ *    ls_forces_noalloc, is part of the loaded library).
  *  - Arguments are checked on the host before anything is enqueued; a
  *    failing check returns a negative ls_status and enqueues nothing.
  *    ls_last_error() then describes the failure (thread-local).
@@ -262,6 +263,30 @@ ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                     const double* pos_dev, const double* Z_dev, const ls_canon* rho,
                     int32_t precision, double* F_dev, double* E_dev,
                     void* ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ls_forces for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight molecular-dynamics or
+ * serving loops, harnesses that forbid allocation). Same arguments, kernels,
+ * results and errors as ls_forces, without ws_dev / ws_bytes: the scratch
+ * (folded density, Grams, per-atom energies) is a fixed array of
+ * LS_FORCES_NOALLOC_BYTES bytes of device memory inside this library, one per
+ * GPU, held until the process ends. The call allocates nothing; its first
+ * call on a device resolves that device's array address once.
+ * Limit: problems with ls_forces_workspace(lat, M0, quad->R, rho->K) above
+ * LS_FORCES_NOALLOC_BYTES are refused with LS_EWORKSPACE before anything is
+ * enqueued (8 MiB holds, e.g., M0 = 64 atoms, R = 48, a rank-8 density on a
+ * 32^3-cell box lattice of n = 128, which needs 2.8 MB).
+ * Every call on one GPU uses the same array and leaves its contents behind:
+ * calls that may overlap on one GPU (several streams, several host threads)
+ * race and give wrong results; the caller orders them (one stream, or
+ * events). Calls in sequence on one stream are safe: every scratch entry a
+ * call reads is written earlier in the same call.
+ */
+#define LS_FORCES_NOALLOC_BYTES (8u << 20)
+ls_status ls_forces_noalloc(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                            const double* pos_dev, const double* Z_dev, const ls_canon* rho,
+                            int32_t precision, double* F_dev, double* E_dev, hipStream_t stream);
 
 /*
  * Canonical sum alpha A + beta B by concatenation of the factor matrices

@@ -14,6 +14,8 @@
 // factors touch HBM.
 //
 // All cross-lane reductions are fixed-order trees (bitwise reproducible).
+#include <mutex>
+
 #include "ls_common.hpp"
 
 namespace ls {
@@ -441,11 +443,12 @@ extern "C" size_t ls_forces_workspace(const ls_lattice* lat, int32_t M0, int32_t
   return t;
 }
 
-extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
-                               const double* pos_dev, const double* Z_dev, const ls_canon* rho,
-                               int32_t precision, double* F_dev, double* E_dev, void* ws_dev,
-                               size_t ws_bytes, hipStream_t stream) {
-  clear_error();
+// The body of ls_forces and ls_forces_noalloc: `scratch_name` names the
+// buffer in the error text when it is too small.
+static ls_status forces_run(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                            const double* pos_dev, const double* Z_dev, const ls_canon* rho,
+                            int32_t precision, double* F_dev, double* E_dev, void* ws_dev,
+                            size_t ws_bytes, const char* scratch_name, hipStream_t stream) {
   Lat L;
   ls_status st = check_lattice(lat, &L);
   if (st != LS_OK) return st;
@@ -471,7 +474,8 @@ extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32
   int X, W;
   forces_layout(L, M0, qa.R, rho->K, &off_gv, &off_gd, &off_e, &total, &X, &W);
   if (ws_dev == nullptr || ws_bytes < total) {
-    set_error("workspace of %zu bytes required", total);
+    set_error("%s of %zu bytes required (%zu available)", scratch_name, total,
+              ws_dev == nullptr ? (size_t)0 : ws_bytes);
     return LS_EWORKSPACE;
   }
   char* ws = (char*)ws_dev;
@@ -498,4 +502,73 @@ extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32
   if (st != LS_OK || E_dev == nullptr) return st;
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, stream, Eatom, M0, E_dev);
   return launch_status("ls_forces (energy)");
+}
+
+extern "C" ls_status ls_forces(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                               const double* pos_dev, const double* Z_dev, const ls_canon* rho,
+                               int32_t precision, double* F_dev, double* E_dev, void* ws_dev,
+                               size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  return forces_run(lat, quad, M0, pos_dev, Z_dev, rho, precision, F_dev, E_dev, ws_dev, ws_bytes,
+                    "workspace", stream);
+}
+
+// ---------------------------------------------------------------------------
+// ls_forces without a workspace argument: the folded density, the Grams and
+// the per-atom energies go to a fixed device array of this library. Every
+// kernel of the forces writes each scratch entry it later reads (nothing has
+// to start at zero), so consecutive calls need no clearing.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LS_FORCES_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The device address of `scratch` on the current device, resolved once per
+// device (the host-side name of the array is not a device address).
+static ls_status scratch_address(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_error("ls_forces_noalloc: no usable current device (%s)", hipGetErrorString(e));
+    return LS_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("ls_forces_noalloc: scratch address on device %d: %s", dev, hipGetErrorString(e));
+      return LS_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return LS_OK;
+}
+
+extern "C" ls_status ls_forces_noalloc(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                                       const double* pos_dev, const double* Z_dev,
+                                       const ls_canon* rho, int32_t precision, double* F_dev,
+                                       double* E_dev, hipStream_t stream) {
+  clear_error();
+  // the size check first, so that an oversized problem is refused on the
+  // host before any device query
+  if (lat != nullptr && quad != nullptr && rho != nullptr) {
+    const size_t need = ls_forces_workspace(lat, M0, quad->R, rho->K);
+    if (need > (size_t)LS_FORCES_NOALLOC_BYTES) {
+      set_error("ls_forces_noalloc: the problem needs %zu bytes of scratch, above the fixed %zu "
+                "(use ls_forces with a workspace)",
+                need, (size_t)LS_FORCES_NOALLOC_BYTES);
+      return LS_EWORKSPACE;
+    }
+  }
+  void* ptr = nullptr;
+  const ls_status st = scratch_address(&ptr);
+  if (st != LS_OK) return st;
+  return forces_run(lat, quad, M0, pos_dev, Z_dev, rho, precision, F_dev, E_dev, ptr,
+                    (size_t)LS_FORCES_NOALLOC_BYTES, "fixed scratch", stream);
 }
