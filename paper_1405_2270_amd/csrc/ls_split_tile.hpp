@@ -9,11 +9,16 @@ namespace ls {
 // ---------------------------------------------------------------------------
 // split-bf16 kernels
 // ---------------------------------------------------------------------------
-// Every operand value is rounded once to FP32 and cut into NT bf16 terms by
-// truncation: x0 = x with its low 16 bits cleared, x1 = (x - x0) likewise,
-// x2 = x - x0 - x1. Each difference is exact in FP32, and three 8-bit bf16
-// significands hold the whole 24-bit FP32 significand, so x0 + x1 + x2 = x.
-// With NT = 2 the last term is rounded to nearest (|x - x0 - x1| <= 2^-16 |x|).
+// Every operand value is rounded once to FP32 and cut into NT bf16 terms.
+// NT = 3, by truncation: x0 = x with its low 16 bits cleared, x1 = (x - x0)
+// likewise, x2 = x - x0 - x1. Each difference is exact in FP32, and three
+// 8-bit bf16 significands hold the whole 24-bit FP32 significand, so
+// x0 + x1 + x2 = x.
+// NT = 2, by rounding to nearest (even): x0 = bf16(x), x1 = bf16(x - x0), so
+// |x - x0| <= 2^-8 |x| and |x - x0 - x1| <= 2^-16 |x| (x - x0 is exact in
+// FP32: x0 lies within a factor 2 of x). The dropped product x1 y1 then has
+// either sign with equal odds; truncated terms would all share the sign of
+// x y and drop a bias of about 2^-16 |x y| in every product.
 // Products: x0y0 + x0y1 + x1y0, and for NT = 3 also x1y1 + x0y2 + x2y0, on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation, small terms first.
 //
@@ -35,7 +40,7 @@ __device__ __forceinline__ void split_fp32(float x, unsigned (&u)[NT]) {
   unsigned b = __float_as_uint(x);
 #pragma unroll
   for (int t = 0; t < NT - 1; ++t) {
-    const unsigned hi = b & 0xffff0000u;
+    const unsigned hi = (NT == 2 ? b + 0x7fffu + ((b >> 16) & 1u) : b) & 0xffff0000u;
     u[t] = hi;
     x -= __uint_as_float(hi);
     b = __float_as_uint(x);

@@ -1,7 +1,7 @@
 """Batched systems in one persistent launch against the FP64 oracle.
 
 Each system's energy (FP64 throughout) and its reconstructed sub-box (FP64,
-FP32 or split-bf16x6 reconstruction) are compared with the oracle; graph
+FP32, split-bf16x3 or split-bf16x6 reconstruction) are compared with the oracle; graph
 replays must be bitwise identical; every tile variant and the autotuned one
 must give the same results (FP64 and FP32 tiles sum in the same order: equal
 to 1e-12; the split tiles use two MFMA shapes: each within the oracle gate)."""
@@ -14,6 +14,7 @@ from oracle.canonical import reconstruct as o_reconstruct, sample_columns
 from oracle.physics import energy as o_energy
 from oracle.quadrature import rule_s
 from workloads import small_box, config4
+from _gates import gate
 
 pytestmark = pytest.mark.gpu
 dev = torch.device("cuda:0")
@@ -54,7 +55,7 @@ def _batch(L, systems, precision):
     return L.Batch(items, precision)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3"])
 def test_batch_against_oracle(precision):
     import paper_1405_2270_amd as L
     systems = _systems()
@@ -64,7 +65,7 @@ def test_batch_against_oracle(precision):
     assert err == 0 and np.all(sec > 0)
     first = [o.double().cpu().numpy().copy() for o in B.out]
     E1 = [float(e.cpu()) for e in B.E]
-    refs = []
+    refs, Ks = [], []
     for i, (s, box) in enumerate(systems):
         q = s.quad
         t, w = rule_s(q["M"], q["C0"], q["s"])
@@ -76,8 +77,10 @@ def test_batch_against_oracle(precision):
         ref = o_reconstruct(Fo, co, box[:3], box[3:]) / s.h ** 3
         ref_abs = o_reconstruct(Fo, np.abs(co), box[:3], box[3:]) / s.h ** 3
         refs.append((ref, np.max(np.abs(ref_abs))))
+        Ks.append(len(co))
         err_v = np.max(np.abs(first[i] - ref)) / np.max(np.abs(ref_abs))
-        assert err_v < (1e-12 if precision == "f64" else 1e-6), (i, err_v)
+        print(f"batch {precision} system {i}: rel_mag {err_v:.3e}")
+        assert err_v < gate(precision, len(co)), (i, err_v)
     # graph replay: bitwise identical
     B.run(tile=2)
     torch.cuda.synchronize()
@@ -94,7 +97,7 @@ def test_batch_against_oracle(precision):
                 assert np.max(np.abs(a - first[i])) <= 1e-12 * np.max(np.abs(first[i])) + 1e-300
             else:
                 ref, scale = refs[i]
-                assert np.max(np.abs(a - ref)) / scale < 1e-6, (tile, i)
+                assert np.max(np.abs(a - ref)) / scale < gate(precision, Ks[i]), (tile, i)
     best, ms = B.autotune()
     assert 1 <= best <= L.api.lib().ls_batch_tiles() and ms > 0
     B.run()

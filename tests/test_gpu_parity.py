@@ -5,10 +5,10 @@ Error measures (both stated for every potential/energy check):
   rel_mag = max|x - x_o| / max|x_o^{|Z|}|, the oracle rerun with |Z_nu|, which
             is the scale rounding errors follow when charges cancel.
 Gates: FP64 path 1e-12 (rel_mag, and rel_inf where charges do not cancel;
-factor and master rows 1e-12 of each row's maximum),
-mixed FP32 / split-bf16x6 / scaled FP16x3 1e-6 (rel_mag), split-bf16x3 3e-5
-(rel_mag, two bf16 terms carry ~16 bits), forces 1e-5 normwise for the FP32
-Grams.
+factor and master rows 1e-12 of each row's maximum; forces normwise),
+mixed FP32 / split-bf16x6 / scaled FP16x3 1e-6 (rel_mag), split-bf16x3 its
+own arithmetic bound (about 5e-5: it does not meet 1e-6, see _gates.py),
+forces 1e-5 normwise for the FP32 Grams.
 """
 import ctypes
 
@@ -150,12 +150,46 @@ def test_derivative_factors(L, name, maker):
             assert _close_rows(a, b, 1e-12), (name, l)
 
 
+# box lattices whose widest axis selects each instantiation of the stored-
+# masters assembly: up to 8, 16, 32 and 64 images per residue window, and the
+# direct kernel beyond 64 (Theorem 3.1, eq. EwaldTensorM0)
+WIDTHS = [
+    ("L12", lambda: small_box(121, n=5, L=(12, 2, 3), M0=2)),
+    ("L40", lambda: small_box(122, n=4, L=(2, 40, 2), M0=2)),
+    ("L64", lambda: small_box(123, n=3, L=(3, 2, 64), M0=2)),
+    ("L70", lambda: small_box(124, n=3, L=(70, 2, 3), M0=2)),
+]
+
+
+@pytest.mark.parametrize("name,maker", WIDTHS, ids=[s[0] for s in WIDTHS])
+@pytest.mark.parametrize("deriv", [False, True], ids=["value", "derivative"])
+def test_assembly_lattice_widths(L, name, maker, deriv):
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    pos = _t(sysm.pos)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z, derivative=deriv)
+    masters = L.kernel_vectors(spec, qt, pos, derivative=deriv)
+    F, coef = L.assemble(spec, qt, pos, None if deriv else _t(sysm.Z), masters, derivative=deriv)
+    torch.cuda.synchronize()
+    for l in range(3):
+        assert _close_rows(F[l].cpu().numpy(), Fo[l], 1e-12), (name, deriv, l)
+    if not deriv:
+        assert np.allclose(coef.cpu().numpy(), co, rtol=1e-15, atol=0)
+        h3 = sysm.h ** 3
+        full = (0, 0, 0, F[0].shape[1], F[1].shape[1], F[2].shape[1])
+        V = L.reconstruct(F, coef, [full], 1.0 / h3, "f64")[0].cpu().numpy()
+        ref = o_reconstruct(Fo, co) / h3
+        ref_abs = o_reconstruct(Fo, np.abs(co)) / h3
+        assert _errors(V, ref, ref_abs)[1] < 1e-12, name
+
+
 def _errors(got, ref, ref_abs):
     err = np.max(np.abs(got - ref))
     return err / np.max(np.abs(ref)), err / np.max(np.abs(ref_abs))
 
 
-PREC_GATES = {"f64": 1e-12, "f32": 1e-6, "bf16x6": 1e-6, "bf16x3": 3e-5, "f16x3": 1e-6}
+from _gates import gate as _gate  # noqa: E402
 
 
 @pytest.mark.parametrize("name,maker", SMALL, ids=[s[0] for s in SMALL])
@@ -177,7 +211,7 @@ def test_reconstruct(L, name, maker, precision):
             ref = o_reconstruct(Fo, co, b[:3], b[3:]) / h3
             ref_abs = o_reconstruct(Fo, np.abs(co), b[:3], b[3:]) / h3
             rel_inf, rel_mag = _errors(out.double().cpu().numpy(), ref, ref_abs)
-            assert rel_mag < PREC_GATES[precision], (name, precision, tile, b, rel_inf, rel_mag)
+            assert rel_mag < _gate(precision, coef.numel()), (name, precision, tile, b, rel_inf, rel_mag)
             if precision == "f64" and np.all(sysm.Z > 0):
                 assert rel_inf < 1e-12
 
@@ -237,8 +271,9 @@ def test_forces_and_energy_by_adjoint(L, name, maker, precision):
     Fo = forces_adjoint(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
     Eo = o_energy(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d)
     Eabs = o_energy(geom, t, w, sysm.pos, np.abs(sysm.Z), sysm.density.D, sysm.density.d)
-    gate = 1e-11 if precision == "f64" else 1e-5
-    assert np.max(np.abs(Fg.cpu().numpy() - Fo)) / np.max(np.abs(Fo)) < gate, name
+    gate = 1e-12 if precision == "f64" else 1e-5
+    err = np.max(np.abs(Fg.cpu().numpy() - Fo)) / np.max(np.abs(Fo))
+    assert err < gate, (name, precision, err)
     assert abs(float(Eg.cpu()) - Eo) / abs(Eabs) < (1e-12 if precision == "f64" else 1e-6)
 
 
@@ -343,7 +378,7 @@ def test_config1_full_potential(L):
     for precision in ("f64", "f32", "bf16x6"):
         V = L.reconstruct(F, coef, [tuple(sysm.boxes[0])], 1.0 / h3, precision)[0]
         rel_inf, _ = _errors(V.double().cpu().numpy(), ref, ref)
-        assert rel_inf < PREC_GATES[precision], (precision, rel_inf)
+        assert rel_inf < _gate(precision, coef.numel()), (precision, rel_inf)
 
 
 @pytest.mark.slow
@@ -367,11 +402,12 @@ def test_config2_sampled(L):
         coef_o = (sysm.Z[:, None] * w[None, :]).ravel()
         ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
         ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
-        for precision in ("f64", "f32", "bf16x6", "f16x3"):
+        for precision in ("f64", "f32", "bf16x6", "bf16x3", "f16x3"):
             V = L.reconstruct(F, coef, [b], 1.0 / h3, precision)[0]
             got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
             rel_inf, rel_mag = _errors(got.double().cpu().numpy(), ref, ref_abs)
-            assert rel_mag < PREC_GATES[precision], (precision, rel_inf, rel_mag)
+            print(f"config2 box {bi} {precision}: rel_inf {rel_inf:.3e} rel_mag {rel_mag:.3e}")
+            assert rel_mag < _gate(precision, coef.numel()), (precision, rel_inf, rel_mag)
             del V
             torch.cuda.empty_cache()
 
@@ -419,11 +455,14 @@ def test_config3_periodic_sampled(L):
     h3 = sysm.h ** 3
     ref = np.asarray(sample_columns(cols, coef_o, sel), np.float64) / h3
     ref_abs = np.asarray(sample_columns(cols, np.abs(coef_o), sel), np.float64) / h3
-    for precision in ("f64", "f32"):
+    for precision in ("f64", "f32", "bf16x6", "bf16x3", "f16x3"):
         V = L.reconstruct(F, coef, [tuple(sysm.boxes[0])], 1.0 / h3, precision)[0]
         got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
         rel_inf, rel_mag = _errors(got.double().cpu().numpy(), ref, ref_abs)
-        assert rel_mag < PREC_GATES[precision], (precision, rel_inf, rel_mag)
+        print(f"config3 {precision}: rel_inf {rel_inf:.3e} rel_mag {rel_mag:.3e}")
+        assert rel_mag < _gate(precision, coef.numel()), (precision, rel_inf, rel_mag)
+        del V
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.slow
@@ -443,8 +482,10 @@ def test_config5_forces_sampled(L):
     geom = _geom(sysm)
     Fo = forces_adjoint_atoms(geom, t, w, sysm.pos, sysm.Z, sysm.density.D, sysm.density.d, atoms)
     scale = np.max(np.abs(Fo))
-    assert np.max(np.abs(F64[atoms] - Fo)) / scale < 1e-11
-    assert np.max(np.abs(F32[atoms] - Fo)) / scale < 1e-5
+    e64 = np.max(np.abs(F64[atoms] - Fo)) / scale
+    e32 = np.max(np.abs(F32[atoms] - Fo)) / scale
+    print(f"config5 forces vs oracle adjoint: f64 {e64:.3e} f32 {e32:.3e}")
+    assert e64 < 1e-12 and e32 < 1e-5, (e64, e32)
     step = sysm.extra["fd_step"]
     for nu in atoms:
         for l in range(3):
