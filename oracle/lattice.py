@@ -31,6 +31,13 @@ Two independent routes are given, and T1 requires them to agree to rounding:
     (Theorem 3.1 / eq. EwaldTensorM0, Lemma 3.2).
 ``brute_force_tensor`` sums the shifted full 3D master tensors over all L^3
 images (tiny grids only) as the reference for both.
+
+Non-equidistant tensor lattices (Sec. 3.1, remark after eq. EwaldTensorM0):
+``tensor_lattice_factors`` (direct sum at arbitrary per-axis lattice
+coordinates), ``tensor_lattice_assembled`` (master windows, for coordinates
+that are whole numbers of cells) and ``tensor_lattice_brute_force`` (3D sum
+over every image triple). Pinned against each other, against
+``direct_factors`` for equidistant coordinates, and against point charges.
 """
 from dataclasses import dataclass
 
@@ -206,3 +213,107 @@ def point_charge_potential(geom, pos, Z, points):
         d = points[:, None, :] - (pos[nu] + K)[None, :, :]
         out += Z[nu] * np.sum(1.0 / np.linalg.norm(d, axis=-1), axis=1)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Non-equidistant tensor lattices (Sec. 3.1, the remark after eq.
+# EwaldTensorM0: the summation stays valid when the L1 x L2 x L3 lattice is a
+# tensor product of arbitrary 1D point sets).
+#
+# The lattice point k = (k0, k1, k2) shifts every unit-cell charge by
+# (s_0[k0], s_1[k1], s_2[k2]); s_l holds L_l coordinates along axis l in
+# length units (equidistant box: s_l[k] = b k). The grid keeps the mesh
+# h = b/n; axis l has N_l cells, cell g spanning [-b/2 + g h, -b/2 + (g+1) h].
+# Because the shift is a tensor product, the 3D sum over all image triples
+# splits into per-axis sums (the argument of Theorem 3.1 with the windows
+# replaced by arbitrary shifts), so the rank stays M0 * R.
+# ---------------------------------------------------------------------------
+@dataclass(frozen=True)
+class TensorLattice:
+    b: float
+    n: int
+    N: tuple       # grid cells per axis
+    s: tuple       # three 1D arrays of lattice coordinates (length units)
+
+    @property
+    def h(self):
+        return self.b / self.n
+
+
+def tensor_lattice_factors(tl, t, w, pos, Z, derivative=False):
+    """Direct sum over the lattice coordinates of every axis:
+    F[l][nu*R+q, g] = sum_k b_g(t_q; a_{nu,l} + s_l[k]), each image's cell
+    integral at its own continuous position (the cell offset is taken as
+    g h - (a + b/2) - s_l[k]). With ``derivative`` the entries are the
+    derivatives with respect to a_{nu,l} (all images move with the atom)."""
+    t = np.asarray(t, np.float64)
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    M0, R = pos.shape[0], t.size
+    cell = gauss_cell_integral_dpos if derivative else gauss_cell_integral
+    F = []
+    for l in range(3):
+        g = np.arange(tl.N[l], dtype=np.float64)
+        out = np.zeros((M0 * R, tl.N[l]))
+        for nu in range(M0):
+            acc = np.zeros((R, tl.N[l]))
+            a = pos[nu, l] + 0.5 * tl.b
+            for sk in np.asarray(tl.s[l], np.float64):
+                y0 = g * tl.h - a - sk
+                y1 = (g + 1.0) * tl.h - a - sk
+                acc += cell(t[:, None], y0[None, :], y1[None, :], tl.h)
+            out[nu * R:(nu + 1) * R] = acc
+        F.append(out)
+    coef = (np.asarray(Z, np.float64)[:, None] * np.asarray(w, np.float64)[None, :]).ravel()
+    return F, coef
+
+
+def tensor_lattice_assembled(tl, t, w, pos, Z):
+    """The same sum by the paper's route when every lattice coordinate is a
+    whole number of cells (s_l[k] = m_k h): one master vector per (atom, axis)
+    on a doubled grid (eq. master_pot) and, per lattice coordinate, its window
+    shifted by m_k cells, added pointwise (Theorem 3.1 with irregular
+    shifts)."""
+    t = np.asarray(t, np.float64)
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    M0, R = pos.shape[0], t.size
+    geom = Geometry(tl.b, tl.n, (1, 1, 1))
+    F = []
+    for l in range(3):
+        m_cells = np.rint(np.asarray(tl.s[l], np.float64) / tl.h).astype(np.int64)
+        if not np.allclose(m_cells * tl.h, tl.s[l], rtol=0, atol=1e-9 * tl.h):
+            raise ValueError("lattice coordinates must be whole numbers of cells")
+        g = np.arange(tl.N[l])
+        X = int(tl.N[l] + tl.n + np.max(np.abs(m_cells)) + 2)
+        out = np.zeros((M0 * R, tl.N[l]))
+        for nu in range(M0):
+            p, d = node_and_offset(geom, pos[nu, l])
+            mv = master_vectors(geom, t, d, X)
+            acc = np.zeros((R, tl.N[l]))
+            for mk in m_cells:
+                acc += mv[:, g - p - mk + X]
+            out[nu * R:(nu + 1) * R] = acc
+        F.append(out)
+    coef = (np.asarray(Z, np.float64)[:, None] * np.asarray(w, np.float64)[None, :]).ravel()
+    return F, coef
+
+
+def tensor_lattice_brute_force(tl, t, w, pos, Z):
+    """Raw Galerkin tensor of the lattice by 3D brute force (tiny grids): for
+    every atom and every image triple (k0, k1, k2), the rank-R tensor
+    sum_q w_q (x)_l b(t_q; a_l + s_l[k_l]) of that single image, formed in
+    3D and added with weight Z_nu (eqs. core_tens, EwaldSumE)."""
+    t = np.asarray(t, np.float64)
+    w = np.asarray(w, np.float64)
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    P = np.zeros(tuple(tl.N))
+    edges = [-0.5 * tl.b + tl.h * np.arange(tl.N[l] + 1, dtype=np.float64) for l in range(3)]
+    for nu in range(pos.shape[0]):
+        for s0 in tl.s[0]:
+            for s1 in tl.s[1]:
+                for s2 in tl.s[2]:
+                    c = pos[nu] + np.array([s0, s1, s2])
+                    v = [gauss_cell_integral(t[:, None], (edges[l][:-1] - c[l])[None, :],
+                                             (edges[l][1:] - c[l])[None, :])
+                         for l in range(3)]
+                    P += Z[nu] * np.einsum("q,qi,qj,qk->ijk", w, v[0], v[1], v[2])
+    return P
