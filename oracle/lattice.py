@@ -221,9 +221,13 @@ def point_charge_potential(geom, pos, Z, points):
 # tensor product of arbitrary 1D point sets).
 #
 # The lattice point k = (k0, k1, k2) shifts every unit-cell charge by
-# (s_0[k0], s_1[k1], s_2[k2]); s_l holds L_l coordinates along axis l in
-# length units (equidistant box: s_l[k] = b k). The grid keeps the mesh
-# h = b/n; axis l has N_l cells, cell g spanning [-b/2 + g h, -b/2 + (g+1) h].
+# h (s_0[k0], s_1[k1], s_2[k2]); s_l holds L_l coordinates along axis l in
+# units of the grid cell h = b/n, not necessarily whole numbers (equidistant
+# box: s_l[k] = n k). Axis l has N_l cells, cell g spanning
+# [-b/2 + g h, -b/2 + (g+1) h]. The cell offset from an image is formed as
+# (g - s_l[k]) h - (a + b/2): the lattice-size difference g - s_l[k] first,
+# so that its rounding error scales with the distance from the image, as in
+# the box lattice's (g - k n) h - (a + b/2).
 # Because the shift is a tensor product, the 3D sum over all image triples
 # splits into per-axis sums (the argument of Theorem 3.1 with the windows
 # replaced by arbitrary shifts), so the rank stays M0 * R.
@@ -233,7 +237,7 @@ class TensorLattice:
     b: float
     n: int
     N: tuple       # grid cells per axis
-    s: tuple       # three 1D arrays of lattice coordinates (length units)
+    s: tuple       # three 1D arrays of lattice coordinates (units of h)
 
     @property
     def h(self):
@@ -242,10 +246,10 @@ class TensorLattice:
 
 def tensor_lattice_factors(tl, t, w, pos, Z, derivative=False):
     """Direct sum over the lattice coordinates of every axis:
-    F[l][nu*R+q, g] = sum_k b_g(t_q; a_{nu,l} + s_l[k]), each image's cell
-    integral at its own continuous position (the cell offset is taken as
-    g h - (a + b/2) - s_l[k]). With ``derivative`` the entries are the
-    derivatives with respect to a_{nu,l} (all images move with the atom)."""
+    F[l][nu*R+q, g] = sum_k b_g(t_q; a_{nu,l} + h s_l[k]), each image's cell
+    integral at its own continuous position. With ``derivative`` the entries
+    are the derivatives with respect to a_{nu,l} (all images move with the
+    atom)."""
     t = np.asarray(t, np.float64)
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     M0, R = pos.shape[0], t.size
@@ -258,8 +262,8 @@ def tensor_lattice_factors(tl, t, w, pos, Z, derivative=False):
             acc = np.zeros((R, tl.N[l]))
             a = pos[nu, l] + 0.5 * tl.b
             for sk in np.asarray(tl.s[l], np.float64):
-                y0 = g * tl.h - a - sk
-                y1 = (g + 1.0) * tl.h - a - sk
+                y0 = (g - sk) * tl.h - a
+                y1 = (g + 1.0 - sk) * tl.h - a
                 acc += cell(t[:, None], y0[None, :], y1[None, :], tl.h)
             out[nu * R:(nu + 1) * R] = acc
         F.append(out)
@@ -269,7 +273,7 @@ def tensor_lattice_factors(tl, t, w, pos, Z, derivative=False):
 
 def tensor_lattice_assembled(tl, t, w, pos, Z):
     """The same sum by the paper's route when every lattice coordinate is a
-    whole number of cells (s_l[k] = m_k h): one master vector per (atom, axis)
+    whole number of cells (s_l[k] = m_k): one master vector per (atom, axis)
     on a doubled grid (eq. master_pot) and, per lattice coordinate, its window
     shifted by m_k cells, added pointwise (Theorem 3.1 with irregular
     shifts)."""
@@ -279,8 +283,8 @@ def tensor_lattice_assembled(tl, t, w, pos, Z):
     geom = Geometry(tl.b, tl.n, (1, 1, 1))
     F = []
     for l in range(3):
-        m_cells = np.rint(np.asarray(tl.s[l], np.float64) / tl.h).astype(np.int64)
-        if not np.allclose(m_cells * tl.h, tl.s[l], rtol=0, atol=1e-9 * tl.h):
+        m_cells = np.rint(np.asarray(tl.s[l], np.float64)).astype(np.int64)
+        if not np.array_equal(m_cells, np.asarray(tl.s[l], np.float64)):
             raise ValueError("lattice coordinates must be whole numbers of cells")
         g = np.arange(tl.N[l])
         X = int(tl.N[l] + tl.n + np.max(np.abs(m_cells)) + 2)
@@ -300,7 +304,7 @@ def tensor_lattice_assembled(tl, t, w, pos, Z):
 def tensor_lattice_brute_force(tl, t, w, pos, Z):
     """Raw Galerkin tensor of the lattice by 3D brute force (tiny grids): for
     every atom and every image triple (k0, k1, k2), the rank-R tensor
-    sum_q w_q (x)_l b(t_q; a_l + s_l[k_l]) of that single image, formed in
+    sum_q w_q (x)_l b(t_q; a_l + h s_l[k_l]) of that single image, formed in
     3D and added with weight Z_nu (eqs. core_tens, EwaldSumE)."""
     t = np.asarray(t, np.float64)
     w = np.asarray(w, np.float64)
@@ -311,7 +315,7 @@ def tensor_lattice_brute_force(tl, t, w, pos, Z):
         for s0 in tl.s[0]:
             for s1 in tl.s[1]:
                 for s2 in tl.s[2]:
-                    c = pos[nu] + np.array([s0, s1, s2])
+                    c = pos[nu] + tl.h * np.array([s0, s1, s2])
                     v = [gauss_cell_integral(t[:, None], (edges[l][:-1] - c[l])[None, :],
                                              (edges[l][1:] - c[l])[None, :])
                          for l in range(3)]

@@ -1,8 +1,9 @@
 """Pins for the oracle's non-equidistant tensor lattices (Sec. 3.1, remark
 after eq. EwaldTensorM0): lattice points at arbitrary per-axis coordinates
-s_l[k], the sum over all image triples split into per-axis sums.
+s_l[k] (units of the cell h), the sum over all image triples split into
+per-axis sums.
 
-  * equidistant coordinates s_l[k] = b k reduce to the box lattice (the
+  * equidistant coordinates s_l[k] = n k reduce to the box lattice (the
     independently pinned direct sum of Theorem 3.1's setting);
   * the direct per-axis sum equals a 3D brute force over every image triple
     (on-grid and off-grid coordinates, off-grid charges, mixed signs);
@@ -37,7 +38,7 @@ def test_equidistant_coordinates_are_the_box_lattice():
     pos = -0.5 * b + rng.uniform(0, 1, (3, 3)) * b
     Z = np.array([1.0, -2.0, 1.0])
     tl = TensorLattice(b, n, tuple(L[l] * n for l in range(3)),
-                       tuple(b * np.arange(L[l]) for l in range(3)))
+                       tuple(float(n) * np.arange(L[l]) for l in range(3)))
     Ft, ct = tensor_lattice_factors(tl, t, w, pos, Z)
     Fd, cd = direct_factors(Geometry(b, n, L), t, w, pos, Z)
     assert np.array_equal(ct, cd)
@@ -46,14 +47,14 @@ def test_equidistant_coordinates_are_the_box_lattice():
 
 
 def _irregular(rng, b, n, L, on_grid):
-    """Per-axis coordinates: a seeded irregular spacing between 0.6 b and 1.4 b."""
-    h = b / n
+    """Per-axis coordinates (cells): a seeded irregular spacing between 0.6 n
+    and 1.4 n cells."""
     s = []
     for Ll in L:
-        gaps = rng.uniform(0.6, 1.4, Ll - 1) * b
+        gaps = rng.uniform(0.6, 1.4, Ll - 1) * n
         c = np.concatenate([[0.0], np.cumsum(gaps)])
-        s.append(np.rint(c / h) * h if on_grid else c)
-    N = tuple(int(np.ceil((s[l][-1] + b) / h)) for l in range(3))
+        s.append(np.rint(c) if on_grid else c)
+    N = tuple(int(np.ceil(s[l][-1] + n)) for l in range(3))
     return tuple(s), N
 
 
@@ -76,7 +77,7 @@ def test_direct_equals_brute_force_and_master_windows():
             for l in range(3):
                 assert _rows_close(Fa[l], F[l], 1e-13), l
     # an axis with a single lattice point and one with coinciding points
-    s = (np.array([0.0]), np.array([0.0, 0.0, 2.5 * b]), np.array([0.3 * b, 1.9 * b]))
+    s = (np.array([0.0]), np.array([0.0, 0.0, 2.5 * n]), np.array([0.3 * n, 1.9 * n]))
     N = (n, int(np.ceil(3.5 * n)), int(np.ceil(2.9 * n)))
     tl = TensorLattice(b, n, N, s)
     F, c = tensor_lattice_factors(tl, t, w, pos, Z)
@@ -98,7 +99,7 @@ def test_point_charges_away_from_the_charges():
     idx = np.stack([rng.integers(0, N[l], 3000) for l in range(3)], 1)
     centres = -0.5 * b + (idx + 0.5) * h
     imgs = np.array(np.meshgrid(s[0], s[1], s[2], indexing="ij")).reshape(3, -1).T
-    charges = (pos[:, None, :] + imgs[None]).reshape(-1, 3)
+    charges = (pos[:, None, :] + h * imgs[None]).reshape(-1, 3)
     q = np.repeat(Z, imgs.shape[0])
     d = np.linalg.norm(centres[:, None, :] - charges[None], axis=-1)
     keep = d.min(axis=1) > 5 * h
