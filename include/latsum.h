@@ -289,9 +289,27 @@ ls_status ls_forces_noalloc(const ls_lattice* lat, const ls_quad* quad, int32_t 
                             int32_t precision, double* F_dev, double* E_dev, hipStream_t stream);
 
 /*
+ * Richardson-regularised periodic sum on the reference cell (Sec. 3.2,
+ * Richardson extrapolation): the assembled periodic tensors of the lattices
+ * L and 2L (Lemma 3.2) combined in canonical form (Appendix, eq. conc) as
+ *   order 1: 2 P_L - P_2L        (sums that grow linearly in L),
+ *   order 2: (4 P_L - P_2L) / 3  (sums that grow quadratically in L);
+ * each is exact when P_L = P + c L^order. lat must be periodic; the images
+ * of 2L follow the even-L convention of the periodic cell.
+ * f0_dev, f1_dev, f2_dev: device [2K][n] FP64, K = M0 * quad->R: rows
+ * [0, K) hold the factors of lattice L, rows [K, 2K) those of lattice 2L.
+ * coef_dev: device [2K], (alpha Z_nu w_q, beta Z_nu w_q) with the weights
+ * above. Errors: LS_EINVAL (non-periodic lattice, order not 1 or 2, null
+ * pointers, and every error of ls_assemble).
+ */
+ls_status ls_richardson(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                        const double* pos_dev, const double* Z_dev, int32_t order,
+                        double* f0_dev, double* f1_dev, double* f2_dev, double* coef_dev,
+                        hipStream_t stream);
+
+/*
  * Canonical sum alpha A + beta B by concatenation of the factor matrices
- * (Appendix, eq. conc); used for the Richardson-regularised periodic sum
- * 2 P_L - P_2L (linear growth) or (4 P_L - P_2L)/3 (quadratic), Sec. 3.2.
+ * (Appendix, eq. conc), e.g. of two different systems.
  * A and B must have equal len[]; outputs: f_l [K_A + K_B][len_l] (rows of A,
  * then rows of B) and coef [K_A + K_B] = (alpha coef_A, beta coef_B), device.
  * Errors: LS_EINVAL.

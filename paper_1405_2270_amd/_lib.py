@@ -90,6 +90,10 @@ _SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Canon),
                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "ls_richardson": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.POINTER(Quad), ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
     "ls_canon_combine": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_double, ctypes.POINTER(Canon),
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),

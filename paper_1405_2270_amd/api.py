@@ -317,13 +317,20 @@ def richardson(lat, quad, pos, Z, order="linear"):
     """Richardson-regularised periodic sum on the reference cell (Sec. 3.2):
     the assembled periodic tensors at L and 2L combined as 2 P_L - P_2L
     (``linear``) or (4 P_L - P_2L)/3 (``quadratic``), in canonical form."""
-    if not lat.periodic:
-        raise ValueError("Richardson regularisation applies to the periodic cell")
-    lat2 = LatticeSpec(lat.b, lat.n, tuple(2 * v for v in lat.L), True)
-    F1, c1 = assemble(lat, quad, pos, Z)
-    F2, c2 = assemble(lat2, quad, pos, Z)
-    a, b = (2.0, -1.0) if order == "linear" else (4.0 / 3.0, -1.0 / 3.0)
-    return combine(F1, c1, a, F2, c2, b)
+    if order not in ("linear", "quadratic"):
+        raise ValueError("order must be 'linear' or 'quadratic'")
+    pos = _pos_tensor(pos)
+    M0 = pos.shape[0]
+    Z = _charges(Z, M0)
+    K2 = 2 * M0 * quad.R
+    dev = pos.device
+    F = [torch.empty((K2, lat.n), dtype=torch.float64, device=dev) for _ in range(3)]
+    coef = torch.empty(K2, dtype=torch.float64, device=dev)
+    check("ls_richardson", lib().ls_richardson(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0,
+                                               _ptr(pos), _ptr(Z), 1 if order == "linear" else 2,
+                                               _ptr(F[0]), _ptr(F[1]), _ptr(F[2]), _ptr(coef),
+                                               _stream()))
+    return F, coef
 
 
 def nuclear_matrix(F, coef, g, ws=None):

@@ -36,6 +36,14 @@ __global__ __launch_bounds__(256) void k_combine_coef(const double* __restrict__
   else if (i < Ka + Kb) out[i] = beta * cb[i - Ka];
 }
 
+// coef[0..K) *= alpha, coef[K..2K) *= beta (the two lattices of a Richardson sum)
+__global__ __launch_bounds__(256) void k_scale_coef(double* __restrict__ coef, int K, double alpha,
+                                                    double beta) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < K) coef[i] *= alpha;
+  else if (i < 2 * K) coef[i] *= beta;
+}
+
 // T[p][r] for pairs p = k*Nb + m, ranks r: 64 x 64 tiles, rank chunk of 16 cells.
 constexpr int NM_BM = 64, NM_BN = 64, NM_BK = 16;
 
@@ -176,4 +184,36 @@ extern "C" ls_status ls_nuclear_matrix(const ls_canon* P, int32_t Nb, const doub
   hipLaunchKernelGGL(k_face_reduce, dim3((Pn + 3) / 4), dim3(256), 0, stream, T, Pn, P->K, P->coef,
                      V_dev);
   return launch_status("ls_nuclear_matrix (reduce)");
+}
+
+extern "C" ls_status ls_richardson(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
+                                   const double* pos_dev, const double* Z_dev, int32_t order,
+                                   double* f0_dev, double* f1_dev, double* f2_dev,
+                                   double* coef_dev, hipStream_t stream) {
+  clear_error();
+  LS_REQUIRE(lat != nullptr && quad != nullptr, "null lattice or quadrature");
+  LS_REQUIRE(lat->periodic != 0, "Richardson extrapolation applies to the periodic cell");
+  LS_REQUIRE(order == 1 || order == 2, "order must be 1 (linear) or 2 (quadratic), got %d", order);
+  LS_REQUIRE(f0_dev && f1_dev && f2_dev && coef_dev, "null output pointer");
+  LS_REQUIRE(M0 >= 1 && quad->R >= 1, "M0 and R must be >= 1");
+  for (int l = 0; l < 3; ++l)
+    LS_REQUIRE(lat->L[l] >= 1 && lat->L[l] <= (1 << 29), "L[%d] out of range", l);
+  // Sec. 3.2: with p_L = p + c L^m (m = 1: sums that grow linearly in L,
+  // m = 2: quadratically), p = (2^m p_L - p_2L) / (2^m - 1)
+  const double alpha = order == 1 ? 2.0 : 4.0 / 3.0;
+  const double beta = order == 1 ? -1.0 : -1.0 / 3.0;
+  ls_lattice lat2 = *lat;
+  for (int l = 0; l < 3; ++l) lat2.L[l] = 2 * lat->L[l];
+  const size_t K = (size_t)M0 * quad->R;
+  const size_t n = (size_t)lat->n;
+  // rows [0, K): the lattice L; rows [K, 2K): the lattice 2L (eq. conc)
+  ls_status st = ls_assemble(lat, quad, M0, pos_dev, Z_dev, nullptr, 0, 0, f0_dev, f1_dev, f2_dev,
+                             coef_dev, stream);
+  if (st != LS_OK) return st;
+  st = ls_assemble(&lat2, quad, M0, pos_dev, Z_dev, nullptr, 0, 0, f0_dev + K * n,
+                   f1_dev + K * n, f2_dev + K * n, coef_dev + K, stream);
+  if (st != LS_OK) return st;
+  hipLaunchKernelGGL(k_scale_coef, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, stream,
+                     coef_dev, (int)K, alpha, beta);
+  return launch_status("ls_richardson");
 }

@@ -76,6 +76,22 @@ def test_invalid_host_arguments(lib):
     assert lib.ls_energy(None, None, 0, None, None, 0, None) == _lib.LS_EINVAL
     assert lib.ls_assemble(None, None, 1, None, None, None, 0, 0, None, None, None, None,
                            None) == _lib.LS_EINVAL
+    # Richardson sums: periodic lattices only, order 1 or 2 (nothing launched)
+    t2, w2 = np.array([1.0, 2.0]), np.array([0.5, 0.5])
+    quad = _lib.Quad(2, t2.ctypes.data_as(_lib.c_double_p), w2.ctypes.data_as(_lib.c_double_p))
+    box = _lib.Lattice(8, (ctypes.c_int32 * 3)(3, 3, 3), 10.0, 0)
+    per = _lib.Lattice(8, (ctypes.c_int32 * 3)(3, 3, 3), 10.0, 1)
+    dummy = ctypes.c_void_p(16)
+    for lat, order, needle in ((box, 1, b"periodic"), (per, 3, b"order"), (per, 0, b"order")):
+        st = lib.ls_richardson(ctypes.byref(lat), ctypes.byref(quad), 1, dummy, dummy, order,
+                               dummy, dummy, dummy, dummy, None)
+        assert st == _lib.LS_EINVAL and needle in lib.ls_last_error(), (order, lib.ls_last_error())
+    # the no-allocation forces refuse a problem beyond their fixed scratch on
+    # the host, before any device query
+    rho = _lib.Canon(8, (ctypes.c_int32 * 3)(24, 24, 24), (ctypes.c_void_p * 3)(16, 16, 16), 16)
+    st = lib.ls_forces_noalloc(ctypes.byref(box), ctypes.byref(quad), 20000, dummy, dummy,
+                               ctypes.byref(rho), 0, dummy, None, None)
+    assert st == _lib.LS_EWORKSPACE and b"scratch" in lib.ls_last_error()
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
     assert lib.ls_reconstruct_tiles(4) == 8 and lib.ls_reconstruct_workspace(None, 4) == 0
     assert lib.ls_reconstruct_workspace(None, 2) == 0
