@@ -159,6 +159,42 @@ ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                       double* f2_dev, double* coef_dev, hipStream_t stream);
 
 /*
+ * Non-equidistant tensor lattice (Sec. 3.1, remark after eq. EwaldTensorM0):
+ * lattice points at arbitrary coordinates per axis, image (k0, k1, k2) of
+ * atom nu at a_nu + h (s0[k0], s1[k1], s2[k2]). The 3D sum over every image
+ * triple splits into per-axis sums as in Theorem 3.1, so the result keeps
+ * rank K = M0 * R.
+ */
+typedef struct {
+  int32_t n;            /* cells per unit-cell edge, h = b / n */
+  double b;             /* unit-cell edge length, > 0 (positions as for ls_lattice) */
+  int32_t N[3];         /* grid cells per axis, cell g of axis l spanning
+                           [-b/2 + g h, -b/2 + (g+1) h]; 1 <= N[l] <= 2^26 */
+  int32_t L[3];         /* lattice coordinates per axis, 1 <= L[l] <= 2^24 */
+  const double* s[3];   /* device [L[l]]: lattice coordinates of axis l in units of
+                           h, any real values, repeats allowed (the equidistant box
+                           lattice is s_l[k] = k n) */
+} ls_tensor_lattice;
+
+/*
+ * Assembled canonical vectors of a tensor lattice: for r = nu*R + q,
+ *   f_l[r][g] = sum_k integral over cell g of exp(-t_q^2 (x - a_{nu,l} - h s_l[k])^2) dx,
+ * coef[r] = Z_nu w_q (the per-axis sums of Theorem 3.1 with the windows
+ * replaced by arbitrary shifts; each image's cell integrals at its own
+ * continuous position, all arithmetic FP64). derivative != 0: position
+ * derivatives of the same sums, coef_dev may be NULL.
+ * f0_dev, f1_dev, f2_dev: device [K][N[l]] FP64, written; coef_dev: device [K].
+ * Work per call: K (N0 L0 + N1 L1 + N2 L2) cell offsets, the cell integral
+ * only where the Gaussian's support reaches the cell. A coordinate beyond
+ * +-1e9 cells counts as +-1e9; a non-finite one gives NaN in its vectors.
+ * Errors: LS_EINVAL (bad sizes, null pointers), LS_EUNSUPPORTED (R > 160).
+ */
+ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad, int32_t M0,
+                             const double* pos_dev, const double* Z_dev, int32_t derivative,
+                             double* f0_dev, double* f1_dev, double* f2_dev, double* coef_dev,
+                             hipStream_t stream);
+
+/*
  * Reconstruction of sub-boxes of a canonical tensor (Appendix, eq. CP_form):
  *   out_b[i][j][k] = scale * sum_r coef[r] f0[r][o0+i] f1[r][o1+j] f2[r][o2+k]
  * for each box b, as one GEMM per box with rows (i, j), columns k and the

@@ -271,6 +271,24 @@ def tensor_lattice_factors(tl, t, w, pos, Z, derivative=False):
     return F, coef
 
 
+def tensor_lattice_entries(tl, t, pos, l, g, derivative=False):
+    """Columns g of ``tensor_lattice_factors``' factor F[l] only (to sample
+    full-size lattices). Returns shape (M0*R, len(g))."""
+    t = np.asarray(t, np.float64)
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    g = np.asarray(g, np.float64)
+    cell = gauss_cell_integral_dpos if derivative else gauss_cell_integral
+    out = np.zeros((pos.shape[0] * t.size, g.size))
+    for nu in range(pos.shape[0]):
+        acc = np.zeros((t.size, g.size))
+        a = pos[nu, l] + 0.5 * tl.b
+        for sk in np.asarray(tl.s[l], np.float64):
+            acc += cell(t[:, None], ((g - sk) * tl.h - a)[None, :],
+                        ((g + 1.0 - sk) * tl.h - a)[None, :], tl.h)
+        out[nu * t.size:(nu + 1) * t.size] = acc
+    return out
+
+
 def tensor_lattice_assembled(tl, t, w, pos, Z):
     """The same sum by the paper's route when every lattice coordinate is a
     whole number of cells (s_l[k] = m_k): one master vector per (atom, axis)

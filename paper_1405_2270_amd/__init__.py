@@ -5,15 +5,15 @@ kernel vectors -> lattice assembly -> energy / reconstruction, plus forces by
 the adjoint. All arithmetic runs in the HIP library ``liblatsum.so``; this
 package only marshals torch tensors into its C ABI.
 """
-from .api import (LatticeSpec, QuadTable, quadrature, master_halfwidth, kernel_vectors, assemble,
-                  assemble_into,
+from .api import (LatticeSpec, TensorLatticeSpec, QuadTable, quadrature, master_halfwidth,
+                  kernel_vectors, assemble, assemble_into, assemble_tensor,
                   reconstruct, reconstruct_into, reconstruct_prepare, reconstruct_tiles, energy, forces,
                   LatticeEnergy,
                   lattice_energy, Batch, combine, richardson,
                   nuclear_matrix, probe_copy, probe_mfma)
 
-__all__ = ["LatticeSpec", "QuadTable", "quadrature", "master_halfwidth", "kernel_vectors",
-           "assemble", "assemble_into", "reconstruct", "reconstruct_into", "reconstruct_prepare",
+__all__ = ["LatticeSpec", "TensorLatticeSpec", "QuadTable", "quadrature", "master_halfwidth",
+           "kernel_vectors", "assemble", "assemble_into", "assemble_tensor", "reconstruct", "reconstruct_into", "reconstruct_prepare",
            "reconstruct_tiles", "energy", "forces",
            "LatticeEnergy", "lattice_energy", "Batch", "combine", "richardson",
            "nuclear_matrix", "probe_copy", "probe_mfma"]

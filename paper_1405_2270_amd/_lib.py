@@ -34,6 +34,11 @@ class Canon(ctypes.Structure):
                 ("f", ctypes.c_void_p * 3), ("coef", ctypes.c_void_p)]
 
 
+class TensorLattice(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("b", ctypes.c_double), ("N", ctypes.c_int32 * 3),
+                ("L", ctypes.c_int32 * 3), ("s", ctypes.c_void_p * 3)]
+
+
 class Box(ctypes.Structure):
     _fields_ = [("o", ctypes.c_int32 * 3), ("e", ctypes.c_int32 * 3)]
 
@@ -65,6 +70,10 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_assemble_tensor": (ctypes.c_int, [ctypes.POINTER(TensorLattice), ctypes.POINTER(Quad),
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ls_reconstruct": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Lattice, Quad, Canon, Box, System, check, lib
+from ._lib import Lattice, Quad, Canon, Box, System, TensorLattice, check, lib
 
 
 def _stream():
@@ -61,6 +61,30 @@ class LatticeSpec:
 
     def c(self):
         return Lattice(self.n, (ctypes.c_int32 * 3)(*self.L), self.b, int(self.periodic))
+
+
+class TensorLatticeSpec:
+    """Non-equidistant tensor lattice: unit cell edge b, n cells per edge
+    (h = b/n), N[l] grid cells per axis and the lattice coordinates s[l] of
+    each axis in units of h (three 1D float64 device tensors)."""
+
+    def __init__(self, b, n, N, s):
+        self.b, self.n, self.N = float(b), int(n), tuple(int(v) for v in N)
+        if len(self.N) != 3 or len(s) != 3:
+            raise ValueError("three axes are required")
+        self.s = tuple(_dev_f64(x, f"s[{l}]").reshape(-1) for l, x in enumerate(s))
+        for l, x in enumerate(self.s):
+            if not x.is_contiguous() or x.numel() < 1:
+                raise ValueError(f"s[{l}] must be a non-empty contiguous vector")
+
+    @property
+    def h(self):
+        return self.b / self.n
+
+    def c(self):
+        return TensorLattice(self.n, self.b, (ctypes.c_int32 * 3)(*self.N),
+                             (ctypes.c_int32 * 3)(*[x.numel() for x in self.s]),
+                             (ctypes.c_void_p * 3)(*[x.data_ptr() for x in self.s]))
 
 
 class QuadTable:
@@ -116,6 +140,28 @@ def assemble(lat, quad, pos, Z, masters=None, derivative=False):
     F = [torch.empty((K, lat.N(l)), dtype=torch.float64, device=dev) for l in range(3)]
     coef = None if derivative else torch.empty(K, dtype=torch.float64, device=dev)
     return assemble_into(lat, quad, pos, Z, masters, F, coef, derivative)
+
+
+def assemble_tensor(tl, quad, pos, Z, derivative=False):
+    """Assembled factors of a non-equidistant tensor lattice (``TensorLatticeSpec``):
+    [f0, f1, f2] ([K][N_l] FP64 each) and coef [K] (None for derivatives)."""
+    pos = _pos_tensor(pos)
+    M0 = pos.shape[0]
+    K = M0 * quad.R
+    dev = pos.device
+    for x in tl.s:
+        if x.device != dev:
+            raise ValueError("lattice coordinates and positions must be on one device")
+    F = [torch.empty((K, tl.N[l]), dtype=torch.float64, device=dev) for l in range(3)]
+    coef = None
+    if not derivative:
+        Z = _charges(Z, M0)
+        coef = torch.empty(K, dtype=torch.float64, device=dev)
+    check("ls_assemble_tensor", lib().ls_assemble_tensor(
+        ctypes.byref(tl.c()), ctypes.byref(quad.c()), M0, _ptr(pos),
+        _ptr(None if derivative else Z), int(derivative), _ptr(F[0]), _ptr(F[1]), _ptr(F[2]),
+        _ptr(coef), _stream()))
+    return F, coef
 
 
 def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):

@@ -172,6 +172,79 @@ __global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict
   out[g] = deriv ? acc : lat.h * acc;
 }
 
+// Non-equidistant tensor lattice (Sec. 3.1, remark after eq. EwaldTensorM0):
+// the lattice coordinates of each axis are arbitrary (units of the cell), so
+// every image has its own sub-cell offset and no master vector is shared;
+// each cell integral is generated in registers, one lane per output cell.
+// The coordinates of the axis pass through LDS 256 at a time, split into an
+// integer part and a fraction, so the cell offset
+//   y0 = (g - p - I_k) - (delta + phi_k)
+// takes its lattice-size part as an exact integer (the rounding of y0 stays
+// at the level of the charge's own sub-cell offset). Coordinates beyond
+// +-1e9 cells are clamped there (exact zeros on any grid this library takes);
+// a non-finite coordinate gives NaN outputs. Memory indices depend on g and
+// k only.
+struct TLat {
+  int n;
+  double b, h;
+  int N[3];
+  int L[3];
+  const double* s[3];
+};
+
+__global__ __launch_bounds__(256) void k_assemble_tensor(const double* __restrict__ pos,
+                                                          QuadArg qa, TLat tl, int deriv,
+                                                          double* __restrict__ f0,
+                                                          double* __restrict__ f1,
+                                                          double* __restrict__ f2,
+                                                          const double* __restrict__ Z,
+                                                          double* __restrict__ coef) {
+  __shared__ int sI[256];
+  __shared__ double sF[256];
+  const int q = blockIdx.y;
+  const int c = blockIdx.z;
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int N = tl.N[l];
+  if ((int)blockIdx.x * 256 >= N) return;  // whole workgroup beyond this axis
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (coef != nullptr && g == 0 && l == 0) coef[nu * qa.R + q] = Z[nu] * qa.w[q];
+  int p;
+  double delta;
+  node_offset(pos[c], tl.b, tl.h, tl.n, &p, &delta);
+  const double tau = qa.tau[q];
+  const double hw = support_halfwidth(tau);
+  const double* s = tl.s[l];
+  const int L = tl.L[l];
+  double acc = 0.0;
+  for (int k0 = 0; k0 < L; k0 += 256) {
+    __syncthreads();
+    if (k0 + (int)threadIdx.x < L) {
+      const double v = s[k0 + threadIdx.x];
+      if (v == v && fabs(v) <= 1e300) {
+        const double fl = floor(fmin(fmax(v, -1e9), 1e9));
+        sI[threadIdx.x] = (int)fl;
+        sF[threadIdx.x] = fmin(fmax(v, -1e9), 1e9) - fl;
+      } else {
+        sI[threadIdx.x] = 0;
+        sF[threadIdx.x] = __builtin_nan("");
+      }
+    }
+    __syncthreads();
+    const int kn = min(256, L - k0);
+    if (g < N) {
+      for (int j = 0; j < kn; ++j) {
+        const double y0 = (double)(g - p - sI[j]) - (delta + sF[j]);
+        if (y0 > hw || y0 < -hw) continue;  // the whole cell beyond the support: exactly 0
+        acc += deriv ? cell_derivative(tau, y0) : cell_integral(tau, y0);
+      }
+    }
+  }
+  if (g < N) {
+    double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * qa.R + q) * (size_t)N;
+    out[g] = deriv ? acc : tl.h * acc;
+  }
+}
+
 }  // namespace ls
 
 using namespace ls;
@@ -254,4 +327,43 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
 #undef LS_ASM
   }
   return launch_status("ls_assemble");
+}
+
+extern "C" ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad,
+                                        int32_t M0, const double* pos_dev, const double* Z_dev,
+                                        int32_t derivative, double* f0_dev, double* f1_dev,
+                                        double* f2_dev, double* coef_dev, hipStream_t stream) {
+  clear_error();
+  LS_REQUIRE(tlat != nullptr, "tensor lattice descriptor is null");
+  LS_REQUIRE(tlat->n >= 1, "n must be >= 1 (got %d)", tlat->n);
+  LS_REQUIRE(std::isfinite(tlat->b) && tlat->b > 0.0, "b must be finite and > 0");
+  TLat tl;
+  tl.n = tlat->n;
+  tl.b = tlat->b;
+  tl.h = tlat->b / tlat->n;
+  int Nmax = 0;
+  for (int l = 0; l < 3; ++l) {
+    LS_REQUIRE(tlat->N[l] >= 1 && tlat->N[l] <= (1 << 26), "N[%d] must be in [1, 2^26] (got %d)",
+               l, tlat->N[l]);
+    LS_REQUIRE(tlat->L[l] >= 1 && tlat->L[l] <= (1 << 24), "L[%d] must be in [1, 2^24] (got %d)",
+               l, tlat->L[l]);
+    LS_REQUIRE(tlat->s[l] != nullptr, "lattice coordinates of axis %d are null", l);
+    tl.N[l] = tlat->N[l];
+    tl.L[l] = tlat->L[l];
+    tl.s[l] = tlat->s[l];
+    Nmax = std::max(Nmax, tl.N[l]);
+  }
+  QuadArg qa;
+  ls_status st = check_quad(quad, tl.h, &qa);
+  if (st != LS_OK) return st;
+  LS_REQUIRE(M0 >= 1 && M0 <= 20000, "M0 must be in [1, 20000] (got %d)", M0);
+  LS_REQUIRE(pos_dev != nullptr && f0_dev != nullptr && f1_dev != nullptr && f2_dev != nullptr,
+             "null device pointer");
+  LS_REQUIRE(derivative || (Z_dev != nullptr && coef_dev != nullptr),
+             "Z and coef are required for value vectors");
+  dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
+  hipLaunchKernelGGL(k_assemble_tensor, grid, dim3(256), 0, stream, pos_dev, qa, tl,
+                     derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, Z_dev,
+                     derivative ? nullptr : coef_dev);
+  return launch_status("ls_assemble_tensor");
 }

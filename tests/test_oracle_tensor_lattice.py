@@ -15,7 +15,8 @@ per-axis sums.
 import numpy as np
 
 from oracle.lattice import (Geometry, TensorLattice, direct_factors, tensor_lattice_factors,
-                            tensor_lattice_assembled, tensor_lattice_brute_force)
+                            tensor_lattice_assembled, tensor_lattice_brute_force,
+                            tensor_lattice_entries)
 from oracle.canonical import reconstruct, sample
 from oracle.quadrature import rule_s
 from workloads import rule_s_params
@@ -128,3 +129,20 @@ def test_derivative_factors_are_central_differences():
         fd = (Fp[l] - Fm[l]) / (2 * step)
         scale = np.max(np.abs(dF[l]))
         assert np.max(np.abs(fd - dF[l])) < 1e-6 * scale, l
+
+
+def test_sampled_columns_match_full_factors():
+    b, n = 6.0, 6
+    rng = np.random.default_rng(25)
+    t, w = _quad(29, n, b)
+    s, N = _irregular(rng, b, n, (3, 2, 2), False)
+    tl = TensorLattice(b, n, N, s)
+    pos = -0.5 * b + rng.uniform(0, 1, (2, 3)) * b
+    for deriv in (False, True):
+        F, _ = tensor_lattice_factors(tl, t, w, pos, [1.0, -1.0], derivative=deriv)
+        for l in range(3):
+            g = np.sort(rng.choice(N[l], 5, replace=False))
+            # the same definition on fewer columns (vectorised sums may round
+            # differently in the last bit)
+            got = tensor_lattice_entries(tl, t, pos, l, g, deriv)
+            assert np.max(np.abs(got - F[l][:, g])) <= 1e-15 * np.max(np.abs(F[l]))

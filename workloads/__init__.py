@@ -11,8 +11,10 @@ uses; ``small_*`` generators give oracle-sized cases of the same structure.
 """
 from .configs import (System, Density, make_density, rule_s_params, quad_spec,
                       config1, config2, config3, config4, config5,
-                      small_box, small_periodic, make_basis, CONFIGS)
+                      small_box, small_periodic, make_basis, CONFIGS, tensor_coords,
+                      small_tensor, config_tensor, config_slab)
 
 __all__ = ["System", "Density", "make_density", "rule_s_params", "quad_spec",
            "config1", "config2", "config3", "config4", "config5",
-           "small_box", "small_periodic", "make_basis", "CONFIGS"]
+           "small_box", "small_periodic", "make_basis", "CONFIGS", "tensor_coords",
+           "small_tensor", "config_tensor", "config_slab"]

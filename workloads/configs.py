@@ -104,9 +104,10 @@ def quad_spec(rule, M, n, L, periodic, b, C0=1.0):
     return {"rule": "S", "M": int(M), "C0": float(C0s), "s": float(s_grid * n / b)}
 
 
-def make_density(b, n, L, periodic, rng, R_rho=8):
+def make_density(b, n, L, periodic, rng, R_rho=8, N=None):
     D = []
-    N = [n if periodic else L[l] * n for l in range(3)]
+    if N is None:
+        N = [n if periodic else L[l] * n for l in range(3)]
     lo = -0.5 * b
     edge = [N[l] * b / n for l in range(3)]
     d = rng.uniform(0.5, 1.5, R_rho)
@@ -265,3 +266,65 @@ def make_basis(sysm, Nb, seed=7):
         mid = -0.5 * sysm.b + (np.arange(N) + 0.5) * sysm.h
         g.append(np.exp(-alpha[:, None] * (mid[None, :] - centres[:, l, None]) ** 2))
     return g
+
+
+def tensor_coords(rng, L, n, jitter, on_grid=False):
+    """Lattice coordinates of one axis of a non-equidistant tensor lattice, in
+    cells: k n plus a seeded displacement uniform in [-jitter, jitter] n per
+    lattice plane (rounded to whole cells if ``on_grid``), sorted."""
+    c = np.arange(L) * float(n) + rng.uniform(-jitter, jitter, L) * n
+    c = np.sort(c - c.min())
+    return np.rint(c) if on_grid else c
+
+
+def _tensor_system(name, rng, b, n, L, frac, Z, M, jitter, on_grid, nbox, box_edge, seed):
+    s = tuple(tensor_coords(rng, L[l], n, jitter, on_grid) for l in range(3))
+    N = tuple(int(np.ceil(s[l][-1])) + n for l in range(3))
+    C0, s_grid = rule_s_params(M, max(N))
+    quad = {"rule": "S", "M": int(M), "C0": float(C0), "s": float(s_grid * n / b)}
+    dens = make_density(b, n, L, False, rng, N=N)
+    boxes = []
+    for _ in range(nbox):
+        e = [min(box_edge, N[l]) if box_edge else int(rng.integers(1, N[l] + 1)) for l in range(3)]
+        o = [int(rng.integers(0, N[l] - e[l] + 1)) for l in range(3)]
+        boxes.append(o + e)
+    sysm = System(name, b, n, tuple(L), False, frac_to_pos(frac, b), Z, quad, dens,
+                  np.array(boxes, np.int64), seed)
+    sysm.extra["s"] = s
+    sysm.extra["N"] = N
+    return sysm
+
+
+def small_tensor(seed, n=12, L=(3, 2, 4), M0=3, jitter=0.3, on_grid=False, nbox=3, b=10.0):
+    """Oracle-sized non-equidistant tensor lattice (lattice coordinates in
+    extra["s"], grid cells per axis in extra["N"])."""
+    rng = np.random.default_rng(seed)
+    frac = rng.uniform(0.0, 1.0, (M0, 3))
+    Z = neutralise(rng.choice([-2.0, -1.0, 1.0, 2.0], M0), rng) if M0 > 1 else np.ones(1)
+    return _tensor_system(f"small_tensor[{seed}]", rng, b, n, L, frac, Z, 29, jitter, on_grid,
+                          nbox, 0, seed)
+
+
+def config_tensor():
+    """The headline structure on a non-equidistant tensor lattice: 32 lattice
+    planes per axis at k n + U[-0.25, 0.25] n cells (n = 128, b = 10), the
+    8-site rock-salt cell of the box workload, rule S R=48, 16 sub-boxes of
+    256^3 cells, rank-8 density."""
+    rng = np.random.default_rng(140500 + 6)
+    b, n, L = 10.0, 128, (32, 32, 32)
+    A = [(.25, .25, .25), (.25, .75, .75), (.75, .25, .75), (.75, .75, .25)]
+    B = [(.75, .75, .75), (.75, .25, .25), (.25, .75, .25), (.25, .25, .75)]
+    frac = np.array(A + B) + rng.uniform(-0.05, 0.05, (8, 3))
+    Z = np.array([1.0] * 4 + [-1.0] * 4)
+    return _tensor_system("cfg_tensor", rng, b, n, L, frac, Z, 47, 0.25, False, 16, 256, 140506)
+
+
+def config_slab(L, n=128, slab=True):
+    """Table 3.1's lattices of unit charges: L x L x 1 (slab) or L x L x L, one
+    charge at the centre of each cell (b = 10, n cells per edge), rule S R=48."""
+    b = 10.0
+    Ls = (L, L, 1) if slab else (L, L, L)
+    pos = frac_to_pos([[0.5, 0.5, 0.5]], b)
+    quad = quad_spec("S", 47, n, Ls, False, b)
+    return System(f"slab[{L}]" if slab else f"cube[{L}]", b, n, Ls, False, pos, np.array([1.0]),
+                  quad, None, None, 140507)
