@@ -24,6 +24,8 @@ canonical   canonical-format operations (Appendix: eqs. CP_form, scal, had,
             conc): reconstruction, scalar product, Hadamard product.
 physics     energy against a charge density, forces (adjoint and central
             finite differences), Richardson extrapolation (Sec. 3.2).
+qtt         quantics-TT compression of assembled vectors (Sec. 4, eq.
+            EwaldTensorQTT) by TT-SVD, and its expansion.
 
 Parity status of every function is listed in its module header.
 """
