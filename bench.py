@@ -80,6 +80,8 @@ def parse():
                    help="processes for the oracle baseline (0: the usable CPUs, at most 16)")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-periodic", action="store_true")
+    p.add_argument("--no-tensor", action="store_true")
+    p.add_argument("--no-table31", action="store_true")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--mode", choices=["bench", "kernels"], default="bench",
                    help="kernels: one launch of each hot-path kernel on the headline workload "
@@ -256,6 +258,142 @@ def bench_periodic(L, T, steps, warmup, truth=None):
     return res
 
 
+# Sec. 3.1, Table 3.1: seconds of the paper's assembled lattice sum (Matlab, a
+# cluster of 8 dual-core AMD Opteron processors; n and R not stated), quoted as
+# context beside the same sums on the GPU
+TABLE_3_1_SECONDS = {
+    "slab": {2: 0.003, 4: 0.004, 8: 0.0073, 16: 0.025, 32: 0.128, 64: 0.65, 128: 2.96},
+    "cube": {2: 0.003, 4: 0.005, 8: 0.0098, 16: 0.039, 32: 0.19, 64: 0.88, 128: 4.01},
+}
+
+
+def bench_table31(L, T, reps=20):
+    """Table 3.1's lattices on the GPU: L x L x 1 and L x L x L lattices of
+    unit charges at the cell centres (n = 128, rule S R = 48), the assembled
+    canonical vectors of the whole lattice sum (kernel vectors, then the
+    assembly) per L; milliseconds per sum from HIP events over back-to-back
+    calls on the launch stream (inputs resident)."""
+    import torch
+    from workloads import config_slab
+    stream = torch.cuda.current_stream()
+    out = {}
+    for kind in ("slab", "cube"):
+        rows = {}
+        for Lv in (2, 4, 8, 16, 32, 64, 128):
+            s = config_slab(Lv, slab=(kind == "slab"))
+            q = s.quad
+            spec = L.LatticeSpec(s.b, s.n, s.L, False)
+            qt = L.quadrature("S", q["M"], q["C0"], q["s"])
+            pos, Z = T(s.pos), T(s.Z)
+            m = L.kernel_vectors(spec, qt, pos)
+            F = [torch.empty((s.K, s.N(l)), dtype=torch.float64, device=pos.device) for l in range(3)]
+            c = torch.empty(s.K, dtype=torch.float64, device=pos.device)
+
+            def one():
+                L.api.kernel_vectors_into(spec, qt, pos, m)
+                L.assemble_into(spec, qt, pos, Z, m, F, c)
+            one()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                one()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows[str(Lv)] = {"ms": round(ms, 4), "paper_s": TABLE_3_1_SECONDS[kind][Lv],
+                             "grid": list(s.N(l) for l in range(3))}
+            del m, F, c
+        out[kind] = rows
+    out["note"] = ("one charge per cell, n=128 cells per unit-cell edge, R=48; the paper's "
+                   "Matlab/Opteron seconds (Table 3.1) beside, as context: its n and R differ")
+    return out
+
+
+def bench_tensor(L, T, steps, warmup, truth=None):
+    """Non-equidistant tensor lattice (32 planes per axis at k n + U[-n/4, n/4]
+    cells, the headline's 8-site cell, R=48): one step = tensor-lattice
+    assembly (every image's cell integrals in registers), the energy and the
+    FP16x3 reconstruction of 16 sub-boxes of 256^3, replayed from a graph."""
+    import ctypes
+    import numpy as np
+    import torch
+    from workloads import config_tensor
+    s = config_tensor()
+    q = s.quad
+    qt = L.quadrature("S", q["M"], q["C0"], q["s"])
+    tl = L.TensorLatticeSpec(s.b, s.n, s.extra["N"], [T(x) for x in s.extra["s"]])
+    pos, Z = T(s.pos), T(s.Z)
+    D = [T(x) for x in s.density.D]
+    d = T(s.density.d)
+    boxes = [tuple(int(v) for v in b) for b in s.boxes]
+    nv = sum(b[3] * b[4] * b[5] for b in boxes)
+    F0, c0 = L.assemble_tensor(tl, qt, pos, Z)
+    cn = L.api._canon(F0, c0)
+    lib = L.api.lib()
+    rws = torch.empty(lib.ls_reconstruct_workspace(ctypes.byref(cn), L._lib.PRECISIONS["f16x3"]),
+                      dtype=torch.uint8, device=pos.device)
+    ews = torch.empty(lib.ls_energy_workspace(s.K, 8), dtype=torch.uint8, device=pos.device)
+    res = {}
+    stream = torch.cuda.current_stream()
+    outs = {}
+    for prec in ("f64", "f16x3"):
+        out = torch.empty(nv, dtype=torch.float64 if prec == "f64" else torch.float32,
+                          device=pos.device)
+
+        def step():
+            F, c = L.assemble_tensor(tl, qt, pos, Z)
+            E = L.energy(F, c, D, d, "f64", ews)
+            L.reconstruct_into(F, c, boxes, out, 1.0 / s.h ** 3, prec, 0, rws)
+            return E
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            gE = step()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = {"ms_per_step": round(ms, 4), "values_per_s": nv / (ms / 1e3)}
+        outs[prec] = out
+        res["energy"] = float(gE.cpu())
+    # the tensor-lattice assembly alone: cell offsets K * sum_l N_l L_l
+    Fa = [torch.empty_like(f) for f in F0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        L.api.assemble_tensor_into(tl, qt, pos, Z, Fa, c0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ams = e0.elapsed_time(e1) / 5
+    offsets = s.K * sum(s.extra["N"][l] * len(s.extra["s"][l]) for l in range(3))
+    res["assembly_ms"] = round(ams, 4)
+    res["cell_offsets_per_s"] = offsets / (ams / 1e3)
+    if truth is not None:
+        sel_local, sel, ref, ref_abs = truth
+        b0 = boxes[0]
+        for prec in ("f64", "f16x3"):
+            V = outs[prec][:b0[3] * b0[4] * b0[5]].view(b0[3], b0[4], b0[5])
+            got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
+            err = float(np.max(np.abs(got.double().cpu().numpy() - ref)))
+            res[prec]["rel_inf_vs_oracle"] = err / float(np.max(np.abs(ref)))
+            res[prec]["rel_mag_vs_oracle"] = err / float(np.max(np.abs(ref_abs)))
+        res["oracle_sample"] = "6^3 points of box 0 (6 seeded cells per axis), extended precision"
+    res["workload"] = ("non-equidistant tensor lattice, 32 planes per axis at k n + U[-n/4, n/4] "
+                       "cells, n=128, 8 charges per cell (rock-salt +-1), R=48, 16 sub-boxes 256^3")
+    return res
+
+
 def host_cpu():
     """Host CPU description: logical CPUs, CPUs this process may run on, and
     the model name from /proc/cpuinfo."""
@@ -391,6 +529,24 @@ def oracle_truths(workers, batch_count, batch_sample=4, force_atoms=(0, 17, 42))
         cost = [s.n ** 3 * s.K for s in systems]
         idx = [int(i) for i in np.argsort(cost, kind="stable")[:batch_sample]]
         out["batch"] = (idx, pool.map(_batch_system_truth, [systems[i] for i in idx]))
+        from oracle.lattice import TensorLattice, tensor_lattice_entries
+        from workloads import config_tensor
+        ct = config_tensor()
+        q = ct.quad
+        t, w = rule_s(q["M"], q["C0"], q["s"])
+        otl = TensorLattice(ct.b, ct.n, ct.extra["N"], ct.extra["s"])
+        b0 = ct.boxes[0]
+        rng = np.random.default_rng(8)
+        sel_local = [np.sort(rng.choice(int(b0[3 + l]), 6, replace=False)) for l in range(3)]
+        cols = pool.starmap(tensor_lattice_entries, [(otl, t, ct.pos, l, b0[l] + sel_local[l])
+                                                     for l in range(3)])
+        sel = np.array(np.meshgrid(np.arange(6), np.arange(6), np.arange(6),
+                                   indexing="ij")).reshape(3, -1).T
+        coef = (ct.Z[:, None] * w[None, :]).ravel()
+        h3 = ct.h ** 3
+        out["tensor"] = (sel_local, sel,
+                         np.asarray(sample_columns(cols, coef, sel), np.float64) / h3,
+                         np.asarray(sample_columns(cols, np.abs(coef), sel), np.float64) / h3)
         c5 = config5()
         q = c5.quad
         t, w = rule_s(q["M"], q["C0"], q["s"])
@@ -805,6 +961,9 @@ def main():
 
     batched = None if args.no_batch else bench_batch(
         L, T, args.batch_count, args.steps, 1, truth=truths["batch"] if truths else None)
+    tensor = None if args.no_tensor else bench_tensor(
+        L, T, args.steps, 1, truths["tensor"] if truths else None)
+    table31 = None if args.no_table31 else bench_table31(L, T)
     periodic = None if args.no_periodic else bench_periodic(
         L, T, args.steps, 1, truths["periodic"] if truths else None)
 
@@ -849,6 +1008,8 @@ def main():
         "kernel_vectors": kernel_vectors,
         "energy_roofline": energy_roofline,
         "measured_peaks": peaks,
+        "tensor_lattice": tensor,
+        "table_3_1": table31,
         "cpu_baseline": cpu,
         "cpu_context": {"config1_full_oracle": cpu_c1} if cpu_c1 else None,
     }

@@ -122,9 +122,19 @@ def master_halfwidth(lat):
 def kernel_vectors(lat, quad, pos, derivative=False):
     """Master vectors [M0*3][R][2X] (FP64) for every atom and axis."""
     pos = _pos_tensor(pos)
+    X = master_halfwidth(lat)
+    out = torch.empty((pos.shape[0] * 3, quad.R, 2 * X), dtype=torch.float64, device=pos.device)
+    return kernel_vectors_into(lat, quad, pos, out, derivative)
+
+
+def kernel_vectors_into(lat, quad, pos, out, derivative=False):
+    """As ``kernel_vectors`` but into a caller-provided tensor of M0*3*R*2X doubles."""
+    pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     X = master_halfwidth(lat)
-    out = torch.empty((M0 * 3, quad.R, 2 * X), dtype=torch.float64, device=pos.device)
+    out = _dev_f64(out, "masters")
+    if out.numel() != M0 * 3 * quad.R * 2 * X or not out.is_contiguous():
+        raise ValueError(f"masters must be contiguous with M0*3*R*2X = {M0 * 3 * quad.R * 2 * X} values")
     check("ls_kernel_vectors", lib().ls_kernel_vectors(ctypes.byref(lat.c()), ctypes.byref(quad.c()),
                                                        M0, _ptr(pos), X, int(derivative), _ptr(out),
                                                        _stream()))
@@ -153,10 +163,24 @@ def assemble_tensor(tl, quad, pos, Z, derivative=False):
         if x.device != dev:
             raise ValueError("lattice coordinates and positions must be on one device")
     F = [torch.empty((K, tl.N[l]), dtype=torch.float64, device=dev) for l in range(3)]
-    coef = None
+    coef = None if derivative else torch.empty(K, dtype=torch.float64, device=dev)
+    return assemble_tensor_into(tl, quad, pos, Z, F, coef, derivative)
+
+
+def assemble_tensor_into(tl, quad, pos, Z, F, coef, derivative=False):
+    """As ``assemble_tensor`` but into caller-provided factors F and coef."""
+    pos = _pos_tensor(pos)
+    M0 = pos.shape[0]
+    K = M0 * quad.R
+    for l in range(3):
+        f = _dev_f64(F[l], "factor")
+        if tuple(f.shape) != (K, tl.N[l]) or not f.is_contiguous():
+            raise ValueError(f"factor {l} must be contiguous with shape {(K, tl.N[l])}")
     if not derivative:
         Z = _charges(Z, M0)
-        coef = torch.empty(K, dtype=torch.float64, device=dev)
+        coef = _dev_f64(coef, "coef")
+        if coef.numel() != K:
+            raise ValueError("coef must have K entries")
     check("ls_assemble_tensor", lib().ls_assemble_tensor(
         ctypes.byref(tl.c()), ctypes.byref(quad.c()), M0, _ptr(pos),
         _ptr(None if derivative else Z), int(derivative), _ptr(F[0]), _ptr(F[1]), _ptr(F[2]),
