@@ -355,6 +355,43 @@ ls_status ls_canon_combine(const ls_canon* A, double alpha, const ls_canon* B, d
                            hipStream_t stream);
 
 /*
+ * Quantics-TT compression of canonical vectors (Sec. 4, eq. EwaldTensorQTT;
+ * Appendix: TT format, eq. tt, and binary folding). Each of nvec vectors of
+ * length len (row v at x_dev + v * ld, device, FP64; e.g. the rows of an
+ * assembled factor matrix, ld = len = N_l) is zero-padded to 2^d entries,
+ * d = ls_qtt_digits(len), folded into a 2 x ... x 2 tensor of order d with
+ * the most significant binary digit first, and decomposed by the TT-SVD:
+ * left to right, each unfolding (rows (alpha_{k-1}, j_k)) is decomposed by an
+ * SVD, and the kept left singular vectors form core k. r_k is the smallest
+ * rank whose discarded singular values have Euclidean norm
+ * <= eps ||x||_2 / sqrt(d - 1), so that ||x - x_QTT||_2 <= eps ||x||_2
+ * (eps = 0: every non-zero singular value kept). FP64 throughout.
+ * Outputs (device, caller-owned):
+ *   cores_dev  [nvec][cap] doubles: core k of vector v (k = 1..d) at offset
+ *              sum_{j<k} 2 r_{j-1} r_j of its slot, shape [r_{k-1}][2][r_k]
+ *              row-major; storage per vector sum_k 2 r_{k-1} r_k;
+ *   ranks_dev  [nvec][d + 1]: r_0 .. r_d (r_0 = r_d = 1);
+ *   status_dev [nvec]: 1 = compressed; -1 = a rank above 32 would be needed
+ *              (the next unfolding would not fit); -2 = the cores exceed cap;
+ *              -3 = the SVD did not converge. Only status 1 vectors have
+ *              valid ranks and cores.
+ * Limits: len <= 4096 (d <= 12), r_k <= 32. Errors: LS_EINVAL.
+ */
+int32_t ls_qtt_digits(int32_t len);
+ls_status ls_qtt_compress(const double* x_dev, int32_t nvec, int32_t len, int64_t ld, double eps,
+                          int32_t cap, double* cores_dev, int32_t* ranks_dev, int32_t* status_dev,
+                          hipStream_t stream);
+/*
+ * The vectors QTT cores represent (eq. tt): y_dev[v * ld + i], i < len, for the
+ * output of ls_qtt_compress with the same nvec, len and cap (cores of at most
+ * 8192 doubles per vector). Vectors whose status is not 1, or whose ranks or
+ * core total are out of range, are written as NaN. Errors: LS_EINVAL.
+ */
+ls_status ls_qtt_expand(const double* cores_dev, const int32_t* ranks_dev,
+                        const int32_t* status_dev, int32_t nvec, int32_t len, int32_t cap,
+                        double* y_dev, int64_t ld, hipStream_t stream);
+
+/*
  * Nuclear-potential operator matrix in a separable basis (Sec. 2.2,
  * Example 2.1, eq. nuc_pot): V[k][m] = <G_k (.) G_m, P> for rank-one basis
  * functions G_k = g_k^(0) (x) g_k^(1) (x) g_k^(2) sampled at cell midpoints:

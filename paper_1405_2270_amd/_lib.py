@@ -106,6 +106,13 @@ _SIGNATURES = {
     "ls_canon_combine": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_double, ctypes.POINTER(Canon),
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_qtt_digits": (ctypes.c_int32, [ctypes.c_int32]),
+    "ls_qtt_compress": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "ls_qtt_expand": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p]),
     "ls_nuclear_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "ls_nuclear_matrix": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.c_int32, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,

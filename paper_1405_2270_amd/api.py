@@ -369,6 +369,42 @@ def forces(lat, quad, pos, Z, D, d, precision="f64", ws=None):
     return F, E
 
 
+def qtt_compress(X, eps, cap=None):
+    """Quantics-TT compression of the rows of X ([nvec][len] float64 device,
+    e.g. an assembled factor matrix): (cores [nvec][cap] float64, ranks
+    [nvec][d+1] int32, status [nvec] int32); see ls_qtt_compress."""
+    X = _dev_f64(X, "X")
+    if X.dim() != 2 or not X.is_contiguous():
+        raise ValueError("X must be a contiguous [nvec][len] matrix")
+    nvec, length = int(X.shape[0]), int(X.shape[1])
+    d = int(lib().ls_qtt_digits(length))
+    if cap is None:
+        cap = 8192
+    cores = torch.empty((nvec, cap), dtype=torch.float64, device=X.device)
+    ranks = torch.empty((nvec, d + 1), dtype=torch.int32, device=X.device)
+    status = torch.empty(nvec, dtype=torch.int32, device=X.device)
+    check("ls_qtt_compress", lib().ls_qtt_compress(_ptr(X), nvec, length, length, float(eps), int(cap),
+                                                   _ptr(cores), _ptr(ranks), _ptr(status), _stream()))
+    return cores, ranks, status
+
+
+def qtt_expand(cores, ranks, status, length):
+    """The vectors [nvec][length] that QTT cores represent (NaN rows where the
+    compression failed)."""
+    for name, t, dt in (("cores", cores, torch.float64), ("ranks", ranks, torch.int32),
+                        ("status", status, torch.int32)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+    nvec, cap = int(cores.shape[0]), int(cores.shape[1])
+    d = int(lib().ls_qtt_digits(int(length)))
+    if tuple(ranks.shape) != (nvec, d + 1) or status.numel() != nvec:
+        raise ValueError("ranks must be [nvec][d+1] and status [nvec]")
+    Y = torch.empty((nvec, int(length)), dtype=torch.float64, device=cores.device)
+    check("ls_qtt_expand", lib().ls_qtt_expand(_ptr(cores), _ptr(ranks), _ptr(status), nvec,
+                                               int(length), cap, _ptr(Y), int(length), _stream()))
+    return Y
+
+
 def combine(FA, ca, alpha, FB, cb, beta):
     """alpha A + beta B as one canonical tensor (eq. conc): factors [A; B]."""
     cA, cB = _canon(FA, ca, "A"), _canon(FB, cb, "B")

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblatsum.so")
 SOURCES = ["ls_host.cpp", "ls_vectors.hip", "ls_recon.hip", "ls_energy.hip", "ls_batch.hip",
-           "ls_extra.hip", "ls_probe.hip"]
+           "ls_extra.hip", "ls_probe.hip", "ls_qtt.hip"]
 ARCH = os.environ.get("LATSUM_ARCH", "gfx950")
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
