@@ -3,8 +3,8 @@
 One step is one pass of the whole hot path over the headline workload (box
 lattice L=32, n=128, N=4096, 8 charges per cell, rule S with R=48, 16 random
 256^3 sub-boxes, rank-8 density):
-  quadrature table (host) -> kernel vectors -> lattice assembly -> energy ->
-  reconstruction of the 16 sub-boxes.
+  quadrature table (host) -> kernel vectors and lattice assembly (one launch,
+  the master windows in LDS) -> energy -> reconstruction of the 16 sub-boxes.
 Inputs are resident in HBM before timing starts. The FP64 path and each mixed
 reconstruction precision are timed; `value` is the fastest mixed variant whose
 potential error against the FP64 oracle stays within 1e-6 (rel_mag, on the
@@ -81,6 +81,7 @@ def parse():
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--no-periodic", action="store_true")
     p.add_argument("--no-tensor", action="store_true")
+    p.add_argument("--no-qtt", action="store_true")
     p.add_argument("--no-table31", action="store_true")
     p.add_argument("--batch-count", type=int, default=512)
     p.add_argument("--mode", choices=["bench", "kernels"], default="bench",
@@ -394,6 +395,46 @@ def bench_tensor(L, T, steps, warmup, truth=None):
     return res
 
 
+def bench_qtt(L, F, eps_list=(1e-6, 1e-8), reps=5):
+    """QTT compression (TT-SVD) of every assembled vector of the headline
+    workload (3 axes x K rows of N = 4096): launch time per axis-matrix from
+    HIP events, storage against the full vectors, ranks, and the largest
+    relative L2 error of the expanded vectors (GPU expansion) per eps."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    nvals = sum(int(f.numel()) for f in F)
+    for eps in eps_list:
+        res = [L.qtt_compress(f, eps) for f in F]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            for f in F:
+                L.qtt_compress(f, eps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        stored, rmax, rsum, bad, err = 0, 0, 0.0, 0, 0.0
+        nvec = 0
+        for f, (cores, ranks, status) in zip(F, res):
+            rk = ranks.long()
+            stored += int((2 * rk[:, :-1] * rk[:, 1:]).sum())
+            rmax = max(rmax, int(rk.max()))
+            rsum += float(rk[:, 1:-1].double().mean(dim=1).sum())
+            nvec += int(rk.shape[0])
+            bad += int((status != 1).sum())
+            Y = L.qtt_expand(cores, ranks, status, int(f.shape[1]))
+            e = ((Y - f).norm(dim=1) / f.norm(dim=1).clamp_min(1e-300)).max()
+            err = max(err, float(e))
+        out[f"{eps:g}"] = {"ms": round(ms, 4), "vectors": nvec, "failed": bad,
+                           "max_rank": rmax, "mean_rank": round(rsum / nvec, 3),
+                           "stored_doubles": stored, "full_doubles": nvals,
+                           "compression": round(nvals / stored, 1),
+                           "max_rel_l2_err": err, "vectors_per_s": nvec / (ms / 1e3)}
+    return out
+
+
 def host_cpu():
     """Host CPU description: logical CPUs, CPUs this process may run on, and
     the model name from /proc/cpuinfo."""
@@ -680,21 +721,24 @@ def main():
     energy_stream = torch.cuda.Stream()
 
     def device_step(prec, qt, ev=None, overlap="beside"):
-        masters = L.kernel_vectors(spec, qt, pos)                          # a2
+        # a2 + a3: the kernel vectors generated inside the box assembly (the
+        # master window in LDS), which also writes the factors' row maxima
+        # for the FP16x3 preparation
         if ev is not None:
             ev[0].record(torch.cuda.current_stream())
-        F, coef = L.assemble(spec, qt, pos, Z, masters)                    # a3
+        rm = torch.empty((3, K), dtype=torch.float64, device=dev)
+        F, coef = L.assemble(spec, qt, pos, Z, None, rowmax=rm)            # a2 + a3
         if ev is not None:
             # timed steps: energy and reconstruction one after the other
             ev[1].record(torch.cuda.current_stream())
             E = L.energy(F, coef, D, d, "f64", ews)                        # a6
             ev[2].record(torch.cuda.current_stream())
-            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws)  # a5
+            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws, rowmax=rm)  # a5
             ev[3].record(torch.cuda.current_stream())
             return F, coef, E
         if overlap == "serial":
             E = L.energy(F, coef, D, d, "f64", ews)                        # a6
-            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws)  # a5
+            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws, rowmax=rm)  # a5
             return F, coef, E
         if overlap == "prepare":
             # the energy on a second stream beside the reconstruction's
@@ -704,9 +748,10 @@ def main():
             energy_stream.wait_stream(cur)
             with torch.cuda.stream(energy_stream):
                 E = L.energy(F, coef, D, d, "f64", ews)                    # a6
-            L.reconstruct_prepare(F, coef, prec, rws)                       # a5 (preparation)
+            L.reconstruct_prepare(F, coef, prec, rws, rowmax=rm)            # a5 (preparation)
             cur.wait_stream(energy_stream)
-            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws, prepared=True)
+            L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws, prepared=True,
+                               rowmax=rm)
             return F, coef, E
         # the energy only reads the factors: it can run on a second stream,
         # beside the reconstruction (fork and join inside the captured graph)
@@ -714,7 +759,7 @@ def main():
         energy_stream.wait_stream(cur)
         with torch.cuda.stream(energy_stream):
             E = L.energy(F, coef, D, d, "f64", ews)                        # a6
-        L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws)  # a5
+        L.reconstruct_into(F, coef, boxes, outs[prec], scale, prec, 0, rws, rowmax=rm)  # a5
         cur.wait_stream(energy_stream)
         return F, coef, E
 
@@ -847,8 +892,12 @@ def main():
     lib_asm = lambda: L.assemble_into(spec, qt0, pos, Z, m0, Fa, ca)
     asm_launch_ms = launch_ms(lib_asm)
     vec_launch_ms = launch_ms(lambda: L.kernel_vectors(spec, qt0, pos))
+    rm0 = torch.empty((3, K), dtype=torch.float64, device=dev)
+    fused_launch_ms = launch_ms(lambda: L.assemble_into(spec, qt0, pos, Z, None, Fa, ca, rowmax=rm0))
     en_launch_ms = launch_ms(lambda: L.energy(F0, c0, D, d, "f64", ews))
-    recon_launch_ms = {p: launch_ms(lambda p=p: L.reconstruct_into(F0, c0, boxes, outs[p], scale, p, 0, rws))
+    # the reconstruction as the step runs it: row maxima from the assembly
+    recon_launch_ms = {p: launch_ms(lambda p=p: L.reconstruct_into(F0, c0, boxes, outs[p], scale, p, 0,
+                                                                   rws, rowmax=rm0))
                        for p in sorted({best, "f64"})}
     for p, t in recon_launch_ms.items():
         results[p]["recon_launch_ms"] = t
@@ -893,6 +942,16 @@ def main():
     cells = 3 * sysm.M0 * sysm.R * 2 * Xh
     kernel_vectors = {"bound": "valu", "launch_ms": round(vec_launch_ms, 4), "cells": cells,
                       "cell_integrals_per_s": round(cells / (vec_launch_ms / 1e3), 1)}
+    # the step's assembly: kernel vectors generated in LDS inside the box
+    # assembly (one launch); its HBM traffic is the factor writes alone, its
+    # work the master window's cell integrals, (2L - 1) n per vector
+    fused_cells = 3 * sysm.M0 * sysm.R * (2 * Lm - 1) * sysm.n
+    fused_bytes = 3 * K * N * 8 + K * 8 + 3 * K * 8
+    fused_assembly = {"bound": "valu", "launch_ms": round(fused_launch_ms, 4), "cells": fused_cells,
+                      "cell_integrals_per_s": round(fused_cells / (fused_launch_ms / 1e3), 1),
+                      "hbm_bytes_per_launch": fused_bytes,
+                      "hbm_GBps": round(fused_bytes / (fused_launch_ms / 1e3) / 1e9, 1),
+                      "vs_two_launches_ms": round(vec_launch_ms + asm_launch_ms, 4)}
     en_bytes = 3 * K * N * 8 + sum(x.numel() for x in D) * 8
     energy_roofline = {"bound": "hbm", "achieved": round(en_bytes / (en_launch_ms / 1e3) / 1e9, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -961,6 +1020,7 @@ def main():
 
     batched = None if args.no_batch else bench_batch(
         L, T, args.batch_count, args.steps, 1, truth=truths["batch"] if truths else None)
+    qtt = None if args.no_qtt else bench_qtt(L, F0)
     tensor = None if args.no_tensor else bench_tensor(
         L, T, args.steps, 1, truths["tensor"] if truths else None)
     table31 = None if args.no_table31 else bench_table31(L, T)
@@ -985,8 +1045,8 @@ def main():
                                "with jitter, rule S R=48 (K=384), 16 sub-boxes 256^3, rank-8 density",
                    "global_batch": len(boxes), "seq_len": None, "parallelism": "none"},
         "step": "host quadrature table + one replay of the captured device step "
-                "(kernel vectors, assembly, then the energy and the reconstruction of the "
-                "16 boxes: " + {"overlap": "the energy on a second stream beside the reconstruction",
+                "(kernel vectors generated inside the box assembly, which also writes the "
+                "factors' row maxima, then the energy and the reconstruction of the 16 boxes: " + {"overlap": "the energy on a second stream beside the reconstruction",
                                 "serial": "the energy, then the reconstruction, on one stream",
                                 "prepare": "the energy on a second stream beside the "
                                            "reconstruction's workspace preparation, joined before "
@@ -1005,9 +1065,11 @@ def main():
         "periodic": periodic,
         "roofline": roofline,
         "assembly_roofline": assembly,
+        "fused_assembly": fused_assembly,
         "kernel_vectors": kernel_vectors,
         "energy_roofline": energy_roofline,
         "measured_peaks": peaks,
+        "qtt": qtt,
         "tensor_lattice": tensor,
         "table_3_1": table31,
         "cpu_baseline": cpu,

@@ -86,6 +86,10 @@ typedef struct {
   int32_t len[3];       /* vector length per axis */
   const double* f[3];   /* device [K][len[l]] FP64 factor matrices */
   const double* coef;   /* device [K] FP64 weights */
+  const double* rowmax; /* device [3][K] or NULL: rowmax[l K + r] = max_x |f[l][r][x]| of these
+                           factors, as ls_assemble writes it; LS_F16X3 reconstruction then
+                           skips its own pass over the factors (a wrong maximum mis-scales the
+                           FP16 terms); ignored elsewhere */
 } ls_canon;
 
 typedef struct {
@@ -150,13 +154,21 @@ ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* quad, int32_t 
  * used exactly once there; masters_dev must be NULL for it. With
  * derivative != 0 the vectors are position derivatives (masters must then be
  * derivative masters or NULL) and coef_dev may be NULL.
+ * Box lattice without stored masters: when (2 L_l - 1) n <= 8192 and
+ * L_l <= 64 on every axis, one workgroup per (atom, axis, q) generates the
+ * master cells its vector needs in LDS (as ls_kernel_vectors does) and sums
+ * them as from stored masters: the same factors bit for bit, without the
+ * masters' trip through device memory (kernel vectors and assembly in one
+ * launch). Larger box lattices generate L integrals per entry.
  * f0_dev, f1_dev, f2_dev: device [K][N_l] FP64, written. coef_dev: device [K].
+ * rowmax_dev: device [3][K] or NULL; if given, rowmax[l K + r] = max_g
+ * |f_l[r][g]| is written too (for ls_canon.rowmax).
  * Errors: LS_EINVAL.
  */
 ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int32_t M0,
                       const double* pos_dev, const double* Z_dev, const double* masters_dev,
                       int32_t X, int32_t derivative, double* f0_dev, double* f1_dev,
-                      double* f2_dev, double* coef_dev, hipStream_t stream);
+                      double* f2_dev, double* coef_dev, double* rowmax_dev, hipStream_t stream);
 
 /*
  * Non-equidistant tensor lattice (Sec. 3.1, remark after eq. EwaldTensorM0):

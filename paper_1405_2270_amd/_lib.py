@@ -31,7 +31,7 @@ class Quad(ctypes.Structure):
 
 class Canon(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("len", ctypes.c_int32 * 3),
-                ("f", ctypes.c_void_p * 3), ("coef", ctypes.c_void_p)]
+                ("f", ctypes.c_void_p * 3), ("coef", ctypes.c_void_p), ("rowmax", ctypes.c_void_p)]
 
 
 class TensorLattice(ctypes.Structure):
@@ -69,7 +69,7 @@ _SIGNATURES = {
     "ls_assemble": (ctypes.c_int, [ctypes.POINTER(Lattice), ctypes.POINTER(Quad), ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                   ctypes.c_void_p, ctypes.c_void_p]),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ls_assemble_tensor": (ctypes.c_int, [ctypes.POINTER(TensorLattice), ctypes.POINTER(Quad),
                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

@@ -141,15 +141,17 @@ def kernel_vectors_into(lat, quad, pos, out, derivative=False):
     return out
 
 
-def assemble(lat, quad, pos, Z, masters=None, derivative=False):
-    """Assembled canonical factors [f0, f1, f2] ([K][N_l] FP64 each) and coef [K]."""
+def assemble(lat, quad, pos, Z, masters=None, derivative=False, rowmax=None):
+    """Assembled canonical factors [f0, f1, f2] ([K][N_l] FP64 each) and coef [K]
+    (``masters`` None: the box lattice's kernel vectors generated inside the
+    assembly where its window fits, else every cell integral in registers)."""
     pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     K = M0 * quad.R
     dev = pos.device
     F = [torch.empty((K, lat.N(l)), dtype=torch.float64, device=dev) for l in range(3)]
     coef = None if derivative else torch.empty(K, dtype=torch.float64, device=dev)
-    return assemble_into(lat, quad, pos, Z, masters, F, coef, derivative)
+    return assemble_into(lat, quad, pos, Z, masters, F, coef, derivative, rowmax)
 
 
 def assemble_tensor(tl, quad, pos, Z, derivative=False):
@@ -188,8 +190,9 @@ def assemble_tensor_into(tl, quad, pos, Z, F, coef, derivative=False):
     return F, coef
 
 
-def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
-    """As ``assemble`` but into caller-provided factors F and coef."""
+def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False, rowmax=None):
+    """As ``assemble`` but into caller-provided factors F and coef; ``rowmax``
+    (a [3][K] float64 device tensor, optional) receives max_g |f_l[r][g]|."""
     pos = _pos_tensor(pos)
     M0 = pos.shape[0]
     K = M0 * quad.R
@@ -207,17 +210,23 @@ def assemble_into(lat, quad, pos, Z, masters, F, coef, derivative=False):
         masters = _dev_f64(masters, "masters")
         if masters.numel() != M0 * 3 * quad.R * 2 * X:
             raise ValueError(f"masters must hold M0*3*R*2X = {M0 * 3 * quad.R * 2 * X} values")
+    if rowmax is not None:
+        rowmax = _dev_f64(rowmax, "rowmax")
+        if rowmax.numel() != 3 * K or not rowmax.is_contiguous():
+            raise ValueError(f"rowmax must be contiguous with 3*K = {3 * K} values")
     check("ls_assemble", lib().ls_assemble(ctypes.byref(lat.c()), ctypes.byref(quad.c()), M0,
                                            _ptr(pos), _ptr(None if derivative else Z),
                                            _ptr(masters), X, int(derivative), _ptr(F[0]),
                                            _ptr(F[1]), _ptr(F[2]), _ptr(None if derivative else coef),
-                                           _stream()))
+                                           _ptr(rowmax), _stream()))
     return F, coef
 
 
-def _canon(F, coef, name="factor"):
+def _canon(F, coef, name="factor", rowmax=None):
     """Canonical-tensor descriptor of three device factor matrices [K][len_l]
-    and their coefficients [K], all contiguous float64 on one device."""
+    and their coefficients [K], all contiguous float64 on one device
+    (``rowmax``: optional [3][K] row maxima of the factors, as ``assemble``
+    writes them)."""
     if len(F) != 3:
         raise ValueError(f"{name}: three factor matrices are required")
     for l, f in enumerate(F):
@@ -232,8 +241,13 @@ def _canon(F, coef, name="factor"):
         raise ValueError(f"{name}: {K} coefficients are required (got {coef.numel()})")
     if any(x.device != F[0].device for x in (F[1], F[2], coef)):
         raise ValueError(f"{name}: all tensors must be on one device")
+    if rowmax is not None:
+        rowmax = _dev_f64(rowmax, f"{name} row maxima")
+        if rowmax.numel() != 3 * K or not rowmax.is_contiguous() or rowmax.device != F[0].device:
+            raise ValueError(f"{name}: row maxima must be a contiguous [3][K] tensor on the device")
     return Canon(K, (ctypes.c_int32 * 3)(*[int(f.shape[1]) for f in F]),
-                 (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F]), coef.data_ptr())
+                 (ctypes.c_void_p * 3)(*[f.data_ptr() for f in F]), coef.data_ptr(),
+                 rowmax.data_ptr() if rowmax is not None else None)
 
 
 def _out_tensor(out, dtype, numel, device, name="out"):
@@ -273,18 +287,19 @@ def _recon_ws(canon, prec, device, ws):
     return ws, ws.numel() * ws.element_size()
 
 
-def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
+def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None, rowmax=None):
     """Sub-boxes of the canonical tensor. ``boxes``: iterable of
     (o0, o1, o2, e0, e1, e2). Returns one tensor [e0][e1][e2] per box
     (views of a single allocation). ``ws``: optional uint8 device workspace
-    (split-bf16 precisions; allocated here when missing or short)."""
-    _canon(F, coef)
+    (split-bf16 precisions; allocated here when missing or short). ``rowmax``:
+    the factors' row maxima from ``assemble`` (optional, FP16x3 uses them)."""
+    _canon(F, coef, rowmax=rowmax)
     boxes = [tuple(int(v) for v in b) for b in boxes]
     prec = _lib.PRECISIONS[precision]
     dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
     sizes = [b[3] * b[4] * b[5] for b in boxes]
     flat = torch.empty(sum(sizes), dtype=dtype, device=F[0].device)
-    reconstruct_into(F, coef, boxes, flat, scale, precision, tile, ws)
+    reconstruct_into(F, coef, boxes, flat, scale, precision, tile, ws, rowmax=rowmax)
     out, off = [], 0
     for b, s in zip(boxes, sizes):
         out.append(flat[off:off + s].view(b[3], b[4], b[5]))
@@ -293,7 +308,7 @@ def reconstruct(F, coef, boxes, scale=1.0, precision="f64", tile=0, ws=None):
 
 
 def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws=None,
-                     prepared=False):
+                     prepared=False, rowmax=None):
     """As ``reconstruct`` but into a caller-provided flat tensor. ``prepared``:
     ``ws`` already holds the preparation of these factors for this precision
     (``reconstruct_prepare``, or an earlier call with the same ``ws``)."""
@@ -301,7 +316,7 @@ def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws
     if any(len(b) != 6 for b in boxes):
         raise ValueError("a box is (o0, o1, o2, e0, e1, e2)")
     prec = _lib.PRECISIONS[precision]
-    canon = _canon(F, coef)
+    canon = _canon(F, coef, rowmax=rowmax)
     dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
     _out_tensor(out, dtype, sum(max(b[3], 0) * max(b[4], 0) * max(b[5], 0) for b in boxes),
                 F[0].device)
@@ -318,13 +333,13 @@ def reconstruct_into(F, coef, boxes, out, scale=1.0, precision="f64", tile=0, ws
     return out
 
 
-def reconstruct_prepare(F, coef, precision, ws=None):
+def reconstruct_prepare(F, coef, precision, ws=None, rowmax=None):
     """The workspace preparation of ``reconstruct`` for these factors and this
     precision, as a call of its own (enqueued on the current stream). Returns
     the workspace (allocated when ``ws`` is None or too small; None when the
     precision needs none)."""
     prec = _lib.PRECISIONS[precision]
-    canon = _canon(F, coef)
+    canon = _canon(F, coef, rowmax=rowmax)
     ws, nws = _recon_ws(canon, prec, F[0].device, ws)
     check("ls_reconstruct_prepare", lib().ls_reconstruct_prepare(ctypes.byref(canon), prec, _ptr(ws),
                                                                  nws, _stream()))

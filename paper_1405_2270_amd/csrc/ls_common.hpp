@@ -43,6 +43,9 @@ ls_status check_lattice(const ls_lattice* lat, Lat* out);
 ls_status check_quad(const ls_quad* quad, double h, QuadArg* out);
 int master_halfwidth(const Lat& L);
 ls_status launch_status(const char* what);
+// rmax[l K + r] = max_x |f_l[r][x]| (one workgroup per rank and axis)
+ls_status launch_rank_max(const double* f0, const double* f1, const double* f2, int K, int len0,
+                          int len1, int len2, double* rmax, hipStream_t stream);
 
 #define LS_REQUIRE(cond, ...)            \
   do {                                   \

@@ -208,10 +208,10 @@ extern "C" ls_status ls_richardson(const ls_lattice* lat, const ls_quad* quad, i
   const size_t n = (size_t)lat->n;
   // rows [0, K): the lattice L; rows [K, 2K): the lattice 2L (eq. conc)
   ls_status st = ls_assemble(lat, quad, M0, pos_dev, Z_dev, nullptr, 0, 0, f0_dev, f1_dev, f2_dev,
-                             coef_dev, stream);
+                             coef_dev, nullptr, stream);
   if (st != LS_OK) return st;
   st = ls_assemble(&lat2, quad, M0, pos_dev, Z_dev, nullptr, 0, 0, f0_dev + K * n,
-                   f1_dev + K * n, f2_dev + K * n, coef_dev + K, stream);
+                   f1_dev + K * n, f2_dev + K * n, coef_dev + K, nullptr, stream);
   if (st != LS_OK) return st;
   hipLaunchKernelGGL(k_scale_coef, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, stream,
                      coef_dev, (int)K, alpha, beta);

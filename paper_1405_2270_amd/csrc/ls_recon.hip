@@ -184,6 +184,13 @@ __global__ __launch_bounds__(256) void k_rank_max(const double* __restrict__ f0,
   if (threadIdx.x == 0) rmax[(size_t)ax * K + r] = v;
 }
 
+ls_status launch_rank_max(const double* f0, const double* f1, const double* f2, int K, int len0,
+                          int len1, int len2, double* rmax, hipStream_t stream) {
+  hipLaunchKernelGGL(k_rank_max, dim3(K, 3), dim3(256), 0, stream, f0, f1, f2, K, len0, len1,
+                     len2, rmax);
+  return launch_status("row maxima");
+}
+
 // floor(log2 m) for a row maximum m, 0 for a zero or non-finite row
 __device__ __forceinline__ int row_exp(double m) { return (m > 0.0 && isfinite(m)) ? ilogb(m) : 0; }
 
@@ -1404,11 +1411,17 @@ static ls_status prepare_ws(const ls_canon* P, int precision, void* ws_dev, hipS
   const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
   if (precision == LS_F16X3) {
-    hipLaunchKernelGGL(k_rank_max, dim3(P->K, 3), dim3(256), 0, stream, P->f[0], P->f[1], P->f[2],
-                       P->K, P->len[0], P->len[1], P->len[2], (double*)(wsb + fl.rmax));
+    // the row maxima: those the assembly wrote, if the descriptor carries
+    // them, else one pass over the three factor matrices
+    const double* rmax = P->rowmax;
+    if (rmax == nullptr) {
+      hipLaunchKernelGGL(k_rank_max, dim3(P->K, 3), dim3(256), 0, stream, P->f[0], P->f[1],
+                         P->f[2], P->K, P->len[0], P->len[1], P->len[2], (double*)(wsb + fl.rmax));
+      rmax = (const double*)(wsb + fl.rmax);
+    }
     const int n8 = (P->K + 7) / 8;
     hipLaunchKernelGGL(k_prep_f16, dim3((std::max(P->len[1], P->len[2]) + 63) / 64, nch + n8 + 1), dim3(64),
-                       0, stream, P->f[1], P->f[2], P->coef, (const double*)(wsb + fl.rmax), P->K,
+                       0, stream, P->f[1], P->f[2], P->coef, rmax, P->K,
                        P->len[1], P->len[2], nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f),
                        (double*)(wsb + fl.coefS), (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
     return launch_status("ls_reconstruct (scales and pre-split)");

@@ -106,6 +106,118 @@ __global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// box assembly with the master window in LDS (kernel vectors fused in)
+// ---------------------------------------------------------------------------
+// One workgroup per (atom, axis, q) vector. The master cells the vector
+// needs, j in [-p - (L-1) n, N - p), are generated into LDS exactly as
+// k_masters generates them (shared edges across the lanes of a wave; cells
+// beyond the Gaussian's support are exact zeros and not evaluated), then the
+// residue-class sums of k_assemble_box run on them: beta[d] of residue rho is
+// window entry rho + (d + L - 1) n, the same values added in the same order,
+// so the factors equal the stored-masters assembly's bit for bit, without the
+// masters' round trip through HBM. The lanes split each residue's L outputs
+// into `parts` runs (the prefix sum of a later run first re-adds the earlier
+// terms in the same order). Optionally the row maximum max_g |f_l[r][g]|
+// goes to rowmax[l K + r].
+constexpr int kWindowCells = 8192;  // LDS window: (2L - 1) n <= 8192 cells (64 KB)
+
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_assemble_box_lds(const double* __restrict__ pos,
+                                                           const double* __restrict__ Z,
+                                                           QuadArg qa, int n, int L0, int L1,
+                                                           int L2, double b, double h, int deriv,
+                                                           double* __restrict__ f0,
+                                                           double* __restrict__ f1,
+                                                           double* __restrict__ f2,
+                                                           double* __restrict__ coef,
+                                                           double* __restrict__ rowmax) {
+  __shared__ double ms[kWindowCells];
+  __shared__ double red[4];
+  const int R = qa.R;
+  const int q = blockIdx.x;
+  const int c = blockIdx.y;
+  const int nu = c / 3, l = c - 3 * (c / 3);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (coef != nullptr && tid == 0 && l == 0) coef[nu * R + q] = Z[nu] * qa.w[q];
+  const int L = (l == 0) ? L0 : (l == 1 ? L1 : L2);
+  const int N = L * n;
+  const int W = (2 * L - 1) * n;
+  int p;
+  double delta;
+  node_offset(pos[c], b, h, n, &p, &delta);
+  const double tau = qa.tau[q];
+  const int jlo = -p - (L - 1) * n;
+  // cells whose offset exceeds the support half-width are exactly 0
+  const double hw = support_halfwidth(tau);
+  const int js = (int)fmax((double)jlo, floor(delta - hw) - 1.0);
+  const int je = (int)fmin((double)(jlo + W), ceil(delta + hw) + 2.0);
+  for (int i = tid; i < W; i += 256) {
+    const int j = jlo + i;
+    if (j < js || j >= je) ms[i] = 0.0;
+  }
+  // the support: 63 cells per wave and step, lane i's left edge shared with
+  // lane i - 1 as its right edge
+  for (int base = js + wave * kMasterCellsPerWave; base < je; base += 4 * kMasterCellsPerWave) {
+    const int j = base + lane;
+    const double y0 = (double)j - delta;
+    double v;
+    if (deriv) {
+      v = cell_derivative(tau, y0);
+    } else {
+      const double e = edge_needed(tau, j, delta) ? edge_value(tau, y0) : 0.0;
+      const double eR = __shfl_down(e, 1, 64);
+      v = h * cell_from_edges(tau, y0, e, eR);
+    }
+    if (lane < kMasterCellsPerWave && j < je) ms[j - jlo] = v;
+  }
+  __syncthreads();
+  double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * R + q) * (size_t)N;
+  // lanes per residue: parts runs of the L outputs
+  int parts = 1;
+  while (parts * 2 * n <= 256 && parts * 2 <= L) parts *= 2;
+  const int run = (L + parts - 1) / parts;
+  double vmax = 0.0;
+  for (int t0 = 0; t0 < n * parts; t0 += 256) {
+    const int t = t0 + tid;
+    if (t < n * parts) {
+      const int rho = t % n, part = t / n;
+      const int m0 = part * run, m1 = min(L, m0 + run);
+      const double* beta = ms + rho;  // beta(d) = beta[(d + L - 1) n]
+      // suf[e] = sum_{i=e}^{L-2} beta(i - (L-1)) for the outputs m0 <= e <= L-2
+      double suf[LMAX > 1 ? LMAX - 1 : 1];
+      double acc = 0.0;
+#pragma unroll
+      for (int e = LMAX - 2; e >= 0; --e) {
+        if (e <= L - 2 && e >= m0) acc += beta[e * n];
+        suf[e] = acc;
+      }
+      // prefix over the outputs before this run, in order
+      double pre = 0.0;
+#pragma unroll
+      for (int m = 0; m < LMAX; ++m)
+        if (m < m0) pre += beta[(m + L - 1) * n];
+#pragma unroll
+      for (int m = 0; m < LMAX; ++m) {
+        if (m >= m0 && m < m1) {
+          pre += beta[(m + L - 1) * n];
+          const double s = (m <= L - 2) ? suf[m] : 0.0;
+          const double v = s + pre;
+          out[(size_t)m * n + rho] = v;
+          vmax = fmax(vmax, fabs(v));
+        }
+      }
+    }
+  }
+  if (rowmax != nullptr) {
+    for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+    if (lane == 0) red[wave] = vmax;
+    __syncthreads();
+    const size_t K = (size_t)(gridDim.y / 3) * R;
+    if (tid == 0) rowmax[(size_t)l * K + nu * R + q] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  }
+}
+
 // Box assembly from masters for any L: one lane per output, L reads.
 __global__ __launch_bounds__(256) void k_assemble_box_direct(const double* __restrict__ masters,
                                                               const double* __restrict__ pos,
@@ -274,7 +386,7 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
                                  const double* pos_dev, const double* Z_dev,
                                  const double* masters_dev, int32_t X, int32_t derivative,
                                  double* f0_dev, double* f1_dev, double* f2_dev, double* coef_dev,
-                                 hipStream_t stream) {
+                                 double* rowmax_dev, hipStream_t stream) {
   clear_error();
   Lat L;
   ls_status st = check_lattice(lat, &L);
@@ -295,15 +407,33 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
   // the coefficients coef[nu R + q] = Z[nu] w[q] are written by the assembly
   // kernel itself (value vectors only)
   double* coef = derivative ? nullptr : coef_dev;
-  if (masters_dev == nullptr) {
+  const int Lmax = std::max(L.L[0], std::max(L.L[1], L.L[2]));
+  bool rowmax_done = false;
+  if (masters_dev == nullptr && !L.periodic && Lmax <= 64 &&
+      (long long)(2 * Lmax - 1) * L.n <= kWindowCells) {
+    // box: master window in LDS, kernel vectors and assembly in one launch
+    dim3 grid(qa.R, 3 * M0);
+#define LS_ASM_LDS(LM)                                                                           \
+  hipLaunchKernelGGL(k_assemble_box_lds<LM>, grid, dim3(256), 0, stream, pos_dev, Z_dev, qa, L.n, \
+                     L.L[0], L.L[1], L.L[2], L.b, L.h, derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, \
+                     coef, rowmax_dev)
+    if (Lmax <= 8)
+      LS_ASM_LDS(8);
+    else if (Lmax <= 16)
+      LS_ASM_LDS(16);
+    else if (Lmax <= 32)
+      LS_ASM_LDS(32);
+    else
+      LS_ASM_LDS(64);
+#undef LS_ASM_LDS
+    rowmax_done = true;
+  } else if (masters_dev == nullptr) {
     const int Nmax = L.N[0] > L.N[1] ? (L.N[0] > L.N[2] ? L.N[0] : L.N[2])
                                      : (L.N[1] > L.N[2] ? L.N[1] : L.N[2]);
     dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
     hipLaunchKernelGGL(k_assemble_fused, grid, dim3(256), 0, stream, pos_dev, qa, L,
                        derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, Z_dev, coef);
   } else {
-    const int Lmax = L.L[0] > L.L[1] ? (L.L[0] > L.L[2] ? L.L[0] : L.L[2])
-                                     : (L.L[1] > L.L[2] ? L.L[1] : L.L[2]);
     dim3 grid((L.n + 63) / 64, (qa.R + 3) / 4, 3 * M0);
 #define LS_ASM(LM)                                                                            \
   hipLaunchKernelGGL(k_assemble_box<LM>, grid, dim3(256), 0, stream, masters_dev, pos_dev,    \
@@ -326,7 +456,10 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
     }
 #undef LS_ASM
   }
-  return launch_status("ls_assemble");
+  st = launch_status("ls_assemble");
+  if (st != LS_OK || rowmax_dev == nullptr || rowmax_done) return st;
+  return launch_rank_max(f0_dev, f1_dev, f2_dev, M0 * qa.R, L.N[0], L.N[1], L.N[2], rowmax_dev,
+                         stream);
 }
 
 extern "C" ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad,

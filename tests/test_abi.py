@@ -75,7 +75,7 @@ def test_invalid_host_arguments(lib):
     assert lib.ls_reconstruct(None, None, 1, 1.0, 0, 0, None, None, 0, None) == _lib.LS_EINVAL
     assert lib.ls_energy(None, None, 0, None, None, 0, None) == _lib.LS_EINVAL
     assert lib.ls_assemble(None, None, 1, None, None, None, 0, 0, None, None, None, None,
-                           None) == _lib.LS_EINVAL
+                           None, None) == _lib.LS_EINVAL
     # Richardson sums: periodic lattices only, order 1 or 2 (nothing launched)
     t2, w2 = np.array([1.0, 2.0]), np.array([0.5, 0.5])
     quad = _lib.Quad(2, t2.ctypes.data_as(_lib.c_double_p), w2.ctypes.data_as(_lib.c_double_p))

@@ -527,3 +527,77 @@ def test_f16x3_wide_dynamic_range(L, f2_shift):
             assert torch.isfinite(g).all(), (tile, b)
             err = float((g.double() - r).abs().max()) / float(ra.abs().max())
             assert err < 1e-6, (tile, b, err)
+
+
+FUSED_CASES = [c for c in SMALL + WIDTHS if not c[0].startswith("periodic")]
+
+
+@pytest.mark.parametrize("name,maker", FUSED_CASES, ids=[c[0] for c in FUSED_CASES])
+@pytest.mark.parametrize("deriv", [False, True], ids=["value", "derivative"])
+def test_fused_box_assembly_equals_stored_masters(L, name, maker, deriv):
+    # kernel vectors generated inside the assembly (LDS window) give the
+    # stored-masters assembly's factors bit for bit (L > 64 takes the
+    # per-entry route and is compared with the oracle elsewhere); the row
+    # maxima written beside them are the rows' maxima exactly
+    sysm = maker()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    pos = _t(sysm.pos)
+    Z = None if deriv else _t(sysm.Z)
+    Fm, cm = L.assemble(spec, qt, pos, Z, L.kernel_vectors(spec, qt, pos, derivative=deriv),
+                        derivative=deriv)
+    K = Fm[0].shape[0]
+    Ff = [torch.empty_like(f) for f in Fm]
+    cf = None if deriv else torch.empty_like(cm)
+    rmax = torch.full((3, K), -1.0, dtype=torch.float64, device=dev)
+    L.assemble_into(spec, qt, pos, Z, None, Ff, cf, derivative=deriv, rowmax=rmax)
+    torch.cuda.synchronize()
+    for l in range(3):
+        if max(sysm.L) <= 64:
+            assert torch.equal(Ff[l], Fm[l]), (name, deriv, l)
+        assert torch.equal(rmax[l], Ff[l].abs().max(dim=1).values), (name, deriv, l)
+    if not deriv:
+        assert torch.equal(cf, cm)
+
+
+def test_row_maxima_on_every_assembly_route(L):
+    # stored masters and the periodic cell compute the maxima after the
+    # assembly; the FP16x3 reconstruction with them equals the one that
+    # finds them itself, bit for bit
+    for sysm in (small_box(131, n=10, L=(3, 2, 4), M0=3), small_periodic(132, n=12, L=(5, 3, 5), M0=3)):
+        t, w, qt = _quads(sysm, L)
+        spec = _spec(sysm, L)
+        pos, Z = _t(sysm.pos), _t(sysm.Z)
+        masters = None if sysm.periodic else L.kernel_vectors(spec, qt, pos)
+        F, coef = L.assemble(spec, qt, pos, Z, masters)
+        rmax = torch.empty((3, coef.numel()), dtype=torch.float64, device=dev)
+        F2 = [torch.empty_like(f) for f in F]
+        c2 = torch.empty_like(coef)
+        L.assemble_into(spec, qt, pos, Z, masters, F2, c2, rowmax=rmax)
+        torch.cuda.synchronize()
+        for l in range(3):
+            assert torch.equal(F2[l], F[l])
+            assert torch.equal(rmax[l], F[l].abs().max(dim=1).values)
+        box = [(0, 0, 0) + tuple(int(f.shape[1]) for f in F)]
+        V1 = L.reconstruct(F, coef, box, 1.0, "f16x3")[0]
+        V2 = L.reconstruct(F, coef, box, 1.0, "f16x3", rowmax=rmax)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(V1, V2)
+
+
+def test_config2_fused_assembly_bitwise(L):
+    # the headline workload: fused kernel vectors + assembly equal the
+    # stored-masters route bit for bit at full size
+    sysm = config2()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    pos, Z = _t(sysm.pos), _t(sysm.Z)
+    Fm, cm = L.assemble(spec, qt, pos, Z, L.kernel_vectors(spec, qt, pos))
+    Ff = [torch.empty_like(f) for f in Fm]
+    cf = torch.empty_like(cm)
+    rmax = torch.empty((3, cm.numel()), dtype=torch.float64, device=dev)
+    L.assemble_into(spec, qt, pos, Z, None, Ff, cf, rowmax=rmax)
+    torch.cuda.synchronize()
+    for l in range(3):
+        assert torch.equal(Ff[l], Fm[l]), l
+        assert torch.equal(rmax[l], Fm[l].abs().max(dim=1).values), l
