@@ -91,10 +91,13 @@ def parse():
 
 
 def kernels_once():
-    """One launch of each hot-path kernel on the headline workload (the
-    reconstruction of all 16 boxes per precision, as timed by the benchmark),
-    preceded by a plain 1 GiB device copy whose counters calibrate the traffic
-    counters (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    """One launch of each hot-path kernel on the headline workload (kernel
+    vectors and assembly through stored masters, then the step's fused
+    assembly; the energy; the reconstruction of all 16 boxes per precision, as
+    timed by the benchmark; the QTT compression of the factor rows), the
+    forces workload (FP64 and FP32 Grams) and the non-equidistant lattice's
+    assembly, preceded by a plain 1 GiB device copy whose counters calibrate
+    the traffic counters (FETCH_SIZE / WRITE_SIZE per dispatch)."""
     import numpy as np
     import torch
     import paper_1405_2270_amd as L
@@ -113,13 +116,32 @@ def kernels_once():
     pos, Z = T(s.pos), T(s.Z)
     masters = L.kernel_vectors(spec, qt, pos)
     F, coef = L.assemble(spec, qt, pos, Z, masters)
+    rm = torch.empty((3, coef.numel()), dtype=torch.float64, device=dev)
+    F, coef = L.assemble(spec, qt, pos, Z, None, rowmax=rm)       # the step's fused assembly
     E = L.energy(F, coef, [T(x) for x in s.density.D], T(s.density.d), "f64")
     boxes = [tuple(int(v) for v in b) for b in s.boxes]
     nv = sum(b[3] * b[4] * b[5] for b in boxes)
     for prec in ("f64", "f32", "bf16x6", "f16x3"):
         out = torch.empty(nv, dtype=torch.float64 if prec == "f64" else torch.float32, device=dev)
-        L.reconstruct_into(F, coef, boxes, out, 1.0 / s.h ** 3, prec)
+        L.reconstruct_into(F, coef, boxes, out, 1.0 / s.h ** 3, prec, rowmax=rm)
         del out
+    # QTT compression of the factor rows (eps 1e-6)
+    for f in F:
+        L.qtt_compress(f, 1e-6)
+    # forces workload (FP64 and FP32 Grams)
+    from workloads import config5, config_tensor
+    c5 = config5()
+    q5 = c5.quad
+    spec5 = L.LatticeSpec(c5.b, c5.n, c5.L, False)
+    qt5 = L.quadrature("S", q5["M"], q5["C0"], q5["s"])
+    D5 = [T(x) for x in c5.density.D]
+    for prec in ("f64", "f32"):
+        L.forces(spec5, qt5, T(c5.pos), T(c5.Z), D5, T(c5.density.d), prec)
+    # non-equidistant tensor lattice assembly
+    ct = config_tensor()
+    qc = ct.quad
+    tl = L.TensorLatticeSpec(ct.b, ct.n, ct.extra["N"], [T(x) for x in ct.extra["s"]])
+    L.assemble_tensor(tl, L.quadrature("S", qc["M"], qc["C0"], qc["s"]), T(ct.pos), T(ct.Z))
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))
 

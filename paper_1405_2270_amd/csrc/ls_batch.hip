@@ -4,8 +4,9 @@
 // one unit cell per axis).
 //
 // One kernel, k_batch, drains a device work queue. Workgroups take task
-// indices from a global counter; the queue is ordered by phase, and within a
-// phase by decreasing system cost:
+// indices from a global counter; the queue is a pipeline over groups of
+// systems taken by decreasing cost (the FOLDs of one group, the VECs of the
+// previous one, the TILEs of the one before):
 //   FOLD (system, axis)  Phi_l[s][i] = sum_k rho_l[s][i + k n], the density
 //                        folded back over the lattice shifts (one lane per
 //                        residue class, suffix/prefix sums, no subtraction).
@@ -444,6 +445,10 @@ static bool get_tile(int precision, int tile, TileCfg* c) {
   return false;
 }
 constexpr int kBatchTiles = 4;
+#ifndef LS_BATCH_GROUP
+#define LS_BATCH_GROUP 64
+#endif
+constexpr int kBatchGroup = LS_BATCH_GROUP;  // systems per pipeline stage of the queue
 
 struct SysHost {
   SysDev d;             // pointers into ws are offsets until bound
@@ -480,22 +485,39 @@ static ls_status build_tasks(ls_batch* B, int tile, TileCfg* cfg) {
     set_error("tile %d not available for the batch precision", tile);
     return LS_EUNSUPPORTED;
   }
-  // LPT order within each phase
+  // Systems in decreasing cost (LPT), in groups of kBatchGroup; the queue is
+  // a three-stage software pipeline over the groups: chunk t holds the FOLD
+  // tasks of group t, the VEC tasks of group t - 1 and the TILE tasks of
+  // group t - 2. Every task still waits only on tasks of earlier chunks (its
+  // system's FOLDs one chunk before its VECs, the VECs one chunk before its
+  // TILEs), which running workgroups dequeued earlier, so every wait ends;
+  // the chunk of other work between the stages covers most of the waiting,
+  // and each system finishes about two chunks after it starts, so the
+  // per-system times measure the system, not the whole queue.
   std::vector<int> order(B->count);
   for (int i = 0; i < B->count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return B->sys[a].cost > B->sys[b].cost; });
   B->tasks.clear();
-  for (int i : order)
-    for (int l = 0; l < 3; ++l) B->tasks.push_back({TASK_FOLD, i, l, 0});
-  for (int i : order)
-    for (int c = 0; c < 3 * B->sys[i].d.M0; ++c) B->tasks.push_back({TASK_VEC, i, c, 0});
-  for (int i : order) {
-    SysDev& d = B->sys[i].d;
-    const long long M = (long long)d.e[0] * d.e[1];
-    const int tm = (int)((M + cfg->bm - 1) / cfg->bm);
-    d.tiles_n = (d.e[2] + cfg->bn - 1) / cfg->bn;
-    for (int t = 0; t < tm * d.tiles_n; ++t) B->tasks.push_back({TASK_TILE, i, t, 0});
+  const int ngroups = (B->count + kBatchGroup - 1) / kBatchGroup;
+  auto group = [&](int g, auto&& emit) {
+    if (g < 0 || g >= ngroups) return;
+    for (int k = g * kBatchGroup; k < std::min(B->count, (g + 1) * kBatchGroup); ++k) emit(order[k]);
+  };
+  for (int t = 0; t < ngroups + 2; ++t) {
+    group(t, [&](int i) {
+      for (int l = 0; l < 3; ++l) B->tasks.push_back({TASK_FOLD, i, l, 0});
+    });
+    group(t - 1, [&](int i) {
+      for (int c = 0; c < 3 * B->sys[i].d.M0; ++c) B->tasks.push_back({TASK_VEC, i, c, 0});
+    });
+    group(t - 2, [&](int i) {
+      SysDev& d = B->sys[i].d;
+      const long long M = (long long)d.e[0] * d.e[1];
+      const int tm = (int)((M + cfg->bm - 1) / cfg->bm);
+      d.tiles_n = (d.e[2] + cfg->bn - 1) / cfg->bn;
+      for (int t2 = 0; t2 < tm * d.tiles_n; ++t2) B->tasks.push_back({TASK_TILE, i, t2, 0});
+    });
   }
   B->ntasks = (int)B->tasks.size();
   return LS_OK;

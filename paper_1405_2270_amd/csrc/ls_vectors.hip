@@ -121,19 +121,29 @@ __global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__
 // terms in the same order). Optionally the row maximum max_g |f_l[r][g]|
 // goes to rowmax[l K + r].
 constexpr int kWindowCells = 8192;  // LDS window: (2L - 1) n <= 8192 cells (64 KB)
+// 512 lanes per vector (four waves per SIMD, as the window's 64 KB of LDS
+// and 128 registers allow): 48 us on the headline workload, against 54 us
+// with 256 lanes and 70 us with 1024 (one workgroup per CU, generation and
+// stores no longer overlap), and 54 us for the two launches through stored
+// masters
+#ifndef LS_ASM_THREADS
+#define LS_ASM_THREADS 512
+#endif
+constexpr int kAsmThreads = LS_ASM_THREADS;
 
-template <int LMAX>
-__global__ __launch_bounds__(256) void k_assemble_box_lds(const double* __restrict__ pos,
-                                                           const double* __restrict__ Z,
-                                                           QuadArg qa, int n, int L0, int L1,
-                                                           int L2, double b, double h, int deriv,
-                                                           double* __restrict__ f0,
-                                                           double* __restrict__ f1,
-                                                           double* __restrict__ f2,
-                                                           double* __restrict__ coef,
-                                                           double* __restrict__ rowmax) {
+template <int LMAX, int BS>
+__global__ __launch_bounds__(BS) void k_assemble_box_lds(const double* __restrict__ pos,
+                                                          const double* __restrict__ Z,
+                                                          QuadArg qa, int n, int L0, int L1,
+                                                          int L2, double b, double h, int deriv,
+                                                          double* __restrict__ f0,
+                                                          double* __restrict__ f1,
+                                                          double* __restrict__ f2,
+                                                          double* __restrict__ coef,
+                                                          double* __restrict__ rowmax) {
+  constexpr int NW = BS / 64;
   __shared__ double ms[kWindowCells];
-  __shared__ double red[4];
+  __shared__ double red[NW];
   const int R = qa.R;
   const int q = blockIdx.x;
   const int c = blockIdx.y;
@@ -152,13 +162,13 @@ __global__ __launch_bounds__(256) void k_assemble_box_lds(const double* __restri
   const double hw = support_halfwidth(tau);
   const int js = (int)fmax((double)jlo, floor(delta - hw) - 1.0);
   const int je = (int)fmin((double)(jlo + W), ceil(delta + hw) + 2.0);
-  for (int i = tid; i < W; i += 256) {
+  for (int i = tid; i < W; i += BS) {
     const int j = jlo + i;
     if (j < js || j >= je) ms[i] = 0.0;
   }
   // the support: 63 cells per wave and step, lane i's left edge shared with
   // lane i - 1 as its right edge
-  for (int base = js + wave * kMasterCellsPerWave; base < je; base += 4 * kMasterCellsPerWave) {
+  for (int base = js + wave * kMasterCellsPerWave; base < je; base += NW * kMasterCellsPerWave) {
     const int j = base + lane;
     const double y0 = (double)j - delta;
     double v;
@@ -175,10 +185,10 @@ __global__ __launch_bounds__(256) void k_assemble_box_lds(const double* __restri
   double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * R + q) * (size_t)N;
   // lanes per residue: parts runs of the L outputs
   int parts = 1;
-  while (parts * 2 * n <= 256 && parts * 2 <= L) parts *= 2;
+  while (parts * 2 * n <= BS && parts * 2 <= L) parts *= 2;
   const int run = (L + parts - 1) / parts;
   double vmax = 0.0;
-  for (int t0 = 0; t0 < n * parts; t0 += 256) {
+  for (int t0 = 0; t0 < n * parts; t0 += BS) {
     const int t = t0 + tid;
     if (t < n * parts) {
       const int rho = t % n, part = t / n;
@@ -213,8 +223,12 @@ __global__ __launch_bounds__(256) void k_assemble_box_lds(const double* __restri
     for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
     if (lane == 0) red[wave] = vmax;
     __syncthreads();
-    const size_t K = (size_t)(gridDim.y / 3) * R;
-    if (tid == 0) rowmax[(size_t)l * K + nu * R + q] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (tid == 0) {
+      double mx = red[0];
+      for (int w = 1; w < NW; ++w) mx = fmax(mx, red[w]);
+      const size_t K = (size_t)(gridDim.y / 3) * R;
+      rowmax[(size_t)l * K + nu * R + q] = mx;
+    }
   }
 }
 
@@ -414,7 +428,8 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
     // box: master window in LDS, kernel vectors and assembly in one launch
     dim3 grid(qa.R, 3 * M0);
 #define LS_ASM_LDS(LM)                                                                           \
-  hipLaunchKernelGGL(k_assemble_box_lds<LM>, grid, dim3(256), 0, stream, pos_dev, Z_dev, qa, L.n, \
+  hipLaunchKernelGGL((k_assemble_box_lds<LM, kAsmThreads>), grid, dim3(kAsmThreads), 0, stream,    \
+                     pos_dev, Z_dev, qa, L.n,                                                     \
                      L.L[0], L.L[1], L.L[2], L.b, L.h, derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, \
                      coef, rowmax_dev)
     if (Lmax <= 8)
