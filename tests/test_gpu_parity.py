@@ -601,3 +601,30 @@ def test_config2_fused_assembly_bitwise(L):
     for l in range(3):
         assert torch.equal(Ff[l], Fm[l]), l
         assert torch.equal(rmax[l], Fm[l].abs().max(dim=1).values), l
+
+
+@pytest.mark.slow
+def test_config2_full_factors_and_energy_against_oracle(L):
+    # the headline workload at full size against the oracle's direct sum:
+    # every factor row of the step's fused assembly (1e-12 of each row's
+    # maximum) and the energy <P, rho> (eq. scal) for FP64 (1e-12) and FP32
+    # Grams (1e-6), rel_mag with the |Z| energy
+    from oracle.canonical import scalar_product
+    sysm = config2()
+    t, w, qt = _quads(sysm, L)
+    spec = _spec(sysm, L)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z)
+    rm = torch.empty((3, len(co)), dtype=torch.float64, device=dev)
+    F, coef = L.assemble(spec, qt, _t(sysm.pos), _t(sysm.Z), None, rowmax=rm)
+    torch.cuda.synchronize()
+    for l in range(3):
+        assert _close_rows(F[l].cpu().numpy(), Fo[l], 1e-12), l
+    D = [_t(x) for x in sysm.density.D]
+    d = _t(sysm.density.d)
+    Eo = scalar_product(Fo, co, sysm.density.D, sysm.density.d)
+    Eabs = scalar_product(Fo, np.abs(co), sysm.density.D, sysm.density.d)
+    for precision, gate in (("f64", 1e-12), ("f32", 1e-6)):
+        E = float(L.energy(F, coef, D, d, precision).cpu())
+        err = abs(E - Eo) / abs(Eabs)
+        print(f"config2 energy {precision}: rel_mag {err:.3e} (E {E!r}, oracle {Eo!r})")
+        assert err < gate, (precision, err)
