@@ -1305,7 +1305,11 @@ static bool launch_f16(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry)
     case 5: return launch_stream<2, 16, 2, 1, 1>(s, bs, (float*)out);
     case 6: return launch_stream<2, 32, 2, 1, 1>(s, bs, (float*)out);
     case 7: return launch_stream<2, 16, 2, 1, 0>(s, bs, (float*)out);
-    default: return launch_stream<2, 32, 3, 1, 5>(s, bs, (float*)out);
+    // the 32x32 shape with 128-column tiles and padded f2 fragments: 0.57
+    // against 0.64 ms unpadded on the headline boxes, still 5-7 % slower than
+    // tile 1 (its two accumulators per column fragment leave each
+    // accumulation chain of the 16-pass MFMA only one independent MFMA)
+    default: return launch_stream<2, 32, 3, 1, 20>(s, bs, (float*)out);
   }
 }
 

@@ -122,17 +122,26 @@ __global__ __launch_bounds__(256) void k_assemble_box(const double* __restrict__
 // goes to rowmax[l K + r].
 constexpr int kWindowCells = 8192;  // LDS window: (2L - 1) n <= 8192 cells (64 KB)
 // 512 lanes per vector (four waves per SIMD, as the window's 64 KB of LDS
-// and 128 registers allow): 48 us on the headline workload, against 54 us
-// with 256 lanes and 70 us with 1024 (one workgroup per CU, generation and
-// stores no longer overlap), and 54 us for the two launches through stored
-// masters
+// and 120 registers allow) and runs of at most 8 outputs per lane: 42 us on
+// the headline workload, against 45 us with runs of 32, 48-54 us with 256
+// lanes or the cell constants hoisted out of the generation loop, 52-70 us
+// with 1024 lanes (one workgroup per CU: generation and stores no longer
+// overlap; forcing 64 registers spills), and 54 us for the two launches
+// through stored masters
 #ifndef LS_ASM_THREADS
 #define LS_ASM_THREADS 512
 #endif
+#ifndef LS_ASM_RUN
+#define LS_ASM_RUN 8
+#endif
+#ifndef LS_ASM_MINW
+#define LS_ASM_MINW 1
+#endif
 constexpr int kAsmThreads = LS_ASM_THREADS;
+constexpr int kAsmRun = LS_ASM_RUN;  // outputs per lane and residue (suffix registers)
 
-template <int LMAX, int BS>
-__global__ __launch_bounds__(BS) void k_assemble_box_lds(const double* __restrict__ pos,
+template <int RUN, int BS>
+__global__ __launch_bounds__(BS, LS_ASM_MINW) void k_assemble_box_lds(const double* __restrict__ pos,
                                                           const double* __restrict__ Z,
                                                           QuadArg qa, int n, int L0, int L1,
                                                           int L2, double b, double h, int deriv,
@@ -162,29 +171,38 @@ __global__ __launch_bounds__(BS) void k_assemble_box_lds(const double* __restric
   const double hw = support_halfwidth(tau);
   const int js = (int)fmax((double)jlo, floor(delta - hw) - 1.0);
   const int je = (int)fmin((double)(jlo + W), ceil(delta + hw) + 2.0);
+#pragma unroll 1
   for (int i = tid; i < W; i += BS) {
     const int j = jlo + i;
     if (j < js || j >= je) ms[i] = 0.0;
   }
   // the support: 63 cells per wave and step, lane i's left edge shared with
   // lane i - 1 as its right edge
+#pragma unroll 1
   for (int base = js + wave * kMasterCellsPerWave; base < je; base += NW * kMasterCellsPerWave) {
     const int j = base + lane;
-    const double y0 = (double)j - delta;
+    // tau and delta re-enter each iteration as opaque register values, so the
+    // compiler cannot hoist the cell integral's tau-dependent constants out of
+    // the loop (that kept them all live and doubled the registers per lane)
+    double tq = tau, dq = delta;
+    asm volatile("" : "+v"(tq), "+v"(dq));
+    const double y0 = (double)j - dq;
     double v;
     if (deriv) {
-      v = cell_derivative(tau, y0);
+      v = cell_derivative(tq, y0);
     } else {
-      const double e = edge_needed(tau, j, delta) ? edge_value(tau, y0) : 0.0;
+      const double e = edge_needed(tq, j, dq) ? edge_value(tq, y0) : 0.0;
       const double eR = __shfl_down(e, 1, 64);
-      v = h * cell_from_edges(tau, y0, e, eR);
+      v = h * cell_from_edges(tq, y0, e, eR);
     }
     if (lane < kMasterCellsPerWave && j < je) ms[j - jlo] = v;
   }
   __syncthreads();
   double* out = ((l == 0) ? f0 : (l == 1 ? f1 : f2)) + ((size_t)nu * R + q) * (size_t)N;
-  // lanes per residue: parts runs of the L outputs
+  // lanes per residue: `parts` runs of at most RUN outputs (RUN a compile-time
+  // bound, so a run's suffix sums stay in RUN registers)
   int parts = 1;
+  while ((L + parts - 1) / parts > RUN) parts *= 2;
   while (parts * 2 * n <= BS && parts * 2 <= L) parts *= 2;
   const int run = (L + parts - 1) / parts;
   double vmax = 0.0;
@@ -194,24 +212,27 @@ __global__ __launch_bounds__(BS) void k_assemble_box_lds(const double* __restric
       const int rho = t % n, part = t / n;
       const int m0 = part * run, m1 = min(L, m0 + run);
       const double* beta = ms + rho;  // beta(d) = beta[(d + L - 1) n]
-      // suf[e] = sum_{i=e}^{L-2} beta(i - (L-1)) for the outputs m0 <= e <= L-2
-      double suf[LMAX > 1 ? LMAX - 1 : 1];
+      // suf(e) = sum_{i=e}^{L-2} beta(i - (L-1)), accumulated from i = L-2
+      // downwards (the terms above this run first), so every suffix sum adds
+      // the same terms in the same order as the stored-masters assembly
       double acc = 0.0;
+      for (int e = L - 2; e >= m1; --e) acc += beta[e * n];
+      double suf[RUN];
 #pragma unroll
-      for (int e = LMAX - 2; e >= 0; --e) {
-        if (e <= L - 2 && e >= m0) acc += beta[e * n];
-        suf[e] = acc;
+      for (int u = RUN - 1; u >= 0; --u) {
+        const int e = m0 + u;
+        if (e < m1 && e <= L - 2) acc += beta[e * n];
+        suf[u] = acc;
       }
       // prefix over the outputs before this run, in order
       double pre = 0.0;
+      for (int m = 0; m < m0; ++m) pre += beta[(m + L - 1) * n];
 #pragma unroll
-      for (int m = 0; m < LMAX; ++m)
-        if (m < m0) pre += beta[(m + L - 1) * n];
-#pragma unroll
-      for (int m = 0; m < LMAX; ++m) {
-        if (m >= m0 && m < m1) {
+      for (int u = 0; u < RUN; ++u) {
+        const int m = m0 + u;
+        if (m < m1) {
           pre += beta[(m + L - 1) * n];
-          const double s = (m <= L - 2) ? suf[m] : 0.0;
+          const double s = (m <= L - 2) ? suf[u] : 0.0;
           const double v = s + pre;
           out[(size_t)m * n + rho] = v;
           vmax = fmax(vmax, fabs(v));
@@ -427,20 +448,9 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
       (long long)(2 * Lmax - 1) * L.n <= kWindowCells) {
     // box: master window in LDS, kernel vectors and assembly in one launch
     dim3 grid(qa.R, 3 * M0);
-#define LS_ASM_LDS(LM)                                                                           \
-  hipLaunchKernelGGL((k_assemble_box_lds<LM, kAsmThreads>), grid, dim3(kAsmThreads), 0, stream,    \
-                     pos_dev, Z_dev, qa, L.n,                                                     \
-                     L.L[0], L.L[1], L.L[2], L.b, L.h, derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, \
-                     coef, rowmax_dev)
-    if (Lmax <= 8)
-      LS_ASM_LDS(8);
-    else if (Lmax <= 16)
-      LS_ASM_LDS(16);
-    else if (Lmax <= 32)
-      LS_ASM_LDS(32);
-    else
-      LS_ASM_LDS(64);
-#undef LS_ASM_LDS
+hipLaunchKernelGGL((k_assemble_box_lds<kAsmRun, kAsmThreads>), grid, dim3(kAsmThreads), 0, stream,
+                       pos_dev, Z_dev, qa, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h,
+                       derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, coef, rowmax_dev);
     rowmax_done = true;
   } else if (masters_dev == nullptr) {
     const int Nmax = L.N[0] > L.N[1] ? (L.N[0] > L.N[2] ? L.N[0] : L.N[2])
