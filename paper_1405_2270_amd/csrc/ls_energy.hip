@@ -225,8 +225,15 @@ __global__ __launch_bounds__(256) void k_fold_density(const double* __restrict__
 
 // Value and derivative Grams of one (atom, axis, q) against the folded density:
 //   Gv[s] = sum_j h*B(j) Phi[s][j + p],  Gd[s] = sum_j dB(j) Phi[s][j + p]
-template <typename T>
-__global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
+// RHO: the density ranks the per-lane accumulators hold (8 or kMaxRho).
+// four waves per SIMD: 128 registers (a few spilled): 0.43 against 0.46 ms
+// per forces call with three waves (150 registers, no spill) and 0.64 ms
+// with 16 accumulators per lane and the cell constants hoisted (183)
+#ifndef LS_FG_MINW
+#define LS_FG_MINW 4
+#endif
+template <typename T, int RHO>
+__global__ __launch_bounds__(256, LS_FG_MINW) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
                                                       Lat lat, const double* __restrict__ Phi,
                                                       int Krho, int X, int W, int K,
                                                       double* __restrict__ Gv,
@@ -241,9 +248,9 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
   node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
   const double tau = qa.tau[q];
   const double* ph = Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
-  T av[kMaxRho], ad[kMaxRho];
+  T av[RHO], ad[RHO];
 #pragma unroll
-  for (int s = 0; s < kMaxRho; ++s) {
+  for (int s = 0; s < RHO; ++s) {
     av[s] = 0;
     ad[s] = 0;
   }
@@ -252,17 +259,22 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
   const int jbeg = (int)fmax((double)-X, floor(delta - hw));
   const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
   // chunks of 255 cells: thread t evaluates edge j0 + t once (shared edges)
+#pragma unroll 1
   for (int j0 = jbeg; j0 < jend; j0 += 255) {
     const int j = j0 + (int)threadIdx.x;
-    eb[threadIdx.x] = edge_needed(tau, j, delta) ? edge_value(tau, (double)j - delta) : 0.0;
+    // tau and delta opaque per chunk: the cell integral's tau-dependent
+    // constants are recomputed instead of held live across the loop
+    double tq = tau, dq = delta;
+    asm volatile("" : "+v"(tq), "+v"(dq));
+    eb[threadIdx.x] = edge_needed(tq, j, dq) ? edge_value(tq, (double)j - dq) : 0.0;
     __syncthreads();
     if (threadIdx.x < 255 && j < jend) {
-      const double y0 = (double)j - delta;
-      const double bv = lat.h * cell_from_edges(tau, y0, eb[threadIdx.x], eb[threadIdx.x + 1]);
-      const double bd = cell_derivative(tau, y0);
+      const double y0 = (double)j - dq;
+      const double bv = lat.h * cell_from_edges(tq, y0, eb[threadIdx.x], eb[threadIdx.x + 1]);
+      const double bd = cell_derivative(tq, y0);
       if (bv != 0.0 || bd != 0.0) {
 #pragma unroll
-        for (int s = 0; s < kMaxRho; ++s) {
+        for (int s = 0; s < RHO; ++s) {
           if (s < Krho) {
             const T f = (T)ph[(size_t)s * W + j];
             av[s] += (T)bv * f;
@@ -277,7 +289,7 @@ __global__ __launch_bounds__(256) void k_force_grams(const double* __restrict__ 
   const int r = nu * qa.R + q;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int s = 0; s < kMaxRho; ++s) {
+  for (int s = 0; s < RHO; ++s) {
     if (s < Krho) {
       const double tv = wave_sum64((double)av[s]);
       const double td = wave_sum64((double)ad[s]);
@@ -488,12 +500,23 @@ static ls_status forces_run(const ls_lattice* lat, const ls_quad* quad, int32_t 
                      rho->f[0], rho->f[1], rho->f[2], L, rho->K, X, W, Phi);
   st = launch_status("ls_forces (fold)");
   if (st != LS_OK) return st;
-  if (precision == LS_F64)
-    hipLaunchKernelGGL(k_force_grams<double>, dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev,
-                       qa, L, Phi, rho->K, X, W, K, Gv, Gd);
-  else
-    hipLaunchKernelGGL(k_force_grams<float>, dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev,
-                       qa, L, Phi, rho->K, X, W, K, Gv, Gd);
+  // accumulators for 8 density ranks where they suffice (fewer registers per
+  // lane, more waves per SIMD for the cell integrals)
+#define LS_FG(T, RH)                                                                           \
+  hipLaunchKernelGGL((k_force_grams<T, RH>), dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev, \
+                     qa, L, Phi, rho->K, X, W, K, Gv, Gd)
+  if (precision == LS_F64) {
+    if (rho->K <= 8)
+      LS_FG(double, 8);
+    else
+      LS_FG(double, kMaxRho);
+  } else {
+    if (rho->K <= 8)
+      LS_FG(float, 8);
+    else
+      LS_FG(float, kMaxRho);
+  }
+#undef LS_FG
   st = launch_status("ls_forces (grams)");
   if (st != LS_OK) return st;
   hipLaunchKernelGGL(k_force_combine, dim3(M0), dim3(256), 0, stream, Z_dev, qa,
