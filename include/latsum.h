@@ -459,9 +459,25 @@ int32_t ls_batch_tiles(void);
 ls_status ls_batch_run(ls_batch_t batch, void* ws_dev, size_t ws_bytes, int32_t tile,
                        hipStream_t stream);
 /* Times every tile variant on this batch (two runs each, synchronous) and
- * keeps the fastest for tile = 0. *best_ms (nullable) receives its time. */
+ * keeps the fastest for tile = 0. *best_ms (nullable) receives its time.
+ * The choice is also entered in the autotune cache under the batch's shape
+ * class (its precision and the multiset of its systems' n, L, M0, R, density
+ * rank and sub-box extents), so that a later ls_batch_create of the same
+ * class starts with it as its tile 0 without autotuning. */
 ls_status ls_batch_autotune(ls_batch_t batch, void* ws_dev, size_t ws_bytes, hipStream_t stream,
                             int32_t* best_tile, double* best_ms);
+/* Autotune cache (project addition, per the batch's autotuned tiles): the
+ * fastest tile per shape class, kept in the process and, once a file is
+ * named here, in that text file (one "key precision tile ms" line per entry,
+ * rewritten whenever an entry is added). ls_batch_cache_file(path) empties
+ * the in-process cache, loads the entries the file holds (a missing file is
+ * created by the next autotune) and writes to it from then on; NULL stops
+ * writing. The file is the library's only file access. Errors: none (a file
+ * that cannot be written leaves the in-process cache in use). */
+ls_status ls_batch_cache_file(const char* path);
+/* The cached tile of this batch's shape class (*tile = 0 if none; *ms
+ * nullable: the time it was tuned at). Host only. */
+ls_status ls_batch_tuned_tile(ls_batch_t batch, int32_t* tile, double* ms);
 /* After the last run has completed: per-system device time in seconds
  * (first task start to last task end, device wall clock) into seconds[count]
  * (nullable), the span of each phase (folding, vector tasks, tiles: first

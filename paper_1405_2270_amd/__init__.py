@@ -9,11 +9,11 @@ from .api import (LatticeSpec, TensorLatticeSpec, QuadTable, quadrature, master_
                   kernel_vectors, assemble, assemble_into, assemble_tensor,
                   reconstruct, reconstruct_into, reconstruct_prepare, reconstruct_tiles, energy, forces,
                   LatticeEnergy,
-                  lattice_energy, Batch, combine, richardson,
+                  lattice_energy, Batch, batch_cache_file, combine, richardson,
                   nuclear_matrix, qtt_compress, qtt_expand, probe_copy, probe_mfma)
 
 __all__ = ["LatticeSpec", "TensorLatticeSpec", "QuadTable", "quadrature", "master_halfwidth",
            "kernel_vectors", "assemble", "assemble_into", "assemble_tensor", "reconstruct", "reconstruct_into", "reconstruct_prepare",
            "reconstruct_tiles", "energy", "forces",
-           "LatticeEnergy", "lattice_energy", "Batch", "combine", "richardson",
+           "LatticeEnergy", "lattice_energy", "Batch", "batch_cache_file", "combine", "richardson",
            "nuclear_matrix", "qtt_compress", "qtt_expand", "probe_copy", "probe_mfma"]

@@ -124,6 +124,8 @@ _SIGNATURES = {
                                     ctypes.c_void_p]),
     "ls_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p, c_int32_p, c_double_p]),
+    "ls_batch_cache_file": (ctypes.c_int, [ctypes.c_char_p]),
+    "ls_batch_tuned_tile": (ctypes.c_int, [ctypes.c_void_p, c_int32_p, c_double_p]),
     "ls_batch_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, c_double_p, c_double_p,
                                        c_int32_p]),
     "ls_batch_destroy": (None, [ctypes.c_void_p]),

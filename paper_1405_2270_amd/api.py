@@ -5,6 +5,7 @@ runs in the HIP library. Inputs must be CUDA (HIP) tensors of dtype float64 and
 contiguous; outputs are allocated here with torch and filled by the library.
 """
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -552,6 +553,15 @@ class Batch:
                                                            _stream(), ctypes.byref(t), ctypes.byref(ms)))
         return t.value, ms.value
 
+    def tuned_tile(self):
+        """(tile, ms) of this batch's shape class in the autotune cache ((0, 0.0)
+        if it has none)."""
+        t = ctypes.c_int32(0)
+        ms = ctypes.c_double(0.0)
+        check("ls_batch_tuned_tile", lib().ls_batch_tuned_tile(self._handle, ctypes.byref(t),
+                                                               ctypes.byref(ms)))
+        return t.value, ms.value
+
     def report(self, phases=False):
         """(per-system seconds, error flag) of the last completed run; with
         ``phases`` also the spans of the folding, vector and tile phases."""
@@ -578,6 +588,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def batch_cache_file(path):
+    """Name the autotune cache file of the batches (None: in-process only):
+    loads its entries and writes new ones there."""
+    check("ls_batch_cache_file", lib().ls_batch_cache_file(
+        None if path is None else os.fsencode(path)))
 
 
 def probe_copy(src, dst):

@@ -29,7 +29,11 @@
 // Per-system device clock stamps (first task start, last task end) give the
 // per-system latency distribution.
 #include <algorithm>
+#include <array>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "ls_split_tile.hpp"
@@ -469,6 +473,7 @@ struct ls_batch {
   void* bound_ws = nullptr;
   int ntasks = 0;
   int best_tile = 0;
+  uint64_t shape_key = 0;  // autotune cache key: precision and the multiset of system shapes
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<ls::Task> tasks;
@@ -633,6 +638,74 @@ static ls_status bind(ls_batch* B, void* ws_dev, int tile, hipStream_t stream) {
 
 using namespace ls;
 
+// ---------------------------------------------------------------------------
+// autotune cache: the fastest tile per (precision, shape class), where the
+// shape class is the multiset of the systems' shapes (n, L, M0, R, density
+// rank, sub-box extents), hashed (FNV-1a, 64 bits) in a canonical order. It
+// lives in the process and, once ls_batch_cache_file names a file, in that
+// text file too (one "key precision tile ms" line per entry, rewritten on
+// every new entry).
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneEntry {
+  int precision, tile;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<uint64_t, TuneEntry> g_tune;
+std::string g_tune_path;
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+void tune_save_locked() {
+  if (g_tune_path.empty()) return;
+  FILE* f = fopen(g_tune_path.c_str(), "w");
+  if (f == nullptr) return;  // the in-process cache still holds the entry
+  for (const auto& kv : g_tune)
+    fprintf(f, "%016llx %d %d %.6f\n", (unsigned long long)kv.first, kv.second.precision,
+            kv.second.tile, kv.second.ms);
+  fclose(f);
+}
+}  // namespace
+
+extern "C" ls_status ls_batch_cache_file(const char* path) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  g_tune_path = path ? path : "";
+  if (path == nullptr) return LS_OK;
+  FILE* f = fopen(path, "r");
+  if (f == nullptr) return LS_OK;  // a new file: written by the next autotune
+  unsigned long long key;
+  int prec, tile;
+  double ms;
+  while (fscanf(f, "%llx %d %d %lf", &key, &prec, &tile, &ms) == 4)
+    if (tile >= 1 && tile <= kBatchTiles) g_tune[(uint64_t)key] = TuneEntry{prec, tile, ms};
+  fclose(f);
+  return LS_OK;
+}
+
+extern "C" ls_status ls_batch_tuned_tile(ls_batch_t B, int32_t* tile, double* ms) {
+  clear_error();
+  LS_REQUIRE(B != nullptr && tile != nullptr, "null pointer");
+  *tile = 0;
+  if (ms) *ms = 0.0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const auto it = g_tune.find(B->shape_key);
+  if (it != g_tune.end()) {
+    *tile = it->second.tile;
+    if (ms) *ms = it->second.ms;
+  }
+  return LS_OK;
+}
+
 extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
                                      ls_batch_t* batch, size_t* ws_bytes) {
   clear_error();
@@ -738,6 +811,22 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   B->off_tasks = off;
   off += al(sizeof(Task) * max_tasks);
   B->ws_bytes = off;
+  // shape class for the autotune cache
+  std::vector<std::array<int32_t, 10>> shapes(count);
+  for (int i = 0; i < count; ++i) {
+    const SysDev& d = B->sys[i].d;
+    shapes[i] = {d.n, d.L[0], d.L[1], d.L[2], d.M0, d.R, d.Krho, d.e[0], d.e[1], d.e[2]};
+  }
+  std::sort(shapes.begin(), shapes.end());
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(key, &precision, sizeof(precision));
+  key = fnv1a(key, shapes.data(), shapes.size() * sizeof(shapes[0]));
+  B->shape_key = key;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) B->best_tile = it->second.tile;
+  }
   *ws_bytes = off;
   *batch = B;
   return LS_OK;
@@ -798,6 +887,11 @@ extern "C" ls_status ls_batch_autotune(ls_batch_t B, void* ws_dev, size_t ws_byt
   (void)hipEventDestroy(e1);
   if (st != LS_OK) return st;
   B->best_tile = best_id;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[B->shape_key] = TuneEntry{B->precision, best_id, (double)best_t};
+    tune_save_locked();
+  }
   *best = best_id;
   if (best_ms) *best_ms = best_t;
   return LS_OK;

@@ -154,3 +154,43 @@ def test_config4_smallest_systems_against_oracle():
         got = B.out[k][sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
         assert np.max(np.abs(got.double().cpu().numpy() - ref)) / np.max(np.abs(ref_abs)) < 1e-6
     B.close()
+
+
+def test_autotune_cache_by_shape_class(tmp_path):
+    # the autotuned tile is cached under the batch's shape class: a second
+    # batch of the same shapes (other positions and charges) starts with it,
+    # a batch of other shapes does not; the cache file is written and read
+    import paper_1405_2270_amd as L
+    path = str(tmp_path / "tune.txt")
+    L.batch_cache_file(path)
+    systems = _systems()
+    B = _batch(L, systems, "f32")
+    assert B.tuned_tile() == (0, 0.0)
+    best, ms = B.autotune()
+    assert B.tuned_tile()[0] == best
+    B.close()
+    moved = []
+    for s, box in systems:
+        s2 = small_box(s.seed + 1000, n=s.n, L=s.L, M0=s.M0)
+        moved.append((s2, box))
+    B2 = _batch(L, moved, "f32")
+    assert B2.tuned_tile()[0] == best
+    B2.run()  # tile 0: the cached one
+    sec, err = B2.report()
+    assert err == 0
+    B2.close()
+    B3 = _batch(L, systems[:3], "f32")
+    assert B3.tuned_tile() == (0, 0.0)
+    B3.close()
+    lines = open(path).read().split()
+    assert len(lines) == 4 and int(lines[2]) == best
+    # a fresh process state: reloaded from the file
+    L.batch_cache_file(None)
+    B4 = _batch(L, systems, "f32")
+    assert B4.tuned_tile() == (0, 0.0)
+    B4.close()
+    L.batch_cache_file(path)
+    B5 = _batch(L, systems, "f32")
+    assert B5.tuned_tile()[0] == best
+    B5.close()
+    L.batch_cache_file(None)
