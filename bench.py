@@ -146,7 +146,7 @@ def kernels_once():
     print(json.dumps({"mode": "kernels", "energy": float(E.cpu()), "copy_bytes": 8 << 27}))
 
 
-def bench_batch(L, T, count, steps, warmup, precisions=("f64", "f32", "bf16x6", "bf16x3"),
+def bench_batch(L, T, count, steps, warmup, precisions=("f64", "f32", "bf16x6", "bf16x3", "f16x3"),
                 truth=None):
     """Batched workload: `count` box systems in one persistent launch (graph
     replay), reconstruction of each system's central unit cell in each

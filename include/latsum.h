@@ -445,9 +445,11 @@ typedef struct {
 typedef struct ls_batch* ls_batch_t;
 
 /* Plan a batch; *ws_bytes receives the device workspace size.
- * precision: LS_F64, LS_F32, LS_BF16X3 or LS_BF16X6, the reconstruction's
- * (split-bf16: both operands split inside the tile, FP32 accumulation and
- * output); everything else is FP64.
+ * precision: LS_F64, LS_F32, LS_BF16X3, LS_BF16X6 or LS_F16X3, the
+ * reconstruction's (split precisions: both operands split inside the tile,
+ * FP32 accumulation and output; LS_F16X3 scales every rank of both operands
+ * by powers of two from the largest value of each sub-box factor column, as
+ * the LS_F16X3 reconstruction does); everything else is FP64.
  * Errors: LS_EINVAL (system index in the message), LS_EUNSUPPORTED. */
 ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
                           ls_batch_t* batch, size_t* ws_bytes);

@@ -19,7 +19,9 @@
 //                        last VEC task forms E = sum_r coef_r sum_s d_s prod_l G.
 //   TILE (system, tile)  one MFMA tile of the sub-box reconstruction.
 // A VEC task waits until its system's FOLD tasks are done, a TILE until its
-// VEC tasks are done. Every awaited task was dequeued earlier by a running
+// VEC tasks are done and the last of them has formed the energy (and, for
+// LS_F16X3, the per-rank scales of the FP16 tiles from the largest value of
+// every sub-box column). Every awaited task was dequeued earlier by a running
 // workgroup and never waits on a later one, so every wait ends; each wait is
 // also bounded (a spin limit sets an error flag and skips the task).
 // Producer: all lanes fence (agent scope), barrier, one lane increments the
@@ -30,6 +32,7 @@
 // per-system latency distribution.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -63,6 +66,8 @@ struct SysDev {
   double* G;      // [3][K][Krho]
   double* Fc[3];  // [K][e_l]
   double* coef;   // [K]
+  double* fmax;   // [3][K] max_x |Fc_l[r][x]| (before the LS_F16X3 normalisation)
+  double* fsc;    // [2K + 1] FP16 tiles: left scales, right scales, output scale
 };
 
 struct BatchArg {
@@ -70,6 +75,8 @@ struct BatchArg {
   const Task* tasks;
   const double* tau;
   const double* w;
+  const double* qhw;  // support_halfwidth(tau) per node
+  const double* qk;   // cell_half_norm(tau) per node
   int* head;
   int* err;
   int* fold_done;
@@ -79,6 +86,7 @@ struct BatchArg {
   unsigned long long* t_phase;  // [3][2]: first start, last end per task type
   int ntasks;
   int nsys;
+  int f16;  // LS_F16X3: the last VEC task also forms the FP16 scales
 };
 
 constexpr int kSpinLimit = 1 << 22;
@@ -154,13 +162,35 @@ __device__ void fold_task(const SysDev& S, int l) {
   }
 }
 
-// Out-of-line edge and cell evaluations: keep the erfc/series constants and
-// temporaries out of the persistent kernel's loop nests (register pressure).
-__device__ __attribute__((noinline)) double edge_ool(double tau, int j, double delta) {
-  return edge_needed(tau, j, delta) ? edge_value(tau, (double)j - delta) : 0.0;
-}
-__device__ __attribute__((noinline)) double cell_ool(double tau, double y0, double eL, double eR) {
-  return cell_from_edges(tau, y0, eL, eR);
+constexpr int kVecQ = 16;
+// LDS row stride in doubles, 2 mod 32: the 16 rows x 2 cells that a half-wave
+// reads as the MFMA A operand fall on distinct bank pairs
+constexpr int kVecRow = 258;
+
+// The cell values of one chunk for the nodes q0 .. q0 + ng - 1 (ng <= kVecQ):
+// lane i evaluates the left edge of its cell j (y0 = j - delta) where a cell
+// next to it needs it, takes the right edge from lane i + 1, and writes the
+// cell value h * integral (0 outside the node's support or for cell_ok false)
+// to col[g * kVecRow] (col null: lane 63, which only supplies an edge). Out of
+// line: the persistent kernel's own register allocation stays that of its
+// tile loops. The nodes' support half-widths and norms come precomputed.
+__device__ __attribute__((noinline)) void vec_chunk_cells(const BatchArg& ba, int q0, int ng,
+                                                          int j, double delta, double h,
+                                                          bool cell_ok, double* col) {
+  const double y0 = (double)j - delta;
+#pragma unroll 1
+  for (int g = 0; g < kVecQ; ++g) {
+    double cv = 0.0;
+    if (g < ng) {
+      const double tau = ba.tau[q0 + g], hw = ba.qhw[q0 + g];
+      const bool in = (double)j >= delta - hw - 1.0 && (double)j <= delta + hw + 1.0;
+      double eL = 0.0;
+      if (in && edge_needed(tau, j, delta)) eL = edge_value(tau, y0);
+      const double eR = __shfl_down(eL, 1, 64);
+      if (cell_ok && in) cv = h * cell_from_edges(tau, y0, eL, eR, ba.qk[q0 + g]);
+    }
+    if (col) col[g * kVecRow] = cv;
+  }
 }
 
 // Vector task: atom nu, axis l, all q, in groups of kVecQ = 16 quadrature
@@ -172,11 +202,7 @@ __device__ __attribute__((noinline)) double cell_ool(double tau, double y0, doub
 // loaded once per 16 points, and a wave keeps one 16x16 accumulator tile
 // (four registers per lane). The central-cell factor columns are gathered
 // from the same LDS values. All sums run in a fixed order.
-constexpr int kVecQ = 16;
-// LDS row stride in doubles, 2 mod 32: the 16 rows x 2 cells that a half-wave
-// reads as the MFMA A operand fall on distinct bank pairs
-constexpr int kVecRow = 258;
-constexpr int kVecSmem = (kVecQ * kVecRow + kVecQ * 256 + 4 * kVecQ * kBatchRho) * 8;
+constexpr int kVecSmem = (kVecQ * kVecRow + kVecQ * 256 + 4 * kVecQ * kBatchRho + kVecQ) * 8;
 typedef double vec_d4_t __attribute__((ext_vector_type(4)));
 
 __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbuf) {
@@ -193,6 +219,7 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
   double* bq = sbuf;                          // [kVecQ][kVecRow] cell values
   double* vb = sbuf + kVecQ * kVecRow;        // [kVecQ][256] central-cell columns
   double* red = vb + kVecQ * 256;             // [4 waves][kVecQ][kBatchRho]
+  double* cmax = red + 4 * kVecQ * kBatchRho;  // [kVecQ] column maxima
   // a chunk is 4 x 63 cells: wave wv covers cells 63 wv .. 63 wv + 62; lane i
   // evaluates the left edge of cell 63 wv + i and takes the right edge from
   // lane i + 1 (lane 63 only supplies an edge)
@@ -206,7 +233,7 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
     // support of the group: the union of the points' supports
     int jbeg = X, jend = -X;
     for (int g = 0; g < ng; ++g) {
-      const double hw = support_halfwidth(ba.tau[S.qoff + q0 + g]);
+      const double hw = ba.qhw[S.qoff + q0 + g];
       jbeg = min(jbeg, (int)fmax((double)-X, floor(delta - hw)));
       jend = max(jend, (int)fmin((double)X, ceil(delta + hw) + 1.0));
     }
@@ -217,21 +244,8 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
 #pragma unroll 1
     for (int j0 = jbeg; j0 < jend; j0 += CH) {
       const int j = j0 + ci;
-      const double y0 = (double)j - delta;
       const bool cell_ok = lane < 63 && j < jend;
-#pragma unroll 1
-      for (int g = 0; g < kVecQ; ++g) {
-        double cv = 0.0;
-        if (g < ng) {  // uniform
-          const double tau = ba.tau[S.qoff + q0 + g];
-          const double hw = support_halfwidth(tau);
-          const bool in = (double)j >= delta - hw - 1.0 && (double)j <= delta + hw + 1.0;
-          const double eL = in ? edge_ool(tau, j, delta) : 0.0;
-          const double eR = __shfl_down(eL, 1, 64);
-          if (cell_ok && in) cv = S.h * cell_ool(tau, y0, eL, eR);
-        }
-        if (lane < 63) bq[g * kVecRow + ci] = cv;
-      }
+      vec_chunk_cells(ba, S.qoff + q0, ng, j, delta, S.h, cell_ok, lane < 63 ? bq + ci : nullptr);
       __syncthreads();
       // Gram: wave wv takes cells 64 wv .. 64 wv + 63 of the chunk, 4 per MFMA
 #pragma unroll 4
@@ -279,11 +293,27 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
             ((red[tid] + red[st + tid]) + red[2 * st + tid]) + red[3 * st + tid];
       }
     }
+    // largest magnitude of each sub-box column; for LS_F16X3 the column is
+    // stored divided by 2^floor(log2 max) (exact), so its maximum lies in [1, 2)
+    for (int g = wv; g < ng; g += 4) {
+      double m = 0.0;
+      for (int x = lane; x < e; x += 64) m = fmax(m, fabs(vb[g * 256 + x]));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+      if (lane == 0) cmax[g] = m;
+    }
+    __syncthreads();
 #pragma unroll
     for (int g = 0; g < kVecQ; ++g) {
       if (g < ng) {
         const int r = nu * S.R + q0 + g;
-        if (tid < e) S.Fc[l][(size_t)r * e + tid] = vb[g * 256 + tid];
+        const double m = cmax[g];
+        if (tid < e) {
+          double v = vb[g * 256 + tid];
+          if (ba.f16 && m > 0.0 && isfinite(m)) v = ldexp(v, -ilogb(m));
+          S.Fc[l][(size_t)r * e + tid] = v;
+        }
+        if (tid == 0) S.fmax[(size_t)l * S.K + r] = m;
         if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q0 + g];
       }
     }
@@ -310,11 +340,51 @@ __device__ void energy_task(const SysDev& S, double* sbuf) {
   __syncthreads();
 }
 
-// NT = 0: FP64 / FP32 tiles (recon_tile<T>); NT = 2, 3: split-bf16 tiles with
-// NT terms (split_tile, FP32 output, MFMA shape MF).
-template <typename T, int BM, int BN, int WM, int WN, int BK, int NT = 0, int MF = 16>
+// Scales of the FP16 tiles (LS_F16X3). The VEC tasks stored every sub-box
+// column divided by 2^e_l,r, e_l,r = floor(log2 max_x |Fc_l[r][x]|), so the
+// stored columns lie below 2 in magnitude. With E_r = e_0,r + e_1,r + e_2,r and
+// t_r = floor(log2 |coef_r|) + E_r (the true rank term is below 2^(t_r + 4)),
+// T = max_r t_r over the ranks not identically zero on the sub-box:
+//   left operand   2^12 Fc_0[r][i] Fc_1[r][j]          (below 2^14),
+//   right operand  coef_r 2^(12 - T + E_r) Fc_2[r][k]  (below 2^14),
+//   output scale   2^(T - 24) (g = 24 - T undoes 2^12 2^(12 - T)).
+// Every factor is formed by ldexp of a finite value with a bounded result, so
+// nothing overflows; ranks that vanish on the sub-box (a zero column or
+// coefficient) get both scales 0. The same power-of-two scheme as the
+// LS_F16X3 reconstruction, with the exponents kept as integers.
+__device__ void f16_scales(const SysDev& S, int* ibuf) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int K = S.K;
+  auto live = [&](int r) {
+    return S.fmax[r] > 0.0 && S.fmax[K + r] > 0.0 && S.fmax[2 * K + r] > 0.0 &&
+           isfinite(S.fmax[r]) && isfinite(S.fmax[K + r]) && isfinite(S.fmax[2 * K + r]) &&
+           S.coef[r] != 0.0 && isfinite(S.coef[r]);
+  };
+  auto rexp = [&](int r) { return ilogb(S.fmax[r]) + ilogb(S.fmax[K + r]) + ilogb(S.fmax[2 * K + r]); };
+  int T = INT_MIN;
+  for (int r = tid; r < K; r += 256)
+    if (live(r)) T = max(T, ilogb(fabs(S.coef[r])) + rexp(r));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) T = max(T, __shfl_xor(T, off, 64));
+  if (lane == 0) ibuf[wv] = T;
+  __syncthreads();
+  T = max(max(ibuf[0], ibuf[1]), max(ibuf[2], ibuf[3]));
+  __syncthreads();
+  if (T == INT_MIN) T = 0;  // no live rank: every scale is 0
+  for (int r = tid; r < K; r += 256) {
+    const bool on = live(r);
+    S.fsc[r] = on ? 4096.0 : 0.0;
+    S.fsc[K + r] = on ? ldexp(S.coef[r], 12 - T + rexp(r)) : 0.0;
+  }
+  if (tid == 0) S.fsc[2 * K] = ldexp(1.0, T - 24);
+}
+
+// NT = 0: FP64 / FP32 tiles (recon_tile<T>); NT = 2, 3: split tiles with NT
+// terms (split_tile, FP32 output, MFMA shape MF): bf16 terms (FMT = 0) or, for
+// LS_F16X3, scaled FP16 terms (FMT = 1).
+template <typename T, int BM, int BN, int WM, int WN, int BK, int NT = 0, int MF = 16, int FMT = 0>
 __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
-  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1>() : recon_smem_bytes<T, BM, BN, BK>();
+  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1, FMT>() : recon_smem_bytes<T, BM, BN, BK>();
   constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
   __shared__ int s_task, s_flag;
@@ -343,13 +413,17 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
       if (threadIdx.x == 0) s_flag = (prev == S.nvec - 1) ? 1 : 0;
       __syncthreads();
       if (s_flag) {
+        // the system's last VEC task: energy and FP16 scales, then the second
+        // signal that its TILE tasks wait for (count nvec + 1)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         energy_task(S, reinterpret_cast<double*>(smem));
+        if (ba.f16) f16_scales(S, reinterpret_cast<int*>(smem));
+        signal_counter(&ba.vec_done[tk.sys]);
         if (threadIdx.x == 0) atomicMax(&ba.t_end[tk.sys], (unsigned long long)wall_clock64());
       }
       if (threadIdx.x == 0) atomicMax(&ba.t_phase[3], (unsigned long long)wall_clock64());
     } else {
-      if (!wait_counter(&ba.vec_done[tk.sys], S.nvec, ba.err, &s_flag)) continue;
+      if (!wait_counter(&ba.vec_done[tk.sys], S.nvec + 1, ba.err, &s_flag)) continue;
       BoxArg a;
       a.A1 = S.Fc[0];
       a.A2 = S.Fc[1];
@@ -365,11 +439,17 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
       a.e2 = S.e[2];
       a.scale = 1.0 / (S.h * S.h * S.h);
       const int tm = tk.a / S.tiles_n, tn = tk.a - tm * S.tiles_n;
-      if constexpr (NT == 0)
+      if constexpr (NT == 0) {
         recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
-      else
+      } else if constexpr (FMT == 1) {
+        a.coef = S.fsc;
+        a.scale *= S.fsc[2 * S.K];
+        split_tile<NT, BM, BN, WM, WN, 1, MF, 1>(a, tm * BM, tn * BN,
+                                                 reinterpret_cast<float*>(S.out), smem, S.fsc + S.K);
+      } else {
         split_tile<NT, BM, BN, WM, WN, 1, MF>(a, tm * BM, tn * BN, reinterpret_cast<float*>(S.out),
                                               smem);
+      }
       __syncthreads();
       if (threadIdx.x == 0) {
         const unsigned long long now = wall_clock64();
@@ -441,11 +521,30 @@ static bool batch_tile_split(int tile, TileCfg* c) {
   return false;
 }
 
+// LS_F16X3 tiles: scaled FP16 terms split inside the tile, the shapes of the
+// split-bf16 tiles
+static bool batch_tile_f16(int tile, TileCfg* c) {
+#define LS_BH(ID, BM_, BN_, WM_, WN_, MF_)                                    \
+  if (tile == ID) {                                                         \
+    c->bm = BM_;                                                            \
+    c->bn = BN_;                                                            \
+    c->fn = (const void*)&k_batch<float, BM_, BN_, WM_, WN_, 16, 2, MF_, 1>; \
+    return true;                                                            \
+  }
+  LS_BH(1, 128, 128, 64, 64, 16)
+  LS_BH(2, 128, 128, 64, 64, 32)
+  LS_BH(3, 128, 64, 64, 32, 32)
+  LS_BH(4, 64, 128, 32, 64, 32)
+#undef LS_BH
+  return false;
+}
+
 static bool get_tile(int precision, int tile, TileCfg* c) {
   if (precision == LS_F64) return batch_tile<double>(tile, c);
   if (precision == LS_F32) return batch_tile<float>(tile, c);
   if (precision == LS_BF16X3) return batch_tile_split<2>(tile, c);
   if (precision == LS_BF16X6) return batch_tile_split<3>(tile, c);
+  if (precision == LS_F16X3) return batch_tile_f16(tile, c);
   return false;
 }
 constexpr int kBatchTiles = 4;
@@ -456,7 +555,7 @@ constexpr int kBatchGroup = LS_BATCH_GROUP;  // systems per pipeline stage of th
 
 struct SysHost {
   SysDev d;             // pointers into ws are offsets until bound
-  size_t off_phi, off_g, off_fc[3], off_coef;
+  size_t off_phi, off_g, off_fc[3], off_coef, off_fmax, off_fsc;
   double cost;
 };
 
@@ -466,8 +565,9 @@ struct ls_batch {
   int precision;
   int count;
   std::vector<ls::SysHost> sys;
-  std::vector<double> tau, w;
-  size_t off_ctrl, off_fold, off_vec, off_ts, off_te, off_sys, off_tau, off_w, off_tasks, ws_bytes;
+  std::vector<double> tau, w, qhw, qk;
+  size_t off_ctrl, off_fold, off_vec, off_ts, off_te, off_sys, off_tau, off_w, off_hw, off_k, off_tasks,
+      ws_bytes;
   // per bound tile: tasks differ only in the tile split of TILE tasks
   int bound_tile = -1;
   void* bound_ws = nullptr;
@@ -534,6 +634,8 @@ static BatchArg make_arg(ls_batch* B, char* ws) {
   a.tasks = (const Task*)(ws + B->off_tasks);
   a.tau = (const double*)(ws + B->off_tau);
   a.w = (const double*)(ws + B->off_w);
+  a.qhw = (const double*)(ws + B->off_hw);
+  a.qk = (const double*)(ws + B->off_k);
   a.head = (int*)(ws + B->off_ctrl);
   a.err = (int*)(ws + B->off_ctrl) + 1;
   a.fold_done = (int*)(ws + B->off_fold);
@@ -543,6 +645,7 @@ static BatchArg make_arg(ls_batch* B, char* ws) {
   a.t_phase = (unsigned long long*)(ws + B->off_ctrl + 64);
   a.ntasks = B->ntasks;
   a.nsys = B->count;
+  a.f16 = B->precision == LS_F16X3 ? 1 : 0;
   return a;
 }
 
@@ -565,6 +668,8 @@ static ls_status bind(ls_batch* B, void* ws_dev, int tile, hipStream_t stream) {
     d.G = (double*)(ws + B->sys[i].off_g);
     for (int l = 0; l < 3; ++l) d.Fc[l] = (double*)(ws + B->sys[i].off_fc[l]);
     d.coef = (double*)(ws + B->sys[i].off_coef);
+    d.fmax = (double*)(ws + B->sys[i].off_fmax);
+    d.fsc = (double*)(ws + B->sys[i].off_fsc);
     B->devsys[i] = d;
   }
   hipError_t e = hipMemcpyAsync(ws + B->off_sys, B->devsys.data(), sizeof(SysDev) * B->count,
@@ -576,6 +681,12 @@ static ls_status bind(ls_batch* B, void* ws_dev, int tile, hipStream_t stream) {
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + B->off_w, B->w.data(), sizeof(double) * B->w.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + B->off_hw, B->qhw.data(), sizeof(double) * B->qhw.size(),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + B->off_k, B->qk.data(), sizeof(double) * B->qk.size(),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
@@ -711,7 +822,7 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   clear_error();
   LS_REQUIRE(systems != nullptr && batch != nullptr && ws_bytes != nullptr, "null pointer");
   LS_REQUIRE(count >= 1 && count <= (1 << 20), "count must be in [1, 2^20]");
-  if (precision < LS_F64 || precision > LS_BF16X6) {
+  if (precision < LS_F64 || precision > LS_F16X3) {
     set_error("unknown batch precision %d", precision);
     return LS_EUNSUPPORTED;
   }
@@ -785,8 +896,13 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
     d.out = S.out_dev;
     d.E = S.E_dev;
     for (int q = 0; q < qa.R; ++q) {
-      B->tau.push_back(qa.tau[q]);
+      const double tau = qa.tau[q];
+      B->tau.push_back(tau);
       B->w.push_back(qa.w[q]);
+      // the device's support_halfwidth and cell_half_norm (IEEE division on
+      // both sides: the same values)
+      B->qhw.push_back(tau > 0.0 ? 28.0 / tau + 2.0 : 1e300);
+      B->qk.push_back(0.88622692545275801365 / tau);
     }
     nq += qa.R;
     h.off_phi = off;
@@ -799,6 +915,10 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
     }
     h.off_coef = off;
     off += al(sizeof(double) * (size_t)d.K);
+    h.off_fmax = off;
+    off += al(sizeof(double) * 3 * (size_t)d.K);
+    h.off_fsc = off;
+    off += al(sizeof(double) * (2 * (size_t)d.K + 1));
     h.cost = (double)d.K * (2.0 * d.X) + 2.0 * d.K * (double)d.e[0] * d.e[1] * d.e[2] / 64.0;
     // task count bound: smallest tile 64x64
     max_tasks += 3 + 3 * (size_t)S.M0 +
@@ -807,6 +927,10 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   B->off_tau = off;
   off += al(sizeof(double) * nq);
   B->off_w = off;
+  off += al(sizeof(double) * nq);
+  B->off_hw = off;
+  off += al(sizeof(double) * nq);
+  B->off_k = off;
   off += al(sizeof(double) * nq);
   B->off_tasks = off;
   off += al(sizeof(Task) * max_tasks);

@@ -11,6 +11,7 @@
 #include <cstdio>
 
 #include "latsum.h"
+#include "ls_erfc_fit.hpp"
 
 namespace ls {
 
@@ -71,6 +72,10 @@ ls_status launch_rank_max(const double* f0, const double* f1, const double* f2, 
 //  * otherwise the erfc difference on the tail side (or the erf sum across
 //    the origin); there erfc(far)/erfc(near) <= ~0.6, so nothing cancels.
 // Entries whose near edge is beyond |u| = 27 are below 1e-318 and return 0.
+// erfc is erfc_fit (ls_erfc_fit.hpp, relative error about 1e-15); erf(v) is
+// taken as 1 - erfc(v): a cell across the origin outside the series range
+// has tau > 0.35, so its erf sum is at least erf(0.35) ~ 0.38 and the
+// roundings of 1 - erfc add only about 1e-16 relative to it.
 __device__ __forceinline__ bool hermite_cell(double tau, double y0) {
   const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
   return tau <= 0.35 && fabs(a) * tau <= 0.25;
@@ -121,13 +126,13 @@ __device__ __forceinline__ double cell_integral(double tau, double y0) {
   const double k = 0.88622692545275801365 / tau;  // sqrt(pi)/(2 tau)
   if (u0 >= 0.0) {
     if (u0 > 27.0) return 0.0;
-    return k * (erfc(u0) - erfc(u1));
+    return k * (erfc_fit(u0) - (u1 > 27.0 ? 0.0 : erfc_fit(u1)));
   }
   if (u1 <= 0.0) {
     if (u1 < -27.0) return 0.0;
-    return k * (erfc(-u1) - erfc(-u0));
+    return k * (erfc_fit(-u1) - (u0 < -27.0 ? 0.0 : erfc_fit(-u0)));
   }
-  return k * (erf(u1) + erf(-u0));
+  return k * ((1.0 - (u1 > 27.0 ? 0.0 : erfc_fit(u1))) + (1.0 - (u0 < -27.0 ? 0.0 : erfc_fit(-u0))));
 }
 
 // Shared edges. Outside the series range a cell integral is a fixed
@@ -141,17 +146,22 @@ __device__ __forceinline__ bool edge_needed(double tau, int j, double delta) {
 
 __device__ __forceinline__ double edge_value(double tau, double y) {
   const double u = fabs(tau * y);
-  return u > 27.0 ? 0.0 : erfc(u);
+  return u > 27.0 ? 0.0 : erfc_fit(u);
 }
 
-// Integral over cell [y0, y0 + 1] from its edge values eL = E(y0), eR = E(y0 + 1).
-__device__ __forceinline__ double cell_from_edges(double tau, double y0, double eL, double eR) {
+// Integral over cell [y0, y0 + 1] from its edge values eL = E(y0), eR = E(y0 + 1);
+// k = sqrt(pi) / (2 tau) (cell_half_norm), which callers may compute once per node.
+__device__ __forceinline__ double cell_half_norm(double tau) { return 0.88622692545275801365 / tau; }
+__device__ __forceinline__ double cell_from_edges(double tau, double y0, double eL, double eR,
+                                                  double k) {
   if (tau == 0.0) return 1.0;
   if (hermite_cell(tau, y0)) return hermite_series(tau, y0);
-  const double k = 0.88622692545275801365 / tau;
   if (y0 >= 0.0) return k * (eL - eR);
   if (y0 + 1.0 <= 0.0) return k * (eR - eL);
   return k * ((1.0 - eL) + (1.0 - eR));
+}
+__device__ __forceinline__ double cell_from_edges(double tau, double y0, double eL, double eR) {
+  return cell_from_edges(tau, y0, eL, eR, cell_half_norm(tau));
 }
 
 // d/da of the integral of exp(-t^2 (x - a)^2) over a cell, in grid units:

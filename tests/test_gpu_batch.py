@@ -1,7 +1,8 @@
 """Batched systems in one persistent launch against the FP64 oracle.
 
 Each system's energy (FP64 throughout) and its reconstructed sub-box (FP64,
-FP32, split-bf16x3 or split-bf16x6 reconstruction) are compared with the oracle; graph
+FP32, split-bf16x3, split-bf16x6 or scaled FP16x3 reconstruction) are compared
+with the oracle; graph
 replays must be bitwise identical; every tile variant and the autotuned one
 must give the same results (FP64 and FP32 tiles sum in the same order: equal
 to 1e-12; the split tiles use two MFMA shapes: each within the oracle gate)."""
@@ -55,7 +56,7 @@ def _batch(L, systems, precision):
     return L.Batch(items, precision)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3", "f16x3"])
 def test_batch_against_oracle(precision):
     import paper_1405_2270_amd as L
     systems = _systems()
@@ -124,7 +125,8 @@ def test_batch_rejects_bad_systems():
 
 
 @pytest.mark.slow
-def test_config4_smallest_systems_against_oracle():
+@pytest.mark.parametrize("precision", ["f32", "f16x3"])
+def test_config4_smallest_systems_against_oracle(precision):
     # the batched workload's own systems: the six cheapest (oracle cost) in a
     # batch with six mid-size ones; sampled sub-box values and energies
     import paper_1405_2270_amd as L
@@ -133,7 +135,7 @@ def test_config4_smallest_systems_against_oracle():
     order = np.argsort(cost)
     pick = list(order[:6]) + list(order[200:206])
     chosen = [(systems[i], tuple(int(v) for v in systems[i].boxes[0])) for i in pick]
-    B = _batch(L, chosen, "f32")
+    B = _batch(L, chosen, precision)
     B.run()
     sec, err = B.report()
     assert err == 0
@@ -152,7 +154,9 @@ def test_config4_smallest_systems_against_oracle():
         ref = np.asarray(sample_columns(cols, coef, sel), np.float64) / s.h ** 3
         ref_abs = np.asarray(sample_columns(cols, np.abs(coef), sel), np.float64) / s.h ** 3
         got = B.out[k][sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
-        assert np.max(np.abs(got.double().cpu().numpy() - ref)) / np.max(np.abs(ref_abs)) < 1e-6
+        err_v = np.max(np.abs(got.double().cpu().numpy() - ref)) / np.max(np.abs(ref_abs))
+        print(f"config4 {precision} system {pick[k]}: rel_mag {err_v:.3e}")
+        assert err_v < gate(precision, len(coef))
     B.close()
 
 
