@@ -3,10 +3,14 @@
 // eq. scal, for the energy, and the reconstruction of one sub-box of at most
 // one unit cell per axis).
 //
-// One kernel, k_batch, drains a device work queue. Workgroups take task
-// indices from a global counter; the queue is a pipeline over groups of
-// systems taken by decreasing cost (the FOLDs of one group, the VECs of the
-// previous one, the TILEs of the one before):
+// One kernel, k_batch, drains device work queues, one per XCD: every task of
+// a system sits in one queue, so the system's folded density and factor
+// columns, re-read by all its VEC and TILE tasks, stay in that XCD's L2.
+// Workgroups take task indices from their own queue's counter (workgroup b
+// runs on XCD b mod 8: the dispatcher deals workgroups to the XCDs in turn)
+// and, once it is empty, from the other queues in turn. Each queue is a
+// pipeline over groups of its systems taken by decreasing cost (the FOLDs of
+// one group, the VECs of the previous one, the TILEs of the one before):
 //   FOLD (system, axis)  Phi_l[s][i] = sum_k rho_l[s][i + k n], the density
 //                        folded back over the lattice shifts (one lane per
 //                        residue class, suffix/prefix sums, no subtraction).
@@ -21,7 +25,8 @@
 // A VEC task waits until its system's FOLD tasks are done, a TILE until its
 // VEC tasks are done and the last of them has formed the energy (and, for
 // LS_F16X3, the per-rank scales of the FP16 tiles from the largest value of
-// every sub-box column). Every awaited task was dequeued earlier by a running
+// every sub-box column). Every awaited task is earlier in the same queue and
+// was dequeued earlier by a running
 // workgroup and never waits on a later one, so every wait ends; each wait is
 // also bounded (a spin limit sets an error flag and skips the task).
 // Producer: all lanes fence (agent scope), barrier, one lane increments the
@@ -67,7 +72,8 @@ struct SysDev {
   double* Fc[3];  // [K][e_l]
   double* coef;   // [K]
   double* fmax;   // [3][K] max_x |Fc_l[r][x]| (before the LS_F16X3 normalisation)
-  double* fsc;    // [2K + 1] FP16 tiles: left scales, right scales, output scale
+  double* fsc;    // [K + 1] FP16 tiles: left-operand rank factors, output scale
+  uint4* yp;      // LS_F16X3: [2 terms][nch][e_2][32 ranks] FP16 of 2^13 Fc_2 / 2^e_2,r
 };
 
 struct BatchArg {
@@ -77,17 +83,18 @@ struct BatchArg {
   const double* w;
   const double* qhw;  // support_halfwidth(tau) per node
   const double* qk;   // cell_half_norm(tau) per node
-  int* head;
+  int* qhead;  // [kBatchQueues] next task of each queue
   int* err;
   int* fold_done;
   int* vec_done;
   unsigned long long* t_start;
   unsigned long long* t_end;
   unsigned long long* t_phase;  // [3][2]: first start, last end per task type
-  int ntasks;
+  int qstart[9];  // queue q holds tasks qstart[q] .. qstart[q + 1] - 1
   int nsys;
   int f16;  // LS_F16X3: the last VEC task also forms the FP16 scales
 };
+constexpr int kBatchQueues = 8;  // one per XCD
 
 constexpr int kSpinLimit = 1 << 22;
 // density rank handled by the batch kernel (per-lane accumulators)
@@ -311,13 +318,36 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
         if (tid < e) {
           double v = vb[g * 256 + tid];
           if (ba.f16 && m > 0.0 && isfinite(m)) v = ldexp(v, -ilogb(m));
-          S.Fc[l][(size_t)r * e + tid] = v;
+          if (ba.f16 && l == 2) {
+            // the FP16 tiles' right operand, split once here: 2^13 v < 2^14
+            unsigned u[2];
+            split_f16((float)(8192.0 * v), u);
+            unsigned short* y16 = reinterpret_cast<unsigned short*>(S.yp);
+            const size_t nch = (size_t)(S.K + 31) >> 5;
+            const size_t at = (((size_t)(r >> 5)) * e + tid) * 32 + (r & 31);
+            y16[at] = (unsigned short)(u[0] >> 16);
+            y16[nch * e * 32 + at] = (unsigned short)(u[1] >> 16);
+          } else {
+            S.Fc[l][(size_t)r * e + tid] = v;
+          }
         }
         if (tid == 0) S.fmax[(size_t)l * S.K + r] = m;
         if (l == 0 && tid == 0) S.coef[r] = S.Z[nu] * ba.w[S.qoff + q0 + g];
       }
     }
     __syncthreads();
+  }
+  if (ba.f16 && l == 2 && nu == S.M0 - 1 && (S.K & 31) != 0) {
+    // zero the padding ranks K .. 32 nch - 1 of the last chunk (the tiles
+    // multiply them by zero rank factors; they must not hold NaN patterns)
+    unsigned short* y16 = reinterpret_cast<unsigned short*>(S.yp);
+    const size_t nch = (size_t)(S.K + 31) >> 5;
+    const int r0 = S.K & 31, npad = 32 - r0;
+    for (int idx = tid; idx < 2 * e * npad; idx += 256) {
+      const int t = idx / (e * npad), rem = idx - t * e * npad;
+      const int x = rem / npad, rr = r0 + rem - (rem / npad) * npad;
+      y16[((size_t)t * nch + nch - 1) * e * 32 + (size_t)x * 32 + rr] = 0;
+    }
   }
 }
 
@@ -342,16 +372,16 @@ __device__ void energy_task(const SysDev& S, double* sbuf) {
 
 // Scales of the FP16 tiles (LS_F16X3). The VEC tasks stored every sub-box
 // column divided by 2^e_l,r, e_l,r = floor(log2 max_x |Fc_l[r][x]|), so the
-// stored columns lie below 2 in magnitude. With E_r = e_0,r + e_1,r + e_2,r and
+// stored columns lie below 2 in magnitude, and the right operand already
+// split as 2^13 Fc_2[r][k] (below 2^14). With E_r = e_0,r + e_1,r + e_2,r and
 // t_r = floor(log2 |coef_r|) + E_r (the true rank term is below 2^(t_r + 4)),
 // T = max_r t_r over the ranks not identically zero on the sub-box:
-//   left operand   2^12 Fc_0[r][i] Fc_1[r][j]          (below 2^14),
-//   right operand  coef_r 2^(12 - T + E_r) Fc_2[r][k]  (below 2^14),
-//   output scale   2^(T - 24) (g = 24 - T undoes 2^12 2^(12 - T)).
-// Every factor is formed by ldexp of a finite value with a bounded result, so
-// nothing overflows; ranks that vanish on the sub-box (a zero column or
-// coefficient) get both scales 0. The same power-of-two scheme as the
-// LS_F16X3 reconstruction, with the exponents kept as integers.
+//   left operand   coef_r 2^(11 - T + E_r) Fc_0[r][i] Fc_1[r][j]  (below 2^14),
+//   output scale   2^(T - 24) (undoes 2^13 2^(11 - T)).
+// The rank factor is formed by ldexp of a finite value with a result below
+// 2^13, so nothing overflows; ranks that vanish on the sub-box (a zero column
+// or coefficient) get the factor 0. The power-of-two scheme of the LS_F16X3
+// reconstruction, with the exponents kept as integers.
 __device__ void f16_scales(const SysDev& S, int* ibuf) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int K = S.K;
@@ -371,12 +401,176 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
   T = max(max(ibuf[0], ibuf[1]), max(ibuf[2], ibuf[3]));
   __syncthreads();
   if (T == INT_MIN) T = 0;  // no live rank: every scale is 0
-  for (int r = tid; r < K; r += 256) {
-    const bool on = live(r);
-    S.fsc[r] = on ? 4096.0 : 0.0;
-    S.fsc[K + r] = on ? ldexp(S.coef[r], 12 - T + rexp(r)) : 0.0;
+  for (int r = tid; r < K; r += 256) S.fsc[r] = live(r) ? ldexp(S.coef[r], 11 - T + rexp(r)) : 0.0;
+  if (tid == 0) S.fsc[K] = ldexp(1.0, T - 24);
+}
+
+// One BM x BN tile of a sub-box for LS_F16X3: the left operand
+// a.coef[r] f0[r][i] f1[r][j] is rounded to FP32 and split into two FP16
+// terms in the tile (LDS, as split_tile), the right operand comes split from
+// the VEC tasks (yp: per term and 32-rank chunk, 32 FP16 ranks of each
+// column) and goes from global memory straight into the MFMA B fragments;
+// products x0 y0 + x0 y1 + x1 y0 on the FP16 MFMA, FP32
+// accumulation, out = a.scale * acc. smem holds split_smem_bytes<2, BM, BN, 1>().
+template <int BM, int BN, int WM, int WN, int MF>
+__device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
+                                         float* __restrict__ out, char* smem,
+                                         const uint4* __restrict__ yp) {
+  constexpr int NT = 2, BK = SPLIT_BK;
+  constexpr int KW = BK * BM / 256;
+  static_assert(BM >= 64 && 256 % BM == 0, "staging map");
+  static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
+  constexpr int FM = WM / MF, FN = WN / MF, NH = MF == 16 ? 1 : 2;
+  typedef SplitMma<MF> Mma;
+  typedef unsigned WsT[NT][BM][16];
+  WsT& Ws = *reinterpret_cast<WsT*>(smem);
+  double (*alphaS)[BK] = reinterpret_cast<double (*)[BK]>(smem + sizeof(WsT));
+
+  const int M = a.e0 * a.e1, nch = (a.K + BK - 1) / BK;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave / (BN / WN)) * WM, wc = (wave % (BN / WN)) * WN;
+  const int mw = tid % BM;
+  const int kbw = __builtin_amdgcn_readfirstlane(tid / BM) * KW;
+  const int i0 = row0 / a.e1;
+  const bool wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
+  const int m = row0 + mw;
+  const bool mok = m < M;
+  const int mi = mok ? m / a.e1 : 0;
+  const int mj = mok ? m - mi * a.e1 : 0;
+  const double* __restrict__ a1row = a.A1 + mi;
+  const double* __restrict__ a2row = a.A2 + mj;
+  // this lane's B rows (output columns), clamped into the sub-box (columns
+  // beyond it are computed from the last one and not stored)
+  const int lr = lane & (MF - 1), lg = lane / MF;
+  int brow[FN];
+#pragma unroll
+  for (int j = 0; j < FN; ++j) brow[j] = min(col0 + wc + MF * j + lr, a.e2 - 1);
+
+  double w[KW];
+  double cr = 0.0, ca = 1.0;
+  auto load_w = [&](int k0) {
+#pragma unroll
+    for (int kk = 0; kk < KW; ++kk) {
+      const int r = k0 + kbw + kk;
+      double v = 0.0;
+      if (r < a.K && mok) {
+        v = a2row[(size_t)r * a.len1];
+        if (!wfast) v *= a1row[(size_t)r * a.len0];
+      }
+      w[kk] = v;
+    }
+  };
+  auto load_alpha = [&](int k0) {
+    const int r = k0 + tid;
+    cr = 0.0;
+    ca = 1.0;
+    if (tid < BK && r < a.K) {
+      cr = a.coef[r];
+      if (wfast) ca = a.A1[(size_t)r * a.len0 + i0];
+    }
+  };
+  auto put_alpha = [&](int ab) {
+    if (tid < BK) alphaS[ab][tid] = cr * ca;
+  };
+  auto store_w = [&](int ab) {
+#pragma unroll
+    for (int g = 0; g < KW / 8; ++g) {
+      unsigned pk[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = g * 8 + 2 * q;
+        unsigned u0[NT], u1[NT];
+        split_f16((float)(alphaS[ab][kbw + kk] * w[kk]), u0);
+        split_f16((float)(alphaS[ab][kbw + kk + 1] * w[kk + 1]), u1);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
+      }
+      const int slot = ((kbw >> 3) + g) ^ lds_swz(mw);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        *reinterpret_cast<uint4*>(&Ws[t][mw][slot * 4]) = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+    }
+  };
+  typedef uint4 BFrag[NT][FN][NH];
+  auto load_b = [&](int c, BFrag& bv) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          bv[t][j][h] = yp[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg];
+  };
+
+  typename Mma::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
+
+  auto products = [&](const BFrag& bv) {
+    int slot[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) slot[h] = ((NH * h + lg) ^ lds_swz(lr)) * 4;
+#pragma unroll
+    for (int ta = NT - 1; ta >= 0; --ta) {
+      s8_t av[FM][NH];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          av[i][h] = *reinterpret_cast<const s8_t*>(&Ws[ta][wr + MF * i + lr][slot[h]]);
+#pragma unroll
+      for (int tb = NT - 1 - ta; tb >= 0; --tb)
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+              if constexpr (MF == 16)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    __builtin_bit_cast(h8_t, av[i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+              else
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                    __builtin_bit_cast(h8_t, av[i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
+                    acc[i][j], 0, 0, 0);
+            }
+    }
+  };
+  // per chunk c: the right operand's fragments are requested first, so that
+  // staging the left operand (and the barriers) covers their latency
+  BFrag bv;
+  load_alpha(0);
+  put_alpha(0);
+  load_alpha(BK);
+  load_w(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    load_b(c, bv);
+    if (c > 0) __syncthreads();  // Ws of chunk c - 1 consumed
+    store_w(c & 1);
+    put_alpha((c + 1) & 1);
+    __syncthreads();
+    if (c + 1 < nch) load_w((c + 1) * BK);
+    load_alpha((c + 2) * BK);
+    products(bv);
   }
-  if (tid == 0) S.fsc[2 * K] = ldexp(1.0, T - 24);
+
+  const float sc = (float)a.scale;
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < Mma::NV; ++v) {
+        const int row = row0 + wr + i * MF + Mma::drow(lane, v);
+        const int col = col0 + wc + j * MF + Mma::dcol(lane);
+        if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
+      }
 }
 
 // NT = 0: FP64 / FP32 tiles (recon_tile<T>); NT = 2, 3: split tiles with NT
@@ -384,17 +578,31 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
 // LS_F16X3, scaled FP16 terms (FMT = 1).
 template <typename T, int BM, int BN, int WM, int WN, int BK, int NT = 0, int MF = 16, int FMT = 0>
 __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
-  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1, FMT>() : recon_smem_bytes<T, BM, BN, BK>();
+  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1>() : recon_smem_bytes<T, BM, BN, BK>();
   constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
   __shared__ int s_task, s_flag;
+  const int home = blockIdx.x & (kBatchQueues - 1);
+  int tried = 0;  // thread 0: queues found empty so far (home first, then the next ones)
   for (;;) {
-    if (threadIdx.x == 0) s_task = atomicAdd(ba.head, 1);
+    if (threadIdx.x == 0) {
+      int t = -1;
+      while (tried < kBatchQueues) {
+        const int q = (home + tried) & (kBatchQueues - 1);
+        const int k = atomicAdd(&ba.qhead[q], 1);
+        if (k < ba.qstart[q + 1] - ba.qstart[q]) {
+          t = ba.qstart[q] + k;
+          break;
+        }
+        ++tried;
+      }
+      s_task = t;
+    }
     __syncthreads();
     // wave-uniform task index: descriptor loads become scalar loads
     const int t = __builtin_amdgcn_readfirstlane(s_task);
     __syncthreads();
-    if (t >= ba.ntasks) return;
+    if (t < 0) return;
     const Task tk = ba.tasks[t];
     const SysDev& S = ba.sys[tk.sys];
     if (threadIdx.x == 0) {
@@ -443,9 +651,8 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
         recon_tile<T, BM, BN, WM, WN, BK>(a, tm * BM, tn * BN, reinterpret_cast<T*>(S.out), smem);
       } else if constexpr (FMT == 1) {
         a.coef = S.fsc;
-        a.scale *= S.fsc[2 * S.K];
-        split_tile<NT, BM, BN, WM, WN, 1, MF, 1>(a, tm * BM, tn * BN,
-                                                 reinterpret_cast<float*>(S.out), smem, S.fsc + S.K);
+        a.scale *= S.fsc[S.K];
+        f16_tile<BM, BN, WM, WN, MF>(a, tm * BM, tn * BN, reinterpret_cast<float*>(S.out), smem, S.yp);
       } else {
         split_tile<NT, BM, BN, WM, WN, 1, MF>(a, tm * BM, tn * BN, reinterpret_cast<float*>(S.out),
                                               smem);
@@ -462,10 +669,8 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
 
 __global__ void k_batch_reset(BatchArg ba) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    *ba.head = 0;
-    *ba.err = 0;
-  }
+  if (i < kBatchQueues) ba.qhead[i] = 0;
+  if (i == 0) *ba.err = 0;
   if (i < 3) {
     ba.t_phase[2 * i] = ~0ull;
     ba.t_phase[2 * i + 1] = 0ull;
@@ -551,11 +756,11 @@ constexpr int kBatchTiles = 4;
 #ifndef LS_BATCH_GROUP
 #define LS_BATCH_GROUP 64
 #endif
-constexpr int kBatchGroup = LS_BATCH_GROUP;  // systems per pipeline stage of the queue
+constexpr int kBatchGroup = LS_BATCH_GROUP;  // systems per pipeline stage, over all queues
 
 struct SysHost {
   SysDev d;             // pointers into ws are offsets until bound
-  size_t off_phi, off_g, off_fc[3], off_coef, off_fmax, off_fsc;
+  size_t off_phi, off_g, off_fc[3], off_coef, off_fmax, off_fsc, off_yp;
   double cost;
 };
 
@@ -572,6 +777,7 @@ struct ls_batch {
   int bound_tile = -1;
   void* bound_ws = nullptr;
   int ntasks = 0;
+  int qstart[ls::kBatchQueues + 1] = {};
   int best_tile = 0;
   uint64_t shape_key = 0;  // autotune cache key: precision and the multiset of system shapes
   hipGraph_t graph = nullptr;
@@ -590,10 +796,11 @@ static ls_status build_tasks(ls_batch* B, int tile, TileCfg* cfg) {
     set_error("tile %d not available for the batch precision", tile);
     return LS_EUNSUPPORTED;
   }
-  // Systems in decreasing cost (LPT), in groups of kBatchGroup; the queue is
-  // a three-stage software pipeline over the groups: chunk t holds the FOLD
-  // tasks of group t, the VEC tasks of group t - 1 and the TILE tasks of
-  // group t - 2. Every task still waits only on tasks of earlier chunks (its
+  // Systems in decreasing cost (LPT), dealt to the queue with the least cost
+  // so far. Each queue is a three-stage software pipeline over groups of its
+  // systems (kBatchGroup / kBatchQueues each): chunk t holds the FOLD tasks of
+  // group t, the VEC tasks of group t - 1 and the TILE tasks of group t - 2.
+  // Every task still waits only on tasks of earlier chunks of its queue (its
   // system's FOLDs one chunk before its VECs, the VECs one chunk before its
   // TILEs), which running workgroups dequeued earlier, so every wait ends;
   // the chunk of other work between the stages covers most of the waiting,
@@ -603,27 +810,42 @@ static ls_status build_tasks(ls_batch* B, int tile, TileCfg* cfg) {
   for (int i = 0; i < B->count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return B->sys[a].cost > B->sys[b].cost; });
-  B->tasks.clear();
-  const int ngroups = (B->count + kBatchGroup - 1) / kBatchGroup;
-  auto group = [&](int g, auto&& emit) {
-    if (g < 0 || g >= ngroups) return;
-    for (int k = g * kBatchGroup; k < std::min(B->count, (g + 1) * kBatchGroup); ++k) emit(order[k]);
-  };
-  for (int t = 0; t < ngroups + 2; ++t) {
-    group(t, [&](int i) {
-      for (int l = 0; l < 3; ++l) B->tasks.push_back({TASK_FOLD, i, l, 0});
-    });
-    group(t - 1, [&](int i) {
-      for (int c = 0; c < 3 * B->sys[i].d.M0; ++c) B->tasks.push_back({TASK_VEC, i, c, 0});
-    });
-    group(t - 2, [&](int i) {
-      SysDev& d = B->sys[i].d;
-      const long long M = (long long)d.e[0] * d.e[1];
-      const int tm = (int)((M + cfg->bm - 1) / cfg->bm);
-      d.tiles_n = (d.e[2] + cfg->bn - 1) / cfg->bn;
-      for (int t2 = 0; t2 < tm * d.tiles_n; ++t2) B->tasks.push_back({TASK_TILE, i, t2, 0});
-    });
+  std::vector<int> queue[kBatchQueues];
+  double load[kBatchQueues] = {};
+  for (int i : order) {
+    int q = 0;
+    for (int k = 1; k < kBatchQueues; ++k)
+      if (load[k] < load[q]) q = k;
+    queue[q].push_back(i);
+    load[q] += B->sys[i].cost;
   }
+  const int gsize = std::max(1, kBatchGroup / kBatchQueues);
+  B->tasks.clear();
+  for (int q = 0; q < kBatchQueues; ++q) {
+    B->qstart[q] = (int)B->tasks.size();
+    const std::vector<int>& sq = queue[q];
+    const int ngroups = ((int)sq.size() + gsize - 1) / gsize;
+    auto group = [&](int g, auto&& emit) {
+      if (g < 0 || g >= ngroups) return;
+      for (int k = g * gsize; k < std::min((int)sq.size(), (g + 1) * gsize); ++k) emit(sq[k]);
+    };
+    for (int t = 0; t < ngroups + 2; ++t) {
+      group(t, [&](int i) {
+        for (int l = 0; l < 3; ++l) B->tasks.push_back({TASK_FOLD, i, l, 0});
+      });
+      group(t - 1, [&](int i) {
+        for (int c = 0; c < 3 * B->sys[i].d.M0; ++c) B->tasks.push_back({TASK_VEC, i, c, 0});
+      });
+      group(t - 2, [&](int i) {
+        SysDev& d = B->sys[i].d;
+        const long long M = (long long)d.e[0] * d.e[1];
+        const int tm = (int)((M + cfg->bm - 1) / cfg->bm);
+        d.tiles_n = (d.e[2] + cfg->bn - 1) / cfg->bn;
+        for (int t2 = 0; t2 < tm * d.tiles_n; ++t2) B->tasks.push_back({TASK_TILE, i, t2, 0});
+      });
+    }
+  }
+  B->qstart[kBatchQueues] = (int)B->tasks.size();
   B->ntasks = (int)B->tasks.size();
   return LS_OK;
 }
@@ -636,14 +858,14 @@ static BatchArg make_arg(ls_batch* B, char* ws) {
   a.w = (const double*)(ws + B->off_w);
   a.qhw = (const double*)(ws + B->off_hw);
   a.qk = (const double*)(ws + B->off_k);
-  a.head = (int*)(ws + B->off_ctrl);
+  a.qhead = (int*)(ws + B->off_ctrl + 128);
   a.err = (int*)(ws + B->off_ctrl) + 1;
   a.fold_done = (int*)(ws + B->off_fold);
   a.vec_done = (int*)(ws + B->off_vec);
   a.t_start = (unsigned long long*)(ws + B->off_ts);
   a.t_end = (unsigned long long*)(ws + B->off_te);
   a.t_phase = (unsigned long long*)(ws + B->off_ctrl + 64);
-  a.ntasks = B->ntasks;
+  for (int q = 0; q <= kBatchQueues; ++q) a.qstart[q] = B->qstart[q];
   a.nsys = B->count;
   a.f16 = B->precision == LS_F16X3 ? 1 : 0;
   return a;
@@ -670,6 +892,7 @@ static ls_status bind(ls_batch* B, void* ws_dev, int tile, hipStream_t stream) {
     d.coef = (double*)(ws + B->sys[i].off_coef);
     d.fmax = (double*)(ws + B->sys[i].off_fmax);
     d.fsc = (double*)(ws + B->sys[i].off_fsc);
+    d.yp = (uint4*)(ws + B->sys[i].off_yp);
     B->devsys[i] = d;
   }
   hipError_t e = hipMemcpyAsync(ws + B->off_sys, B->devsys.data(), sizeof(SysDev) * B->count,
@@ -831,8 +1054,8 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
   B->count = count;
   B->sys.resize(count);
   size_t off = 0;
-  B->off_ctrl = off;  // head, err at +0; phase stamps [6] u64 at +64
-  off += al(128);
+  B->off_ctrl = off;  // err at +4; phase stamps [6] u64 at +64; queue heads [8] at +128
+  off += al(256);
   B->off_fold = off;
   off += al(sizeof(int) * count);
   B->off_vec = off;
@@ -918,7 +1141,9 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
     h.off_fmax = off;
     off += al(sizeof(double) * 3 * (size_t)d.K);
     h.off_fsc = off;
-    off += al(sizeof(double) * (2 * (size_t)d.K + 1));
+    off += al(sizeof(double) * ((size_t)d.K + 1));
+    h.off_yp = off;
+    if (precision == LS_F16X3) off += al(2 * (size_t)((d.K + 31) / 32) * d.e[2] * 64);
     h.cost = (double)d.K * (2.0 * d.X) + 2.0 * d.K * (double)d.e[0] * d.e[1] * d.e[2] / 64.0;
     // task count bound: smallest tile 64x64
     max_tasks += 3 + 3 * (size_t)S.M0 +

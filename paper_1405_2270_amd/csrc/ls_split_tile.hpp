@@ -123,8 +123,8 @@ struct SplitMma<32> {
 // (rows of 16 dwords, 16-byte slot s of row R at s ^ lds_swz(R)), A rows
 // from arow, B rows from brow. Products x_ta y_tb with ta + tb <= NT - 1; the
 // B fragments of all terms stay in registers, the A fragments are read one
-// term at a time. F16: the terms are FP16 (the same MFMA shapes, f16 inputs).
-template <int NT, int MF, int FM, int FN, bool F16 = false>
+// term at a time.
+template <int NT, int MF, int FM, int FN>
 __device__ __forceinline__ void split_products(typename SplitMma<MF>::acc_t (&acc)[FM][FN],
                                                const unsigned* W, int wplane, const unsigned* Y,
                                                int yplane, int arow, int brow, int lane) {
@@ -157,15 +157,7 @@ __device__ __forceinline__ void split_products(typename SplitMma<MF>::acc_t (&ac
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int j = 0; j < FN; ++j) {
-            if constexpr (F16 && MF == 16)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                  __builtin_bit_cast(h8_t, av[i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
-                  acc[i][j], 0, 0, 0);
-            else if constexpr (F16)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                  __builtin_bit_cast(h8_t, av[i][h]), __builtin_bit_cast(h8_t, bv[tb][j][h]),
-                  acc[i][j], 0, 0, 0);
-            else if constexpr (MF == 16)
+            if constexpr (MF == 16)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                   __builtin_bit_cast(bf8_t, av[i][h]), __builtin_bit_cast(bf8_t, bv[tb][j][h]),
                   acc[i][j], 0, 0, 0);
@@ -177,25 +169,18 @@ __device__ __forceinline__ void split_products(typename SplitMma<MF>::acc_t (&ac
   }
 }
 
-template <int NT, int BM, int BN, int NBUF, int FMT = 0>
+template <int NT, int BM, int BN, int NBUF>
 constexpr int split_smem_bytes() {
-  return NBUF * NT * (BM + BN) * 16 * 4 + (FMT ? 4 : 2) * SPLIT_BK * 8;
+  return NBUF * NT * (BM + BN) * 16 * 4 + 2 * SPLIT_BK * 8;
 }
 
 // One BM x BN tile (rows row0.., columns col0..) of the box GEMM with both
 // operands split in the kernel; out is the box's output, smem holds
-// split_smem_bytes<NT, BM, BN, NBUF, FMT>() bytes (16-byte aligned). All 256
+// split_smem_bytes<NT, BM, BN, NBUF>() bytes (16-byte aligned). All 256
 // threads of the workgroup call it; it ends with the tile stored.
-// FMT = 0: bf16 terms of the FP32-rounded operands (split_fp32<NT>).
-// FMT = 1 (NT = 2): two FP16 terms (split_f16) of operands scaled per rank by
-// the caller's factors, so that both lie below 2^14 in magnitude: a.coef[r]
-// multiplies the left operand (with f0 and f1), ycoef[r] the right one (f2);
-// a.scale undoes the scaling at the store.
-template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF, int FMT = 0>
+template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
 __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
-                                           float* __restrict__ out, char* smem,
-                                           const double* __restrict__ ycoef = nullptr) {
-  static_assert(FMT == 0 || NT == 2, "FP16 terms come in pairs");
+                                           float* __restrict__ out, char* smem) {
   constexpr int BK = SPLIT_BK;
   constexpr int KW = BK * BM / 256, KY = BK * BN / 256;
   static_assert(BM >= 64 && BN >= 64 && 256 % BM == 0 && 256 % BN == 0, "staging map");
@@ -228,11 +213,8 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
   const double* __restrict__ a3row = a.A3 + a.o2 + col0 + ny;
   const int nchunk = (a.K + BK - 1) / BK;
 
-  double (*betaS)[BK] = alphaS + 2;  // FMT = 1: ycoef of the chunk
-
   double w[KW], y[KY];
   double cr = 0.0, ca = 1.0;  // raw parts of one alpha_r (threads tid < BK)
-  double cb = 0.0;            // FMT = 1: ycoef[r] (threads tid < BK)
 
   auto load_ops = [&](int k0) {
 #pragma unroll
@@ -255,24 +237,13 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
     const int r = k0 + tid;
     cr = 0.0;
     ca = 1.0;
-    cb = 0.0;
     if (tid < BK && r < a.K) {
       cr = a.coef[r];
       if (wfast) ca = a.A1[(size_t)r * a.len0 + a.o0 + i0];
-      if constexpr (FMT == 1) cb = ycoef[r];
     }
   };
   auto put_alpha = [&](int ab) {
-    if (tid < BK) {
-      alphaS[ab][tid] = cr * ca;
-      if constexpr (FMT == 1) betaS[ab][tid] = cb;
-    }
-  };
-  auto split = [&](double v, unsigned (&u)[NT]) {
-    if constexpr (FMT == 1)
-      split_f16((float)v, u);
-    else
-      split_fp32<NT>((float)v, u);
+    if (tid < BK) alphaS[ab][tid] = cr * ca;
   };
   auto store = [&](int sb, int ab) {
 #pragma unroll
@@ -282,8 +253,8 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        split(alphaS[ab][kbw + kk] * w[kk], u0);
-        split(alphaS[ab][kbw + kk + 1] * w[kk + 1], u1);
+        split_fp32<NT>((float)(alphaS[ab][kbw + kk] * w[kk]), u0);
+        split_fp32<NT>((float)(alphaS[ab][kbw + kk + 1] * w[kk + 1]), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -300,13 +271,8 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        if constexpr (FMT == 1) {
-          split(betaS[ab][kby + kk] * y[kk], u0);
-          split(betaS[ab][kby + kk + 1] * y[kk + 1], u1);
-        } else {
-          split(y[kk], u0);
-          split(y[kk + 1], u1);
-        }
+        split_fp32<NT>((float)y[kk], u0);
+        split_fp32<NT>((float)y[kk + 1], u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -340,8 +306,8 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
     __syncthreads();
     if (c + 1 < nchunk) load_ops((c + 1) * BK);
     load_alpha((c + 2) * BK);
-    split_products<NT, MF, FM, FN, FMT == 1>(acc, &Ws[sb][0][0][0], BM * 16, &Ys[sb][0][0][0],
-                                             BN * 16, wr, wc, lane);
+    split_products<NT, MF, FM, FN>(acc, &Ws[sb][0][0][0], BM * 16, &Ys[sb][0][0][0], BN * 16, wr,
+                                   wc, lane);
   }
 
   const float sc = (float)a.scale;
