@@ -253,16 +253,22 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
       const int j = j0 + ci;
       const bool cell_ok = lane < 63 && j < jend;
       vec_chunk_cells(ba, S.qoff + q0, ng, j, delta, S.h, cell_ok, lane < 63 ? bq + ci : nullptr);
+      // Gram: wave wv takes cells 64 wv .. 64 wv + 63 of the chunk, 4 per
+      // MFMA; the density values are requested before the barrier, whose
+      // wait for the other waves' cells covers their latency
+      double bvv[16];
+#pragma unroll
+      for (int k4 = 0; k4 < 16; ++k4) {
+        const int i = 64 * wv + 4 * k4 + ck;
+        const int jj = j0 + i;
+        bvv[k4] = (gq < Krho && i < CH && jj < jend) ? ph[(size_t)gq * W + jj] : 0.0;
+      }
       __syncthreads();
-      // Gram: wave wv takes cells 64 wv .. 64 wv + 63 of the chunk, 4 per MFMA
-#pragma unroll 4
+#pragma unroll
       for (int k4 = 0; k4 < 16; ++k4) {
         const int i = 64 * wv + 4 * k4 + ck;  // cell within the chunk
         const double av = (i < CH) ? bq[gq * kVecRow + i] : 0.0;  // rows g >= ng hold 0
-        const int jj = j0 + i;
-        double bvv = 0.0;
-        if (gq < Krho && i < CH && jj < jend) bvv = ph[(size_t)gq * W + jj];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bvv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bvv[k4], acc, 0, 0, 0);
       }
       if (j0 + CH - 1 >= jlo && j0 <= jhi) {  // uniform per chunk
         if (tid < e) {

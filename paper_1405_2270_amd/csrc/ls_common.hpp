@@ -81,7 +81,8 @@ __device__ __forceinline__ bool hermite_cell(double tau, double y0) {
   return tau <= 0.35 && fabs(a) * tau <= 0.25;
 }
 
-__device__ __forceinline__ double hermite_series(double tau, double y0) {
+// ea (nullable) receives exp(-a^2), the factor the series multiplies.
+__device__ __forceinline__ double hermite_series(double tau, double y0, double* ea) {
   const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
   const double c = 0.5 * tau;
   const double c2 = c * c;
@@ -115,7 +116,12 @@ __device__ __forceinline__ double hermite_series(double tau, double y0) {
     cp *= c2;
     sum = fma(h2 * cp, inv_fact[m], sum);
   }
-  return exp(-a * a) * sum;
+  const double e = exp(-a * a);
+  if (ea) *ea = e;
+  return e * sum;
+}
+__device__ __forceinline__ double hermite_series(double tau, double y0) {
+  return hermite_series(tau, y0, nullptr);
 }
 
 __device__ __forceinline__ double cell_integral(double tau, double y0) {
@@ -148,6 +154,16 @@ __device__ __forceinline__ double edge_value(double tau, double y) {
   const double u = fabs(tau * y);
   return u > 27.0 ? 0.0 : erfc_fit(u);
 }
+// The same edge value and the Gaussian G(y) = exp(-tau^2 y^2) there (0 beyond
+// |tau y| = 27, where it is below 1e-316).
+__device__ __forceinline__ double edge_value(double tau, double y, double* gauss) {
+  const double u = fabs(tau * y);
+  if (u > 27.0) {
+    *gauss = 0.0;
+    return 0.0;
+  }
+  return erfc_fit(u, gauss);
+}
 
 // Integral over cell [y0, y0 + 1] from its edge values eL = E(y0), eR = E(y0 + 1);
 // k = sqrt(pi) / (2 tau) (cell_half_norm), which callers may compute once per node.
@@ -162,6 +178,55 @@ __device__ __forceinline__ double cell_from_edges(double tau, double y0, double 
 }
 __device__ __forceinline__ double cell_from_edges(double tau, double y0, double eL, double eR) {
   return cell_from_edges(tau, y0, eL, eR, cell_half_norm(tau));
+}
+
+// sinh(x) for |x| <= 1/4 (Taylor series to x^11: truncation below 1e-17 relative)
+__device__ __forceinline__ double sinh_small(double x) {
+  const double x2 = x * x;
+  double p = 1.0 / 39916800.0;
+  p = fma(p, x2, 1.0 / 362880.0);
+  p = fma(p, x2, 1.0 / 5040.0);
+  p = fma(p, x2, 1.0 / 120.0);
+  p = fma(p, x2, 1.0 / 6.0);
+  p = fma(p, x2, 1.0);
+  return x * p;
+}
+
+// Value and derivative of one cell together (the derivative as
+// cell_derivative defines it), sharing their Gaussian factor:
+//  * series cells (hermite_cell): with a = tau (y0 + 1/2) and c = tau / 2,
+//    G(y0) - G(y1) = exp(-(a - c)^2) - exp(-(a + c)^2)
+//                  = 2 exp(-a^2) exp(-c^2) sinh(2 a c),
+//    exp(-a^2) from the series and |2 a c| = |a| tau <= 1/4; ec = exp(-c^2);
+//  * other cells: from the edge values eL, eR and edge Gaussians gL, gR:
+//    gL - gR where the two differ by a factor of 2 or more, else the larger
+//    one times expm1 of the exponent difference tau^2 (2 y0 + 1), which does
+//    not cancel.
+// k = cell_half_norm(tau). Returns the value's integral; *deriv gets the derivative.
+__device__ __forceinline__ double cell_value_deriv(double tau, double y0, double eL, double eR,
+                                                   double gL, double gR, double k, double ec,
+                                                   double* deriv) {
+  if (tau == 0.0) {
+    *deriv = 0.0;
+    return 1.0;
+  }
+  if (hermite_cell(tau, y0)) {
+    double ea;
+    const double v = hermite_series(tau, y0, &ea);
+    const double a = 0.5 * (tau * y0 + tau * (y0 + 1.0));
+    *deriv = 2.0 * ea * ec * sinh_small(a * tau);
+    return v;
+  }
+  const double x = tau * tau * (2.0 * y0 + 1.0);
+  if (fabs(x) >= 0.6931471805599453)
+    *deriv = gL - gR;
+  else if (fabs(y0) <= fabs(y0 + 1.0))
+    *deriv = -gL * expm1(-x);
+  else
+    *deriv = gR * expm1(x);
+  if (y0 >= 0.0) return k * (eL - eR);
+  if (y0 + 1.0 <= 0.0) return k * (eR - eL);
+  return k * ((1.0 - eL) + (1.0 - eR));
 }
 
 // d/da of the integral of exp(-t^2 (x - a)^2) over a cell, in grid units:

@@ -226,20 +226,20 @@ __global__ __launch_bounds__(256) void k_fold_density(const double* __restrict__
 // Value and derivative Grams of one (atom, axis, q) against the folded density:
 //   Gv[s] = sum_j h*B(j) Phi[s][j + p],  Gd[s] = sum_j dB(j) Phi[s][j + p]
 // RHO: the density ranks the per-lane accumulators hold (8 or kMaxRho).
-// four waves per SIMD: 128 registers (a few spilled): 0.43 against 0.46 ms
-// per forces call with three waves (150 registers, no spill) and 0.64 ms
-// with 16 accumulators per lane and the cell constants hoisted (183)
-#ifndef LS_FG_MINW
-#define LS_FG_MINW 4
-#endif
+// Waves per SIMD: three for FP64 accumulators (0.41 against 0.48 ms per
+// forces call with four, whose 128 registers spill), four for FP32 ones
+// (0.39 against 0.41 ms with three).
+template <typename T>
+constexpr int force_grams_waves() { return sizeof(T) == 8 ? 3 : 4; }
 template <typename T, int RHO>
-__global__ __launch_bounds__(256, LS_FG_MINW) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
+__global__ __launch_bounds__(256, force_grams_waves<T>()) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
                                                       Lat lat, const double* __restrict__ Phi,
                                                       int Krho, int X, int W, int K,
                                                       double* __restrict__ Gv,
                                                       double* __restrict__ Gd) {
   __shared__ double sh[256];
-  __shared__ double eb[256];
+  __shared__ double eb[256];  // edge values erfc(tau |y|)
+  __shared__ double gb[256];  // edge Gaussians exp(-tau^2 y^2)
   const int q = blockIdx.x;
   const int c = blockIdx.y;  // nu*3 + l
   const int nu = c / 3, l = c - 3 * (c / 3);
@@ -258,20 +258,29 @@ __global__ __launch_bounds__(256, LS_FG_MINW) void k_force_grams(const double* _
   const double hw = support_halfwidth(tau);
   const int jbeg = (int)fmax((double)-X, floor(delta - hw));
   const int jend = (int)fmin((double)X, ceil(delta + hw) + 1.0);
-  // chunks of 255 cells: thread t evaluates edge j0 + t once (shared edges)
+  // the node's constants of cell_value_deriv, once per workgroup
+  const double knorm = cell_half_norm(tau), ec = exp(-0.25 * tau * tau);
+  // chunks of 255 cells: thread t evaluates edge j0 + t once (shared edges):
+  // its erfc value and its Gaussian, from which the cell values and
+  // derivatives on both sides of it are formed
 #pragma unroll 1
   for (int j0 = jbeg; j0 < jend; j0 += 255) {
     const int j = j0 + (int)threadIdx.x;
-    // tau and delta opaque per chunk: the cell integral's tau-dependent
-    // constants are recomputed instead of held live across the loop
-    double tq = tau, dq = delta;
-    asm volatile("" : "+v"(tq), "+v"(dq));
-    eb[threadIdx.x] = edge_needed(tq, j, dq) ? edge_value(tq, (double)j - dq) : 0.0;
+    // tau, delta and the node's constants opaque per chunk: the cell
+    // integral's tau-dependent constants are recomputed instead of held live
+    // across the loop
+    double tq = tau, dq = delta, kq = knorm, eq = ec;
+    asm volatile("" : "+v"(tq), "+v"(dq), "+v"(kq), "+v"(eq));
+    double ev = 0.0, gv = 0.0;
+    if (edge_needed(tq, j, dq)) ev = edge_value(tq, (double)j - dq, &gv);
+    eb[threadIdx.x] = ev;
+    gb[threadIdx.x] = gv;
     __syncthreads();
     if (threadIdx.x < 255 && j < jend) {
       const double y0 = (double)j - dq;
-      const double bv = lat.h * cell_from_edges(tq, y0, eb[threadIdx.x], eb[threadIdx.x + 1]);
-      const double bd = cell_derivative(tq, y0);
+      double bd;
+      const double bv = lat.h * cell_value_deriv(tq, y0, eb[threadIdx.x], eb[threadIdx.x + 1],
+                                                 gb[threadIdx.x], gb[threadIdx.x + 1], kq, eq, &bd);
       if (bv != 0.0 || bd != 0.0) {
 #pragma unroll
         for (int s = 0; s < RHO; ++s) {
