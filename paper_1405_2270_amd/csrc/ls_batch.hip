@@ -185,16 +185,29 @@ __device__ __attribute__((noinline)) void vec_chunk_cells(const BatchArg& ba, in
                                                           int j, double delta, double h,
                                                           bool cell_ok, double* col) {
   const double y0 = (double)j - delta;
+  // the node tables' addresses are uniform: read through scalar registers,
+  // their loads become scalar loads
+  typedef const __attribute__((address_space(1))) double* gptr;
+  auto uptr = [](const double* p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (gptr)(((unsigned long long)hi << 32) | lo);
+  };
+  const gptr ttau = uptr(ba.tau + q0);
+  const gptr thw = uptr(ba.qhw + q0);
+  const gptr tk = uptr(ba.qk + q0);
+  ng = __builtin_amdgcn_readfirstlane(ng);
 #pragma unroll 1
   for (int g = 0; g < kVecQ; ++g) {
     double cv = 0.0;
     if (g < ng) {
-      const double tau = ba.tau[q0 + g], hw = ba.qhw[q0 + g];
+      const double tau = ttau[g], hw = thw[g];
       const bool in = (double)j >= delta - hw - 1.0 && (double)j <= delta + hw + 1.0;
       double eL = 0.0;
       if (in && edge_needed(tau, j, delta)) eL = edge_value(tau, y0);
       const double eR = __shfl_down(eL, 1, 64);
-      if (cell_ok && in) cv = h * cell_from_edges(tau, y0, eL, eR, ba.qk[q0 + g]);
+      if (cell_ok && in) cv = h * cell_from_edges(tau, y0, eL, eR, tk[g]);
     }
     if (col) col[g * kVecRow] = cv;
   }
