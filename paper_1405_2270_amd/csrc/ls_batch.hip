@@ -745,8 +745,7 @@ static bool batch_tile_split(int tile, TileCfg* c) {
   return false;
 }
 
-// LS_F16X3 tiles: scaled FP16 terms split inside the tile, the shapes of the
-// split-bf16 tiles
+// LS_F16X3 tiles (f16_tile)
 static bool batch_tile_f16(int tile, TileCfg* c) {
 #define LS_BH(ID, BM_, BN_, WM_, WN_, MF_)                                    \
   if (tile == ID) {                                                         \
@@ -757,8 +756,10 @@ static bool batch_tile_f16(int tile, TileCfg* c) {
   }
   LS_BH(1, 128, 128, 64, 64, 16)
   LS_BH(2, 128, 128, 64, 64, 32)
-  LS_BH(3, 128, 64, 64, 32, 32)
-  LS_BH(4, 64, 128, 32, 64, 32)
+  // the four waves side by side (128 rows x 32 columns each): no two waves
+  // load the same right-operand fragments
+  LS_BH(3, 128, 128, 128, 32, 16)
+  LS_BH(4, 128, 128, 128, 32, 32)
 #undef LS_BH
   return false;
 }
