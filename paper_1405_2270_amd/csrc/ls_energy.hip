@@ -203,36 +203,39 @@ __global__ __launch_bounds__(64) void k_energy_sum(const double* __restrict__ bs
   *E = e;
 }
 
-// Phi[(l*Krho + s)*W + i + X] = sum_{k in images} D_l[s][i + k n],  i in [-X, X + n - 1)
+// Phi[((l*W + i + X) * KP + s] = sum_{k in images} D_l[s][i + k n],  i in [-X, X + n - 1),
+// cell-major with KP >= Krho values per cell (zero for s >= Krho), so the
+// force Grams read one cell's densities as contiguous 16-byte loads
 __global__ __launch_bounds__(256) void k_fold_density(const double* __restrict__ D0,
                                                        const double* __restrict__ D1,
                                                        const double* __restrict__ D2, Lat lat,
-                                                       int Krho, int X, int W,
+                                                       int Krho, int KP, int X, int W,
                                                        double* __restrict__ Phi) {
   const int ii = blockIdx.x * 256 + threadIdx.x;
   const int s = blockIdx.y;
   const int l = blockIdx.z;
   if (ii >= W) return;
-  const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2)) + (size_t)s * lat.N[l];
-  const int i = ii - X;
   double acc = 0.0;
-  for (int k = lat.kmin[l]; k < lat.kmin[l] + lat.L[l]; ++k) {
-    const long long g = (long long)i + (long long)k * lat.n;
-    if (g >= 0 && g < lat.N[l]) acc += D[g];
+  if (s < Krho) {
+    const double* D = (l == 0 ? D0 : (l == 1 ? D1 : D2)) + (size_t)s * lat.N[l];
+    const int i = ii - X;
+    for (int k = lat.kmin[l]; k < lat.kmin[l] + lat.L[l]; ++k) {
+      const long long g = (long long)i + (long long)k * lat.n;
+      if (g >= 0 && g < lat.N[l]) acc += D[g];
+    }
   }
-  Phi[((size_t)l * Krho + s) * W + ii] = acc;
+  Phi[((size_t)l * W + ii) * KP + s] = acc;
 }
 
 // Value and derivative Grams of one (atom, axis, q) against the folded density:
 //   Gv[s] = sum_j h*B(j) Phi[s][j + p],  Gd[s] = sum_j dB(j) Phi[s][j + p]
-// RHO: the density ranks the per-lane accumulators hold (8 or kMaxRho).
-// Waves per SIMD: three for FP64 accumulators (0.41 against 0.48 ms per
-// forces call with four, whose 128 registers spill), four for FP32 ones
-// (0.39 against 0.41 ms with three).
-template <typename T>
-constexpr int force_grams_waves() { return sizeof(T) == 8 ? 3 : 4; }
+// RHO: the density ranks the per-lane accumulators hold (8 or kMaxRho), also
+// the folded density's values per cell (cell-major; 0.30 against 0.41 ms per
+// FP64 forces call with the rank-major layout's eight strided loads per cell).
+// Three waves per SIMD (0.30 / 0.29 ms per FP64 / FP32 forces call; four
+// spill their 128 registers: 0.30 / 0.31 ms).
 template <typename T, int RHO>
-__global__ __launch_bounds__(256, force_grams_waves<T>()) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
+__global__ __launch_bounds__(256, 3) void k_force_grams(const double* __restrict__ pos, QuadArg qa,
                                                       Lat lat, const double* __restrict__ Phi,
                                                       int Krho, int X, int W, int K,
                                                       double* __restrict__ Gv,
@@ -247,7 +250,8 @@ __global__ __launch_bounds__(256, force_grams_waves<T>()) void k_force_grams(con
   double delta;
   node_offset(pos[c], lat.b, lat.h, lat.n, &p, &delta);
   const double tau = qa.tau[q];
-  const double* ph = Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
+  // ph[j * RHO + s] = Phi_l[s][j + p]
+  const double* ph = Phi + ((size_t)l * W + p + X) * RHO;
   T av[RHO], ad[RHO];
 #pragma unroll
   for (int s = 0; s < RHO; ++s) {
@@ -282,13 +286,19 @@ __global__ __launch_bounds__(256, force_grams_waves<T>()) void k_force_grams(con
       const double bv = lat.h * cell_value_deriv(tq, y0, eb[threadIdx.x], eb[threadIdx.x + 1],
                                                  gb[threadIdx.x], gb[threadIdx.x + 1], kq, eq, &bd);
       if (bv != 0.0 || bd != 0.0) {
+        // the cell's RHO densities (zero past Krho), 16 bytes per load
+        const double2* c2 = reinterpret_cast<const double2*>(ph + (ptrdiff_t)j * RHO);
+        double fv[RHO];
+#pragma unroll
+        for (int q2 = 0; q2 < RHO / 2; ++q2) {
+          const double2 v = c2[q2];
+          fv[2 * q2] = v.x;
+          fv[2 * q2 + 1] = v.y;
+        }
 #pragma unroll
         for (int s = 0; s < RHO; ++s) {
-          if (s < Krho) {
-            const T f = (T)ph[(size_t)s * W + j];
-            av[s] += (T)bv * f;
-            ad[s] += (T)bd * f;
-          }
+          av[s] += (T)bv * (T)fv[s];
+          ad[s] += (T)bd * (T)fv[s];
         }
       }
     }
@@ -439,13 +449,16 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
   return launch_status("ls_energy (sum)");
 }
 
-// workspace: Phi [3][Krho][W] | Gv [3][K][Krho] | Gd [3][K][Krho] | Eatom [M0]
+// densities per folded cell: the force Grams' accumulator count
+static int fold_ranks(int Krho) { return Krho <= 8 ? 8 : kMaxRho; }
+
+// workspace: Phi [3][W][fold_ranks] | Gv [3][K][Krho] | Gd [3][K][Krho] | Eatom [M0]
 static void forces_layout(const Lat& L, int M0, int R, int Krho, size_t* off_gv, size_t* off_gd,
                           size_t* off_e, size_t* total, int* X, int* W) {
   *X = master_halfwidth(L);
   *W = 2 * (*X) + L.n;
   const size_t K = (size_t)M0 * R;
-  size_t o = align256((size_t)3 * Krho * (*W) * sizeof(double));
+  size_t o = align256((size_t)3 * fold_ranks(Krho) * (*W) * sizeof(double));
   *off_gv = o;
   o += align256(3 * K * Krho * sizeof(double));
   *off_gd = o;
@@ -505,8 +518,9 @@ static ls_status forces_run(const ls_lattice* lat, const ls_quad* quad, int32_t 
   double* Gd = (double*)(ws + off_gd);
   double* Eatom = (double*)(ws + off_e);
   const int K = M0 * qa.R;
-  hipLaunchKernelGGL(k_fold_density, dim3((W + 255) / 256, rho->K, 3), dim3(256), 0, stream,
-                     rho->f[0], rho->f[1], rho->f[2], L, rho->K, X, W, Phi);
+  const int KP = fold_ranks(rho->K);
+  hipLaunchKernelGGL(k_fold_density, dim3((W + 255) / 256, KP, 3), dim3(256), 0, stream,
+                     rho->f[0], rho->f[1], rho->f[2], L, rho->K, KP, X, W, Phi);
   st = launch_status("ls_forces (fold)");
   if (st != LS_OK) return st;
   // accumulators for 8 density ranks where they suffice (fewer registers per
