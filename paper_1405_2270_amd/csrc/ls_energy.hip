@@ -243,8 +243,10 @@ __global__ __launch_bounds__(256, 3) void k_force_grams(const double* __restrict
   __shared__ double sh[256];
   __shared__ double eb[256];  // edge values erfc(tau |y|)
   __shared__ double gb[256];  // edge Gaussians exp(-tau^2 y^2)
-  const int q = blockIdx.x;
-  const int c = blockIdx.y;  // nu*3 + l
+  // (atom, axis) fastest: the widest Gaussians (smallest q, the most cells)
+  // are dispatched first and the cheap narrow ones fill the tail
+  const int q = blockIdx.y;
+  const int c = blockIdx.x;  // nu*3 + l
   const int nu = c / 3, l = c - 3 * (c / 3);
   int p;
   double delta;
@@ -526,7 +528,7 @@ static ls_status forces_run(const ls_lattice* lat, const ls_quad* quad, int32_t 
   // accumulators for 8 density ranks where they suffice (fewer registers per
   // lane, more waves per SIMD for the cell integrals)
 #define LS_FG(T, RH)                                                                           \
-  hipLaunchKernelGGL((k_force_grams<T, RH>), dim3(qa.R, 3 * M0), dim3(256), 0, stream, pos_dev, \
+  hipLaunchKernelGGL((k_force_grams<T, RH>), dim3(3 * M0, qa.R), dim3(256), 0, stream, pos_dev, \
                      qa, L, Phi, rho->K, X, W, K, Gv, Gd)
   if (precision == LS_F64) {
     if (rho->K <= 8)

@@ -154,8 +154,10 @@ __global__ __launch_bounds__(BS, LS_ASM_MINW) void k_assemble_box_lds(const doub
   __shared__ double ms[kWindowCells];
   __shared__ double red[NW];
   const int R = qa.R;
-  const int q = blockIdx.x;
-  const int c = blockIdx.y;
+  // (atom, axis) fastest: the widest Gaussians (smallest q, the most cells to
+  // generate) are dispatched first and the cheap narrow ones fill the tail
+  const int q = blockIdx.y;
+  const int c = blockIdx.x;
   const int nu = c / 3, l = c - 3 * (c / 3);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (coef != nullptr && tid == 0 && l == 0) coef[nu * R + q] = Z[nu] * qa.w[q];
@@ -247,7 +249,7 @@ __global__ __launch_bounds__(BS, LS_ASM_MINW) void k_assemble_box_lds(const doub
     if (tid == 0) {
       double mx = red[0];
       for (int w = 1; w < NW; ++w) mx = fmax(mx, red[w]);
-      const size_t K = (size_t)(gridDim.y / 3) * R;
+      const size_t K = (size_t)(gridDim.x / 3) * R;
       rowmax[(size_t)l * K + nu * R + q] = mx;
     }
   }
@@ -447,7 +449,7 @@ extern "C" ls_status ls_assemble(const ls_lattice* lat, const ls_quad* quad, int
   if (masters_dev == nullptr && !L.periodic && Lmax <= 64 &&
       (long long)(2 * Lmax - 1) * L.n <= kWindowCells) {
     // box: master window in LDS, kernel vectors and assembly in one launch
-    dim3 grid(qa.R, 3 * M0);
+    dim3 grid(3 * M0, qa.R);
 hipLaunchKernelGGL((k_assemble_box_lds<kAsmRun, kAsmThreads>), grid, dim3(kAsmThreads), 0, stream,
                        pos_dev, Z_dev, qa, L.n, L.L[0], L.L[1], L.L[2], L.b, L.h,
                        derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, coef, rowmax_dev);
