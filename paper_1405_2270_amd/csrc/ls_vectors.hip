@@ -32,8 +32,9 @@ __global__ __launch_bounds__(256) void k_masters(const double* __restrict__ pos,
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int jj = wave * kMasterCellsPerWave + lane;  // master cell (edge for lane 63)
-  const int q = blockIdx.y;
-  const int c = blockIdx.z;  // nu*3 + l
+  // q slowest: the widest Gaussians (the most cells to evaluate) go first
+  const int q = blockIdx.z;
+  const int c = blockIdx.y;  // nu*3 + l
   int p;
   double delta;
   node_offset(pos[c], b, h, n, &p, &delta);
@@ -294,8 +295,9 @@ __global__ __launch_bounds__(256) void k_assemble_fused(const double* __restrict
                                                          double* __restrict__ f2,
                                                          const double* __restrict__ Z,
                                                          double* __restrict__ coef) {
-  const int q = blockIdx.y;
-  const int c = blockIdx.z;
+  // q slowest: the widest Gaussians (the most images in reach) go first
+  const int q = blockIdx.z;
+  const int c = blockIdx.y;
   const int nu = c / 3, l = c - 3 * (c / 3);
   const int N = lat.N[l];
   const int g = blockIdx.x * 256 + threadIdx.x;
@@ -350,8 +352,9 @@ __global__ __launch_bounds__(256) void k_assemble_tensor(const double* __restric
                                                           double* __restrict__ coef) {
   __shared__ int sI[256];
   __shared__ double sF[256];
-  const int q = blockIdx.y;
-  const int c = blockIdx.z;
+  // q slowest: the widest Gaussians (the most images in reach) go first
+  const int q = blockIdx.z;
+  const int c = blockIdx.y;
   const int nu = c / 3, l = c - 3 * (c / 3);
   const int N = tl.N[l];
   if ((int)blockIdx.x * 256 >= N) return;  // whole workgroup beyond this axis
@@ -413,7 +416,7 @@ extern "C" ls_status ls_kernel_vectors(const ls_lattice* lat, const ls_quad* qua
   LS_REQUIRE(X == master_halfwidth(L), "X = %d does not match the lattice (%d)", X,
              master_halfwidth(L));
   const int waves = (2 * X + kMasterCellsPerWave - 1) / kMasterCellsPerWave;
-  dim3 grid((waves + 3) / 4, qa.R, 3 * M0);
+  dim3 grid((waves + 3) / 4, 3 * M0, qa.R);
   hipLaunchKernelGGL(k_masters, grid, dim3(256), 0, stream, pos_dev, qa, L.b, L.h, L.n, X,
                      derivative ? 1 : 0, masters_dev);
   return launch_status("ls_kernel_vectors");
@@ -457,7 +460,7 @@ hipLaunchKernelGGL((k_assemble_box_lds<kAsmRun, kAsmThreads>), grid, dim3(kAsmTh
   } else if (masters_dev == nullptr) {
     const int Nmax = L.N[0] > L.N[1] ? (L.N[0] > L.N[2] ? L.N[0] : L.N[2])
                                      : (L.N[1] > L.N[2] ? L.N[1] : L.N[2]);
-    dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
+    dim3 grid((Nmax + 255) / 256, 3 * M0, qa.R);
     hipLaunchKernelGGL(k_assemble_fused, grid, dim3(256), 0, stream, pos_dev, qa, L,
                        derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, Z_dev, coef);
   } else {
@@ -521,7 +524,7 @@ extern "C" ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_
              "null device pointer");
   LS_REQUIRE(derivative || (Z_dev != nullptr && coef_dev != nullptr),
              "Z and coef are required for value vectors");
-  dim3 grid((Nmax + 255) / 256, qa.R, 3 * M0);
+  dim3 grid((Nmax + 255) / 256, 3 * M0, qa.R);
   hipLaunchKernelGGL(k_assemble_tensor, grid, dim3(256), 0, stream, pos_dev, qa, tl,
                      derivative ? 1 : 0, f0_dev, f1_dev, f2_dev, Z_dev,
                      derivative ? nullptr : coef_dev);
