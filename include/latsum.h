@@ -27,6 +27,9 @@
  *    call only. The library allocates no device memory and keeps no pointer
  *    after a call returns (its one fixed device array, the scratch of
  *    ls_forces_noalloc, is part of the loaded library).
+ *  - Workspaces (the ws_dev arguments) are 256-byte aligned, as hipMalloc
+ *    returns them: the kernels read them with 16-byte vector loads at
+ *    256-byte aligned offsets. A misaligned workspace is refused (LS_EINVAL).
  *  - Arguments are checked on the host before anything is enqueued; a
  *    failing check returns a negative ls_status and enqueues nothing.
  *    ls_last_error() then describes the failure (thread-local).

@@ -1211,6 +1211,7 @@ extern "C" ls_status ls_batch_run(ls_batch_t B, void* ws_dev, size_t ws_bytes, i
     set_error("workspace of %zu bytes required", B->ws_bytes);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   if (tile == 0) tile = B->best_tile ? B->best_tile : 2;
   ls_status st = bind(B, ws_dev, tile, stream);
   if (st != LS_OK) return st;

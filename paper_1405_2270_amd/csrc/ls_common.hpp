@@ -48,6 +48,10 @@ ls_status launch_status(const char* what);
 ls_status launch_rank_max(const double* f0, const double* f1, const double* f2, int K, int len0,
                           int len1, int len2, double* rmax, hipStream_t stream);
 
+// Workspaces are 256-byte aligned (as hipMalloc returns): kernels read them
+// with 16-byte vector loads at 256-byte aligned offsets.
+inline bool ws_aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255) == 0; }
+
 #define LS_REQUIRE(cond, ...)            \
   do {                                   \
     if (!(cond)) {                       \

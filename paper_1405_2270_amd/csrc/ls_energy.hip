@@ -424,6 +424,7 @@ extern "C" ls_status ls_energy(const ls_canon* P, const ls_canon* rho, int32_t p
     set_error("workspace of %zu bytes required", need);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   double* G = (double*)ws_dev;
   double* part = (double*)((char*)ws_dev + align256((size_t)3 * P->K * rho->K * sizeof(double)));
   const size_t boff = energy_bsum_offset(P->K, rho->K);
@@ -514,6 +515,7 @@ static ls_status forces_run(const ls_lattice* lat, const ls_quad* quad, int32_t 
               ws_dev == nullptr ? (size_t)0 : ws_bytes);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(ws_aligned(ws_dev), "the %s must be 256-byte aligned", scratch_name);
   char* ws = (char*)ws_dev;
   double* Phi = (double*)ws;
   double* Gv = (double*)(ws + off_gv);

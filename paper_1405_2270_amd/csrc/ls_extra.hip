@@ -171,6 +171,7 @@ extern "C" ls_status ls_nuclear_matrix(const ls_canon* P, int32_t Nb, const doub
     set_error("workspace of %zu bytes required", need);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   double* T = (double*)ws_dev;
   const int Pn = Nb * Nb;
   const double* g[3] = {g0_dev, g1_dev, g2_dev};

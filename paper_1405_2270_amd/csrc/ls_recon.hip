@@ -1487,6 +1487,7 @@ static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int3
     set_error("tile %d needs a workspace of %zu bytes", t, need);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(!pre || ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
   const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
@@ -1565,5 +1566,6 @@ extern "C" ls_status ls_reconstruct_prepare(const ls_canon* P, int32_t precision
     set_error("a workspace of %zu bytes is required", need);
     return LS_EWORKSPACE;
   }
+  LS_REQUIRE(ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   return prepare_ws(P, precision, ws_dev, stream);
 }

@@ -92,6 +92,17 @@ def test_invalid_host_arguments(lib):
     st = lib.ls_forces_noalloc(ctypes.byref(box), ctypes.byref(quad), 20000, dummy, dummy,
                                ctypes.byref(rho), 0, dummy, None, None)
     assert st == _lib.LS_EWORKSPACE and b"scratch" in lib.ls_last_error()
+    # workspaces must be 256-byte aligned (their kernels issue 16-byte loads):
+    # a large enough but misaligned one is refused on the host
+    misaligned = ctypes.c_void_p(4096 + 8)
+    st = lib.ls_forces(ctypes.byref(box), ctypes.byref(quad), 1, dummy, dummy, ctypes.byref(rho), 0,
+                       dummy, None, misaligned, 1 << 40, None)
+    assert st == _lib.LS_EINVAL and b"aligned" in lib.ls_last_error(), lib.ls_last_error()
+    P = _lib.Canon(4, (ctypes.c_int32 * 3)(24, 24, 24), (ctypes.c_void_p * 3)(16, 16, 16), 16)
+    st = lib.ls_energy(ctypes.byref(P), ctypes.byref(rho), 0, dummy, misaligned, 1 << 40, None)
+    assert st == _lib.LS_EINVAL and b"aligned" in lib.ls_last_error(), lib.ls_last_error()
+    st = lib.ls_reconstruct_prepare(ctypes.byref(P), 4, misaligned, 1 << 40, None)
+    assert st == _lib.LS_EINVAL and b"aligned" in lib.ls_last_error(), lib.ls_last_error()
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
     assert lib.ls_reconstruct_tiles(4) == 8 and lib.ls_reconstruct_workspace(None, 4) == 0
     assert lib.ls_reconstruct_workspace(None, 2) == 0
