@@ -12,7 +12,10 @@
 // <= eps ||x||_2 / sqrt(d - 1), so ||x - x_QTT||_2 <= eps ||x||_2.
 //
 // One workgroup per vector, the unfolding in LDS (m n <= 2^d doubles at every
-// step). The SVD is a one-sided Jacobi (Hestenes) iteration on the rows of C:
+// step). Two launches: the first allows ranks up to 8 (a small rotation
+// array, four workgroups per CU), the second, with ranks up to 32, redoes
+// only the vectors the first refused for their rank (the same rotations in the
+// same order: the result of a vector does not depend on which launch made it). The SVD is a one-sided Jacobi (Hestenes) iteration on the rows of C:
 // plane rotations of row pairs, in a round-robin order (m/2 disjoint pairs
 // per round, one group of lanes per pair, dot products by a shuffle tree
 // inside the group), until every pair is orthogonal to 1e-15 of its norms
@@ -27,7 +30,7 @@ namespace ls {
 
 constexpr int kQttMaxDigits = 12;      // N <= 4096: the unfolding fits in LDS
 constexpr int kQttMaxRank = 32;        // so unfoldings have at most 64 rows
-constexpr int kQttMaxRows = 2 * kQttMaxRank;
+constexpr int kQttFirstRank = 8;       // the first launch's rank limit
 constexpr int kQttMaxSweeps = 40;
 
 // status values per vector
@@ -45,21 +48,27 @@ __device__ __forceinline__ int rr_player(int i, int t, int m) {
   return i == 0 ? 0 : 1 + (i - 1 + t) % (m - 1);
 }
 
+// MAXRANK: the largest rank this launch keeps (a larger one gives
+// kQttRankLimit); REDO: work only on the vectors whose status is
+// kQttRankLimit (a later launch with a larger MAXRANK).
+template <int MAXRANK, bool REDO>
 __global__ __launch_bounds__(256) void k_qtt_compress(const double* __restrict__ X, int len,
                                                        long long ld, int d, double eps, int cap,
                                                        double* __restrict__ cores,
                                                        int* __restrict__ ranks,
                                                        int* __restrict__ status) {
+  constexpr int MR = 2 * MAXRANK;  // rows of an unfolding at most
   __shared__ double C[1 << kQttMaxDigits];
-  __shared__ double W[kQttMaxRows * kQttMaxRows];  // U^T; also staging for the next C
-  __shared__ double sig[kQttMaxRows];
-  __shared__ double tails[kQttMaxRows];
-  __shared__ int perm[kQttMaxRows];
+  __shared__ double W[MR * MR];  // U^T; also staging for the next C
+  __shared__ double sig[MR];
+  __shared__ double tails[MR];
+  __shared__ int perm[MR];
   __shared__ double red[4];
   __shared__ int flag;
   __shared__ int rk_sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int v = blockIdx.x;
+  if (REDO && status[v] != kQttRankLimit) return;  // uniform per workgroup
   const double* x = X + (long long)v * ld;
   double* out = cores + (long long)v * cap;
   int* rv = ranks + (long long)v * (d + 1);
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(256) void k_qtt_compress(const double* __restrict__
     __syncthreads();
     const int rk = rk_sh;
     if (st != kQttOk) break;
-    if (rk > kQttMaxRank) {
+    if (rk > MAXRANK) {
       st = kQttRankLimit;
       break;
     }
@@ -201,15 +210,24 @@ __global__ __launch_bounds__(256) void k_qtt_compress(const double* __restrict__
     off += m * rk;
     if (tid == 0) rv[k] = rk;
     __syncthreads();
-    // next unfolding: rows perm[0..rk) of the rotated C (sigma v^T), staged
-    // through W (rk n <= 2^d doubles, W holds 64^2 = 2^12)
-    for (int e = tid; e < rk * n; e += 256) {
-      const int b = e / n, j = e - b * n;
-      W[e] = C[perm[b] * n + j];
+    // next unfolding: rows perm[0..rk) of the rotated C (sigma v^T) moved to
+    // rows 0..rk-1, staged through W a block of columns at a time (a block is
+    // read from every kept row before any of it is written, and later blocks
+    // read only columns not yet written)
+    const int J = (MR * MR) / rk < n ? (MR * MR) / rk : n;
+    for (int j0 = 0; j0 < n; j0 += J) {
+      const int jn = n - j0 < J ? n - j0 : J;
+      for (int e = tid; e < rk * jn; e += 256) {
+        const int b = e / jn, j = e - b * jn;
+        W[e] = C[perm[b] * n + j0 + j];
+      }
+      __syncthreads();
+      for (int e = tid; e < rk * jn; e += 256) {
+        const int b = e / jn, j = e - b * jn;
+        C[b * n + j0 + j] = W[e];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < rk * n; e += 256) C[e] = W[e];
-    __syncthreads();
     r = rk;
   }
   if (st == kQttOk) {
@@ -312,8 +330,10 @@ extern "C" ls_status ls_qtt_compress(const double* x_dev, int32_t nvec, int32_t 
   LS_REQUIRE(std::isfinite(eps) && eps >= 0.0, "eps must be finite and >= 0");
   const int d = ls_qtt_digits(len);
   LS_REQUIRE(cap >= 2 * d, "cap must hold at least the rank-1 cores (%d doubles)", 2 * d);
-  hipLaunchKernelGGL(k_qtt_compress, dim3(nvec), dim3(256), 0, stream, x_dev, len, (long long)ld,
-                     d, eps, cap, cores_dev, ranks_dev, status_dev);
+  hipLaunchKernelGGL((k_qtt_compress<kQttFirstRank, false>), dim3(nvec), dim3(256), 0, stream,
+                     x_dev, len, (long long)ld, d, eps, cap, cores_dev, ranks_dev, status_dev);
+  hipLaunchKernelGGL((k_qtt_compress<kQttMaxRank, true>), dim3(nvec), dim3(256), 0, stream,
+                     x_dev, len, (long long)ld, d, eps, cap, cores_dev, ranks_dev, status_dev);
   return launch_status("ls_qtt_compress");
 }
 

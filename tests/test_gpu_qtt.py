@@ -90,6 +90,23 @@ def test_failures_are_reported():
     assert status.cpu().tolist() == [-2]
 
 
+def test_rank_limits_of_the_two_launches():
+    # one matrix whose vectors end in different launches: rank 1 (first
+    # launch, ranks up to 8), a sum of 8 cosines of rank 16 (each cosine has
+    # rank 2; redone by the second launch, ranks up to 32) and a random vector
+    # beyond rank 32 (refused)
+    import paper_1405_2270_amd as L
+    i = np.arange(4096, dtype=np.float64)
+    waves = sum(np.cos(wk * i + 0.3 * k) for k, wk in enumerate(np.linspace(0.013, 2.9, 8)))
+    X = np.array([0.999 ** i, waves])
+    ranks, _ = _check(L, X, 1e-12)
+    assert int(ranks[0].max()) == 1 and int(ranks[1].max()) == 16
+    rng = np.random.default_rng(47)
+    Xg = _t(np.vstack([X, rng.standard_normal((1, 4096))]))
+    cores, ranks, status = L.qtt_compress(Xg, 1e-12)
+    assert status.cpu().tolist() == [1, 1, -1]
+
+
 @pytest.mark.slow
 def test_headline_factor_rows_sampled():
     # the assembled vectors of the headline workload (N = 4096): 48 rows per
