@@ -45,11 +45,11 @@ def recon_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(precision):
+def recorded_traffic(precision, tile):
     """HBM bytes per reconstruction launch from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, calibrated by the copy kernel), or None when the
-    summary is missing, covers another precision, or the kernel sources have
-    changed since the counters were taken."""
+    summary is missing, covers another precision or tile, or the kernel sources
+    have changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_SUMMARY)
     if not os.path.exists(path):
         return None
@@ -59,7 +59,8 @@ def recorded_traffic(precision):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 fields[k.strip("`")] = v.strip().strip("`")
-    if fields.get("source_sha256") != recon_source_hash() or fields.get("precision") != precision:
+    if (fields.get("source_sha256") != recon_source_hash() or fields.get("precision") != precision
+            or fields.get("tile") != str(tile)):
         return None
     try:
         return int(fields["bytes_per_launch"])
@@ -725,15 +726,23 @@ def main():
     # reconstruction workspace (pre-split f1 and scales of the split
     # precisions), sized by the library for the largest need
     import ctypes
-    Fq, cq = L.assemble(spec, L.quadrature("S", q["M"], q["C0"], q["s"]), pos, Z)
+    rmq = torch.empty((3, K), dtype=torch.float64, device=dev)
+    Fq, cq = L.assemble(spec, L.quadrature("S", q["M"], q["C0"], q["s"]), pos, Z, rowmax=rmq)
     cn = L.api._canon(Fq, cq)
     rws = torch.empty(max([1] + [lib.ls_reconstruct_workspace(ctypes.byref(cn), L._lib.PRECISIONS[p])
                                  for p in precs]), dtype=torch.uint8, device=dev)
-    del Fq, cq, cn
     outs = {"f64": torch.empty(nvals, dtype=torch.float64, device=dev)}
     for p in precs:
         if p != "f64":
             outs[p] = torch.empty(nvals, dtype=torch.float32, device=dev)
+    # the reconstruction tile of every precision, measured on this call
+    # (ls_reconstruct_autotune, before anything is timed); the steps pass
+    # tile 0, which then takes it
+    tuned = {}
+    for p in ["f64"] + [p for p in precs if p != "f64"]:
+        t, ms = L.reconstruct_autotune(Fq, cq, boxes, outs[p], scale, p, ws=rws, rowmax=rmq, reps=3)
+        tuned[p] = {"tile": t, "ms": round(ms, 4), "tiles_timed": L.reconstruct_tiles(p)}
+    del Fq, cq, cn, rmq
     stream = torch.cuda.current_stream()
 
     energy_stream = torch.cuda.Stream()
@@ -937,7 +946,7 @@ def main():
             "f16x3": "mfma_f16_32x32x16_TFLOPs"}[best]
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 2),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": recorded_traffic(best),
+                "traffic": recorded_traffic(best, tuned[best]["tile"]),
                 "kernel": f"reconstruction ({best}), 16 boxes 256^3 per launch",
                 "peak_basis": (f"{PEAKS_TFLOPS[best]} TFLOP/s dense / {nprod} products"
                                if nprod > 1 else "dense peak of the dtype"),
@@ -1083,6 +1092,7 @@ def main():
         "mixed_speedup_vs_fp64": results["f64"]["ms_per_step"] / rb["ms_per_step"],
         "variants": {p: {k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in r.items()}
                      for p, r in results.items()},
+        "reconstruction_tiles": tuned,
         "energy": E,
         "forces": forces,
         "batched": batched,

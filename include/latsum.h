@@ -217,8 +217,9 @@ ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad,
  * scale = 1/h^3 gives cell averages of the potential; 1 gives the raw tensor.
  * out_dev: device; boxes are stored one after another, each [e0][e1][e2]
  * C-order; element type double for LS_F64, float otherwise.
- * boxes: host [nbox]. tile: 0 = automatic, otherwise a tile id from
- * ls_reconstruct_tiles (used by the autotuner).
+ * boxes: host [nbox]. tile: 0 = automatic (the tile ls_reconstruct_autotune
+ * measured fastest for this call's shape class, else a built-in choice),
+ * otherwise a tile id from 1 to ls_reconstruct_tiles(precision).
  * ws_dev, ws_bytes: device workspace, caller-owned, used by the split
  * precisions only: tiles 6 and above of LS_BF16X3 / LS_BF16X6 first split f1
  * into bf16 terms there (ls_reconstruct_workspace bytes); tile 0 uses them
@@ -278,6 +279,38 @@ size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision);
 
 /* Number of reconstruction tile variants for a precision (for autotuning). */
 int32_t ls_reconstruct_tiles(int32_t precision);
+/* Measured tile choice for ls_reconstruct (the same reconstruction, Appendix,
+ * eq. CP_form; the tiling is a project addition). Runs the call as given with
+ * tile 0 (which validates it), then every tile of `precision` that can run it
+ * (tiles that need the workspace only when ws_dev holds
+ * ls_reconstruct_workspace bytes; tiles that refuse the boxes are skipped):
+ * one untimed run and `reps` timed runs each, with events on `stream`, which
+ * it synchronizes. The fastest is entered in a per-process cache under the
+ * call's shape class (precision, K, len[], whether the workspace serves the
+ * pre-split tiles, nbox and the boxes' extents in order; not their offsets,
+ * the factor values or `scale`), so that later ls_reconstruct and
+ * ls_reconstruct_prepared calls of the class with tile 0 take it. out_dev
+ * holds the last tile's result (every tile writes the reconstruction, within
+ * the precision's rounding; tiles of one MFMA shape agree bit for bit).
+ * tile_out: host, the chosen tile; ms_out (host, nullable): its mean time per
+ * call in ms, preparation included. Thread-safe; calls on several threads
+ * time each other's work.
+ * Errors: those of ls_reconstruct for the call as given; LS_EINVAL (reps not
+ * in [1, 1000], null tile_out); LS_EHIP (event failure, e.g. on a stream
+ * being captured).
+ */
+ls_status ls_reconstruct_autotune(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                  double scale, int32_t precision, void* out_dev, void* ws_dev,
+                                  size_t ws_bytes, int32_t reps, hipStream_t stream,
+                                  int32_t* tile_out, double* ms_out);
+/* The tile ls_reconstruct_autotune chose for this call's shape class, 0 if
+ * it has not been tuned in this process (host only; ws_dev is only compared
+ * with NULL). tile: host; ms (host, nullable): its time when tuned, else 0.
+ * Errors: LS_EINVAL (null pointers, nbox < 1, unknown precision).
+ */
+ls_status ls_reconstruct_tuned_tile(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                    int32_t precision, const void* ws_dev, size_t ws_bytes,
+                                    int32_t* tile, double* ms);
 
 /*
  * Energy as a canonical scalar product (Appendix, eq. scal) with a density

@@ -86,6 +86,15 @@ _SIGNATURES = {
                                               ctypes.c_size_t, ctypes.c_void_p]),
     "ls_reconstruct_workspace": (ctypes.c_size_t, [ctypes.POINTER(Canon), ctypes.c_int32]),
     "ls_reconstruct_tiles": (ctypes.c_int32, [ctypes.c_int32]),
+    "ls_reconstruct_autotune": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
+                                               ctypes.c_double, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_double)]),
+    "ls_reconstruct_tuned_tile": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
+                                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_double)]),
     "ls_energy_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "ls_energy": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Canon), ctypes.c_int32,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),

@@ -351,6 +351,52 @@ def reconstruct_tiles(precision):
     return int(lib().ls_reconstruct_tiles(_lib.PRECISIONS[precision]))
 
 
+def _boxes_c(boxes):
+    boxes = [tuple(int(v) for v in b) for b in boxes]
+    if not boxes or any(len(b) != 6 for b in boxes):
+        raise ValueError("boxes: one or more (o0, o1, o2, e0, e1, e2)")
+    cb = (Box * len(boxes))(*[Box((ctypes.c_int32 * 3)(*b[:3]), (ctypes.c_int32 * 3)(*b[3:]))
+                              for b in boxes])
+    return boxes, cb
+
+
+def reconstruct_autotune(F, coef, boxes, out, scale=1.0, precision="f64", ws=None, rowmax=None,
+                         reps=3):
+    """Times every tile of ``precision`` on this call (``ls_reconstruct_autotune``,
+    synchronous) into the caller's flat ``out``; later calls of the same shape
+    class with tile 0 take the fastest. Returns (tile, ms per call)."""
+    boxes, cb = _boxes_c(boxes)
+    prec = _lib.PRECISIONS[precision]
+    canon = _canon(F, coef, rowmax=rowmax)
+    dtype = torch.float64 if prec == _lib.LS_F64 else torch.float32
+    _out_tensor(out, dtype, sum(max(b[3], 0) * max(b[4], 0) * max(b[5], 0) for b in boxes),
+                F[0].device)
+    ws, nws = _recon_ws(canon, prec, F[0].device, _ws_tensor(ws, F[0].device))
+    t, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    check("ls_reconstruct_autotune",
+          lib().ls_reconstruct_autotune(ctypes.byref(canon), cb, len(boxes), float(scale), prec,
+                                        _ptr(out), _ptr(ws), nws, int(reps), _stream(),
+                                        ctypes.byref(t), ctypes.byref(ms)))
+    return int(t.value), float(ms.value)
+
+
+def reconstruct_tuned_tile(F, coef, boxes, precision="f64", ws_bytes=None):
+    """(tile, ms) the autotuner chose for this shape class, (0, 0.0) if none.
+    ``ws_bytes``: the workspace the calls pass (None: as ``reconstruct``
+    allocates it)."""
+    boxes, cb = _boxes_c(boxes)
+    prec = _lib.PRECISIONS[precision]
+    canon = _canon(F, coef)
+    need = int(lib().ls_reconstruct_workspace(ctypes.byref(canon), prec))
+    nws = need if ws_bytes is None else int(ws_bytes)
+    t, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    check("ls_reconstruct_tuned_tile",
+          lib().ls_reconstruct_tuned_tile(ctypes.byref(canon), cb, len(boxes), prec,
+                                          ctypes.c_void_p(1 if nws > 0 else 0), nws,
+                                          ctypes.byref(t), ctypes.byref(ms)))
+    return int(t.value), float(ms.value)
+
+
 def energy(F, coef, D, d, precision="f64", ws=None):
     """E = <P, rho> (eq. scal) as a device scalar tensor."""
     cP, cR = _canon(F, coef), _canon(D, d, "density")

@@ -14,8 +14,9 @@
 // One workgroup per vector, the unfolding in LDS (m n <= 2^d doubles at every
 // step). Two launches: the first allows ranks up to 8 (a small rotation
 // array, four workgroups per CU), the second, with ranks up to 32, redoes
-// only the vectors the first refused for their rank (the same rotations in the
-// same order: the result of a vector does not depend on which launch made it). The SVD is a one-sided Jacobi (Hestenes) iteration on the rows of C:
+// only the vectors the first refused for their rank (the same rotations in
+// the same order: the result of a vector does not depend on which launch
+// made it). The SVD is a one-sided Jacobi (Hestenes) iteration on the rows of C:
 // plane rotations of row pairs, in a round-robin order (m/2 disjoint pairs
 // per round, one group of lanes per pair, dot products by a shuffle tree
 // inside the group), until every pair is orthogonal to 1e-15 of its norms

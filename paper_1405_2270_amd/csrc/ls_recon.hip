@@ -23,7 +23,10 @@
 // (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
 // f64 one (checked on gfx950).
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "ls_split_tile.hpp"
 
@@ -1448,6 +1451,42 @@ static ls_status check_canon(const ls_canon* P) {
   return LS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Measured tile choice: ls_reconstruct_autotune times every tile of a
+// precision on the caller's own call and keeps the fastest per shape class;
+// a call with tile 0 of a tuned class takes it, other calls the built-in
+// choice (auto_tile).
+// ---------------------------------------------------------------------------
+namespace {
+struct ReconTune {
+  int tile;
+  double ms;
+};
+std::mutex g_rtune_mu;
+std::map<std::vector<long long>, ReconTune> g_rtune;
+
+// shape class of a call: precision, rank, factor lengths, whether the
+// workspace serves the pre-split tiles, and the boxes' extents in order
+// (their offsets do not change the work)
+std::vector<long long> recon_key(const ls_canon* P, const ls_box* boxes, int nbox,
+                                 int precision, bool have_ws) {
+  std::vector<long long> k = {precision, P->K, P->len[0], P->len[1], P->len[2],
+                              have_ws ? 1 : 0, nbox};
+  for (int b = 0; b < nbox; ++b)
+    for (int l = 0; l < 3; ++l) k.push_back(boxes[b].e[l]);
+  return k;
+}
+
+int tuned_tile(const ls_canon* P, const ls_box* boxes, int nbox, int precision, bool have_ws,
+               double* ms) {
+  std::lock_guard<std::mutex> lock(g_rtune_mu);
+  const auto it = g_rtune.find(recon_key(P, boxes, nbox, precision, have_ws));
+  if (it == g_rtune.end()) return 0;
+  if (ms) *ms = it->second.ms;
+  return it->second.tile;
+}
+}  // namespace
+
 // ls_reconstruct, or with prepared = true ls_reconstruct_prepared (the
 // workspace already holds the preparation of prepare_ws)
 static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int32_t nbox,
@@ -1474,9 +1513,10 @@ static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int3
   }
   const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
   const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
-  const int t = tile ? tile
-                     : auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1],
-                                 boxes[0].e[2], boxes[0].e[1], have_ws);
+  int t = tile ? tile : tuned_tile(P, boxes, nbox, precision, have_ws, nullptr);
+  if (t == 0)
+    t = auto_tile(precision, (long long)boxes[0].e[0] * boxes[0].e[1], boxes[0].e[2],
+                  boxes[0].e[1], have_ws);
   BoxSet probe;
   if (!dispatch(precision, t, stream, probe, nullptr, true)) {
     set_error("tile %d not available for precision %d", t, precision);
@@ -1552,6 +1592,96 @@ extern "C" ls_status ls_reconstruct_prepared(const ls_canon* P, const ls_box* bo
                                              hipStream_t stream) {
   return reconstruct_common(P, boxes, nbox, scale, precision, tile, out_dev, ws_dev, ws_bytes,
                             stream, true);
+}
+
+extern "C" ls_status ls_reconstruct_autotune(const ls_canon* P, const ls_box* boxes,
+                                             int32_t nbox, double scale, int32_t precision,
+                                             void* out_dev, void* ws_dev, size_t ws_bytes,
+                                             int32_t reps, hipStream_t stream, int32_t* tile_out,
+                                             double* ms_out) {
+  clear_error();
+  LS_REQUIRE(tile_out != nullptr, "null pointer");
+  *tile_out = 0;
+  if (ms_out) *ms_out = 0.0;
+  LS_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000] (got %d)", reps);
+  // the call as given (tile 0) validates every argument before anything is timed
+  ls_status st = reconstruct_common(P, boxes, nbox, scale, precision, 0, out_dev, ws_dev,
+                                    ws_bytes, stream, false);
+  if (st != LS_OK) return st;
+  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) {
+    set_error("event creation failed");
+    return LS_EHIP;
+  }
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("event creation failed");
+    return LS_EHIP;
+  }
+  int best = 0;
+  float best_ms = 0.f;
+  for (int t = 1; t <= n_tiles(precision) && st == LS_OK; ++t) {
+    BoxSet probe;
+    if (!dispatch(precision, t, stream, probe, nullptr, true)) continue;
+    if (presplit_tile(precision, t) && !have_ws) continue;
+    // untimed first run; a tile that refuses this call's shapes is skipped
+    st = reconstruct_common(P, boxes, nbox, scale, precision, t, out_dev, ws_dev, ws_bytes,
+                            stream, false);
+    if (st == LS_EUNSUPPORTED) {
+      st = LS_OK;
+      continue;
+    }
+    if (st != LS_OK) break;
+    (void)hipEventRecord(e0, stream);
+    for (int i = 0; i < reps && st == LS_OK; ++i)
+      st = reconstruct_common(P, boxes, nbox, scale, precision, t, out_dev, ws_dev, ws_bytes,
+                              stream, false);
+    (void)hipEventRecord(e1, stream);
+    if (st != LS_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      set_error("autotune synchronisation failed");
+      st = LS_EHIP;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (best == 0 || ms < best_ms) {
+      best = t;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LS_OK) return st;
+  if (best == 0) {
+    set_error("no tile of precision %d runs this call", precision);
+    return LS_EUNSUPPORTED;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_rtune_mu);
+    g_rtune[recon_key(P, boxes, nbox, precision, have_ws)] = ReconTune{best, (double)best_ms};
+  }
+  *tile_out = best;
+  if (ms_out) *ms_out = best_ms;
+  return LS_OK;
+}
+
+extern "C" ls_status ls_reconstruct_tuned_tile(const ls_canon* P, const ls_box* boxes,
+                                               int32_t nbox, int32_t precision,
+                                               const void* ws_dev, size_t ws_bytes,
+                                               int32_t* tile, double* ms) {
+  clear_error();
+  LS_REQUIRE(P != nullptr && boxes != nullptr && tile != nullptr, "null pointer");
+  LS_REQUIRE(nbox >= 1, "nbox must be >= 1");
+  LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
+  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
+  if (ms) *ms = 0.0;
+  *tile = tuned_tile(P, boxes, nbox, precision, have_ws, ms);
+  return LS_OK;
 }
 
 extern "C" ls_status ls_reconstruct_prepare(const ls_canon* P, int32_t precision, void* ws_dev,

@@ -103,6 +103,26 @@ def test_invalid_host_arguments(lib):
     assert st == _lib.LS_EINVAL and b"aligned" in lib.ls_last_error(), lib.ls_last_error()
     st = lib.ls_reconstruct_prepare(ctypes.byref(P), 4, misaligned, 1 << 40, None)
     assert st == _lib.LS_EINVAL and b"aligned" in lib.ls_last_error(), lib.ls_last_error()
+    # the reconstruction autotuner refuses a bad repetition count on the host;
+    # its cache answers "not tuned" for a class never timed (host only)
+    B1 = (_lib.Box * 1)(_lib.Box((ctypes.c_int32 * 3)(0, 0, 0), (ctypes.c_int32 * 3)(4, 4, 4)))
+    tile, ms = ctypes.c_int32(-1), ctypes.c_double(-1.0)
+    for reps in (0, 1001):
+        st = lib.ls_reconstruct_autotune(ctypes.byref(P), B1, 1, 1.0, 4, dummy, dummy, 1 << 40, reps,
+                                         None, ctypes.byref(tile), ctypes.byref(ms))
+        assert st == _lib.LS_EINVAL and b"reps" in lib.ls_last_error(), lib.ls_last_error()
+        assert tile.value == 0 and ms.value == 0.0
+    st = lib.ls_reconstruct_autotune(ctypes.byref(P), B1, 1, 1.0, 4, dummy, dummy, 1 << 40, 3,
+                                     None, None, None)
+    assert st == _lib.LS_EINVAL
+    for prec in range(5):
+        st = lib.ls_reconstruct_tuned_tile(ctypes.byref(P), B1, 1, prec, dummy, 1 << 40,
+                                           ctypes.byref(tile), ctypes.byref(ms))
+        assert st == _lib.LS_OK and tile.value == 0 and ms.value == 0.0
+    assert lib.ls_reconstruct_tuned_tile(ctypes.byref(P), B1, 1, 7, None, 0, ctypes.byref(tile),
+                                         None) == _lib.LS_EINVAL
+    assert lib.ls_reconstruct_tuned_tile(ctypes.byref(P), B1, 0, 0, None, 0, ctypes.byref(tile),
+                                         None) == _lib.LS_EINVAL
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
     assert lib.ls_reconstruct_tiles(4) == 8 and lib.ls_reconstruct_workspace(None, 4) == 0
     assert lib.ls_reconstruct_workspace(None, 2) == 0

@@ -25,6 +25,7 @@ from oracle.lattice import Geometry, factor_entries
 from oracle.canonical import sample_columns
 from oracle.quadrature import rule_s
 from workloads import config2
+from _gates import gate
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +104,37 @@ def test_stream_matches_oracle_sampled(setup, precision, tile):
         got = V[sel_local[0][sel[:, 0]], sel_local[1][sel[:, 1]], sel_local[2][sel[:, 2]]]
         err = np.max(np.abs(got.double().cpu().numpy() - ref))
         assert err / np.max(np.abs(ref_abs)) < 1e-6, (precision, tile, b, err)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "f16x3"])
+def test_autotune_choice_is_kept_per_shape_class(setup, precision):
+    # ls_reconstruct_autotune times every tile on the call and caches the
+    # fastest under the call's shape class; tile 0 then runs it (bit for bit
+    # the explicit tile), other extents stay untuned, offsets do not matter
+    L, s, F, coef = setup
+    boxes = _boxes(s)[1:]
+    scale = 1.0 / (s.b / s.n) ** 3
+    dtype = torch.float64 if precision == "f64" else torch.float32
+    n = sum(b[3] * b[4] * b[5] for b in boxes)
+    assert L.reconstruct_tuned_tile(F, coef, boxes, precision) == (0, 0.0)
+    out = torch.full((n,), float("nan"), dtype=dtype, device=dev)
+    tile, ms = L.reconstruct_autotune(F, coef, boxes, out, scale, precision, reps=2)
+    torch.cuda.synchronize()
+    print(f"autotune {precision}: tile {tile}, {ms:.4f} ms")
+    assert 1 <= tile <= L.reconstruct_tiles(precision) and ms > 0
+    t2, ms2 = L.reconstruct_tuned_tile(F, coef, boxes, precision)
+    assert t2 == tile and abs(ms2 - ms) <= 1e-6 * ms
+    a = L.reconstruct(F, coef, boxes, scale, precision, 0)
+    b = L.reconstruct(F, coef, boxes, scale, precision, tile)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    # the autotuner's output is the reconstruction (the last tile it ran),
+    # within the precision's gate (rel_mag against the FP64 path)
+    ref = torch.cat([x.reshape(-1) for x in L.reconstruct(F, coef, boxes, scale, "f64")])
+    mag = torch.cat([x.reshape(-1) for x in L.reconstruct(F, coef.abs(), boxes, scale, "f64")])
+    err = float((out.double() - ref).abs().max() / mag.abs().max())
+    assert err < gate(precision, coef.numel()), err
+    other = [b[:5] + (b[5] - 1,) for b in boxes]
+    assert L.reconstruct_tuned_tile(F, coef, other, precision)[0] == 0
+    moved = [(b[0] + 1,) + b[1:] for b in boxes]
+    assert L.reconstruct_tuned_tile(F, coef, moved, precision)[0] == tile
