@@ -816,8 +816,9 @@ def main():
         # reconstruction (second stream), before it on the same stream, and
         # beside the reconstruction's workspace preparation only; a persistent
         # reconstruction kernel that fills every CU can lose more to the
-        # energy's workgroups than the overlap saves, so all are timed and the
-        # fastest one is reported.
+        # energy's workgroups than the overlap saves, so all are timed once
+        # to choose one, and the chosen one is timed again for the reported
+        # figure (so that it carries no best-of-three selection).
         qt = quad()
         timed = {}
         for sched, overlap in (("overlap", "beside"), ("serial", "serial"), ("prepare", "prepare")):
@@ -839,12 +840,22 @@ def main():
             torch.cuda.synchronize()
             timed[sched] = (time.perf_counter() - t0, (g, gF, gc, gE))
         sched = min(timed, key=lambda k: timed[k][0])
-        wall, graphs[prec] = timed[sched]
+        graphs[prec] = timed[sched][1]
+        g = graphs[prec][0]
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            quad()
+            g.replay()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
         results[prec] = {"ms_per_step": 1e3 * wall / args.steps,
                          "eager_ms_per_step": 1e3 * eager / args.steps,
                          "schedule": sched,
-                         "other_schedule_ms_per_step": {k: round(1e3 * v[0] / args.steps, 4)
-                                                        for k, v in timed.items() if k != sched},
+                         "schedule_trial_ms_per_step": {k: round(1e3 * v[0] / args.steps, 4)
+                                                        for k, v in timed.items()},
                          "assembly_ms": asm_ms, "energy_ms": en_ms, "recon_ms": recon_ms}
 
     # errors of the mixed variants against the FP64 path (not timed)
@@ -1084,7 +1095,7 @@ def main():
                                 "prepare": "the energy on a second stream beside the "
                                            "reconstruction's workspace preparation, joined before "
                                            "its kernels"}[rb["schedule"]] +
-                "; the fastest of three schedules)",
+                "; the fastest of three schedules in a trial run, timed again for this figure)",
         "values_per_step": nvals,
         "fp64": {"values_per_s": results["f64"]["values_per_s"],
                  "ms_per_step": results["f64"]["ms_per_step"],
