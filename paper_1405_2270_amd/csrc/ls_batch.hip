@@ -424,6 +424,15 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
   if (tid == 0) S.fsc[K] = ldexp(1.0, T - 24);
 }
 
+// A pointer into device memory as a global-address-space pointer: its loads
+// become global loads, which count only in the vector-memory counter (a flat
+// load also counts in the LDS counter, so every wait for an LDS read would
+// wait for the loads still in flight as well).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // One BM x BN tile of a sub-box for LS_F16X3: the left operand
 // a.coef[r] f0[r][i] f1[r][j] is rounded to FP32 and split into two FP16
 // terms in the tile (LDS, as split_tile), the right operand comes split from
@@ -431,19 +440,32 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
 // column) and goes from global memory straight into the MFMA B fragments;
 // products x0 y0 + x0 y1 + x1 y0 on the FP16 MFMA, FP32
 // accumulation, out = a.scale * acc. smem holds split_smem_bytes<2, BM, BN, 1>().
-template <int BM, int BN, int WM, int WN, int MF>
-__device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
-                                         float* __restrict__ out, char* smem,
-                                         const uint4* __restrict__ yp) {
+// The tile's rows lie in the values i0 .. ilast of i. With at most kTileNI of
+// them (FAST: with BM = 128, every tile of a box with 43 or more values of
+// j), the factor coef_r f0[r][i] of each of them and each rank of a chunk is
+// formed once in LDS (alphaS[.][i - i0][r]) and a row reads its own, so
+// staging loads only f1, without conditions, and those loads stay in flight
+// through the chunk's MFMAs; otherwise (narrow boxes) each element also loads
+// its f0 value. The two cases are separate loops, so that the waits the
+// compiler places in the first do not follow the second's.
+constexpr int kTileNI = 4;
+
+template <int BM, int BN, int WM, int WN, int MF, bool FAST>
+__device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0,
+                                             float* __restrict__ out, char* smem,
+                                             const uint4* __restrict__ yp) {
   constexpr int NT = 2, BK = SPLIT_BK;
   constexpr int KW = BK * BM / 256;
   static_assert(BM >= 64 && 256 % BM == 0, "staging map");
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   constexpr int FM = WM / MF, FN = WN / MF, NH = MF == 16 ? 1 : 2;
   typedef SplitMma<MF> Mma;
+  constexpr int NI = kTileNI, AST = BK + 1;  // alphaS row stride: rows of i in other banks
   typedef unsigned WsT[NT][BM][16];
+  static_assert(sizeof(WsT) + 2 * NI * AST * sizeof(double) <= split_smem_bytes<2, BM, BN, 1>(),
+                "tile LDS");
   WsT& Ws = *reinterpret_cast<WsT*>(smem);
-  double (*alphaS)[BK] = reinterpret_cast<double (*)[BK]>(smem + sizeof(WsT));
+  double (*alphaS)[NI][AST] = reinterpret_cast<double (*)[NI][AST]>(smem + sizeof(WsT));
 
   const int M = a.e0 * a.e1, nch = (a.K + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -451,13 +473,18 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
   const int mw = tid % BM;
   const int kbw = __builtin_amdgcn_readfirstlane(tid / BM) * KW;
   const int i0 = row0 / a.e1;
-  const bool wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
+  const int ilast = (min(row0 + BM, M) - 1) / a.e1;
+  constexpr bool wfast = FAST;
   const int m = row0 + mw;
   const bool mok = m < M;
-  const int mi = mok ? m / a.e1 : 0;
+  const int mi = mok ? m / a.e1 : i0;
   const int mj = mok ? m - mi * a.e1 : 0;
-  const double* __restrict__ a1row = a.A1 + mi;
-  const double* __restrict__ a2row = a.A2 + mj;
+  const int islot = wfast ? mi - i0 : 0;  // this row's factors in alphaS
+  const auto a1row = gmem(a.A1 + mi);
+  const auto a2row = gmem(a.A2 + mj);
+  const auto a1 = gmem(a.A1);
+  const auto cf = gmem(a.coef);
+  const auto ypg = gmem(yp);
   // this lane's B rows (output columns), clamped into the sub-box (columns
   // beyond it are computed from the last one and not stored)
   const int lr = lane & (MF - 1), lg = lane / MF;
@@ -467,29 +494,38 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
 
   double w[KW];
   double cr = 0.0, ca = 1.0;
+  // FAST: f1 values of ranks k0 + kbw + kk, loaded at clamped ranks (rank
+  // factors past K are 0, rows past M are never stored); otherwise f1 f0
   auto load_w = [&](int k0) {
+    if constexpr (FAST) {
+#pragma unroll
+      for (int kk = 0; kk < KW; ++kk) w[kk] = a2row[(size_t)min(k0 + kbw + kk, a.K - 1) * a.len1];
+      return;
+    }
 #pragma unroll
     for (int kk = 0; kk < KW; ++kk) {
       const int r = k0 + kbw + kk;
       double v = 0.0;
-      if (r < a.K && mok) {
-        v = a2row[(size_t)r * a.len1];
-        if (!wfast) v *= a1row[(size_t)r * a.len0];
-      }
+      if (r < a.K && mok) v = a2row[(size_t)r * a.len1] * a1row[(size_t)r * a.len0];
       w[kk] = v;
     }
   };
+  // thread tid < NI BK: rank k0 + tid % BK and value i0 + tid / BK of i.
+  // Loaded at clamped indices without conditions (so that no path through
+  // the chunk loop has fewer loads in flight, which would make the waits for
+  // the right operand wait for them too); aval says whether the factor is
+  // used, else it is written as 0.
+  const int ai = tid / BK, ar = tid % BK;
+  bool aval = false;
   auto load_alpha = [&](int k0) {
-    const int r = k0 + tid;
-    cr = 0.0;
-    ca = 1.0;
-    if (tid < BK && r < a.K) {
-      cr = a.coef[r];
-      if (wfast) ca = a.A1[(size_t)r * a.len0 + i0];
-    }
+    const int r = k0 + ar;
+    aval = ai < NI && r < a.K && (FAST ? i0 + ai <= ilast : ai == 0);
+    const int rc = min(r, a.K - 1);
+    cr = cf[rc];
+    if constexpr (FAST) ca = a1[(size_t)rc * a.len0 + min(i0 + min(ai, NI - 1), ilast)];
   };
   auto put_alpha = [&](int ab) {
-    if (tid < BK) alphaS[ab][tid] = cr * ca;
+    if (ai < NI) alphaS[ab][ai][ar] = aval ? cr * ca : 0.0;
   };
   auto store_w = [&](int ab) {
 #pragma unroll
@@ -499,8 +535,8 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        split_f16((float)(alphaS[ab][kbw + kk] * w[kk]), u0);
-        split_f16((float)(alphaS[ab][kbw + kk + 1] * w[kk + 1]), u1);
+        split_f16((float)(alphaS[ab][islot][kbw + kk] * w[kk]), u0);
+        split_f16((float)(alphaS[ab][islot][kbw + kk + 1] * w[kk + 1]), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -518,7 +554,7 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int h = 0; h < NH; ++h)
-          bv[t][j][h] = yp[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg];
+          bv[t][j][h] = ypg[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg];
   };
 
   typename Mma::acc_t acc[FM][FN];
@@ -574,7 +610,9 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
     store_w(c & 1);
     put_alpha((c + 1) & 1);
     __syncthreads();
-    if (c + 1 < nch) load_w((c + 1) * BK);
+    // FAST: unconditional (clamped ranks past the last chunk), for the same
+    // reason as the rank factors
+    if (FAST || c + 1 < nch) load_w((c + 1) * BK);
     load_alpha((c + 2) * BK);
     products(bv);
   }
@@ -590,6 +628,18 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
         const int col = col0 + wc + j * MF + Mma::dcol(lane);
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
       }
+}
+
+template <int BM, int BN, int WM, int WN, int MF>
+__device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
+                                         float* __restrict__ out, char* smem,
+                                         const uint4* __restrict__ yp) {
+  const int M = a.e0 * a.e1;
+  const int i0 = row0 / a.e1, ilast = (min(row0 + BM, M) - 1) / a.e1;
+  if (ilast - i0 < kTileNI)
+    f16_tile_run<BM, BN, WM, WN, MF, true>(a, row0, col0, out, smem, yp);
+  else
+    f16_tile_run<BM, BN, WM, WN, MF, false>(a, row0, col0, out, smem, yp);
 }
 
 // NT = 0: FP64 / FP32 tiles (recon_tile<T>); NT = 2, 3: split tiles with NT
