@@ -484,7 +484,8 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   const auto a2row = gmem(a.A2 + mj);
   const auto a1 = gmem(a.A1);
   const auto cf = gmem(a.coef);
-  const auto ypg = gmem(yp);
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  const auto ypg = gmem(reinterpret_cast<const u32x4*>(yp));
   // this lane's B rows (output columns), clamped into the sub-box (columns
   // beyond it are computed from the last one and not stored)
   const int lr = lane & (MF - 1), lg = lane / MF;
@@ -554,7 +555,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int h = 0; h < NH; ++h)
-          bv[t][j][h] = ypg[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg];
+          bv[t][j][h] = __builtin_bit_cast(uint4, ypg[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg]);
   };
 
   typename Mma::acc_t acc[FM][FN];
@@ -596,16 +597,18 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
             }
     }
   };
-  // per chunk c: the right operand's fragments are requested first, so that
-  // staging the left operand (and the barriers) covers their latency
-  BFrag bv;
+  // The right operand's fragments of chunk c + 1 are requested before the
+  // products of chunk c (two register sets, the loop unrolled by two), so
+  // that a whole chunk covers their latency; at the last chunk the request
+  // repeats it (every path through the loop has the same loads in flight).
+  BFrag bv0, bv1;
   load_alpha(0);
   put_alpha(0);
   load_alpha(BK);
   load_w(0);
+  load_b(0, bv0);
   __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    load_b(c, bv);
+  auto step = [&](int c, const BFrag& cur, BFrag& nxt) {
     if (c > 0) __syncthreads();  // Ws of chunk c - 1 consumed
     store_w(c & 1);
     put_alpha((c + 1) & 1);
@@ -614,7 +617,15 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
     // reason as the rank factors
     if (FAST || c + 1 < nch) load_w((c + 1) * BK);
     load_alpha((c + 2) * BK);
-    products(bv);
+    load_b(min(c + 1, nch - 1), nxt);
+    // keep these loads ahead of the MFMAs (the scheduler would otherwise sink
+    // them below, and the next chunk would wait for them)
+    __builtin_amdgcn_sched_barrier(0);
+    products(cur);
+  };
+  for (int c = 0; c < nch; c += 2) {
+    step(c, bv0, bv1);
+    if (c + 1 < nch) step(c + 1, bv1, bv0);
   }
 
   const float sc = (float)a.scale;
