@@ -439,7 +439,9 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const
 // the VEC tasks (yp: per term and 32-rank chunk, 32 FP16 ranks of each
 // column) and goes from global memory straight into the MFMA B fragments;
 // products x0 y0 + x0 y1 + x1 y0 on the FP16 MFMA, FP32
-// accumulation, out = a.scale * acc. smem holds split_smem_bytes<2, BM, BN, 1>().
+// accumulation, out = a.scale * acc. smem holds f16_smem_bytes<BM>(): the
+// split left operand in two buffers (chunk c in buffer c & 1), so one barrier
+// per chunk suffices.
 // The tile's rows lie in the values i0 .. ilast of i. With at most kTileNI of
 // them (FAST: with BM = 128, every tile of a box with 43 or more values of
 // j), the factor coef_r f0[r][i] of each of them and each rank of a chunk is
@@ -449,6 +451,11 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const
 // its f0 value. The two cases are separate loops, so that the waits the
 // compiler places in the first do not follow the second's.
 constexpr int kTileNI = 4;
+
+template <int BM>
+constexpr int f16_smem_bytes() {
+  return 2 * 2 * BM * 16 * 4 + 2 * kTileNI * (SPLIT_BK + 1) * 8;
+}
 
 template <int BM, int BN, int WM, int WN, int MF, bool FAST>
 __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0,
@@ -462,10 +469,10 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   typedef SplitMma<MF> Mma;
   constexpr int NI = kTileNI, AST = BK + 1;  // alphaS row stride: rows of i in other banks
   typedef unsigned WsT[NT][BM][16];
-  static_assert(sizeof(WsT) + 2 * NI * AST * sizeof(double) <= split_smem_bytes<2, BM, BN, 1>(),
+  static_assert(2 * sizeof(WsT) + 2 * NI * AST * sizeof(double) <= f16_smem_bytes<BM>(),
                 "tile LDS");
-  WsT& Ws = *reinterpret_cast<WsT*>(smem);
-  double (*alphaS)[NI][AST] = reinterpret_cast<double (*)[NI][AST]>(smem + sizeof(WsT));
+  WsT* Wsb = reinterpret_cast<WsT*>(smem);
+  double (*alphaS)[NI][AST] = reinterpret_cast<double (*)[NI][AST]>(smem + 2 * sizeof(WsT));
 
   const int M = a.e0 * a.e1, nch = (a.K + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -544,7 +551,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
       const int slot = ((kbw >> 3) + g) ^ lds_swz(mw);
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        *reinterpret_cast<uint4*>(&Ws[t][mw][slot * 4]) = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
+        *reinterpret_cast<uint4*>(&Wsb[ab][t][mw][slot * 4]) = make_uint4(pk[t][0], pk[t][1], pk[t][2], pk[t][3]);
     }
   };
   typedef uint4 BFrag[NT][FN][NH];
@@ -566,7 +573,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
 #pragma unroll
       for (int v = 0; v < Mma::NV; ++v) acc[i][j][v] = 0.0f;
 
-  auto products = [&](const BFrag& bv) {
+  auto products = [&](const BFrag& bv, int ab) {
     int slot[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) slot[h] = ((NH * h + lg) ^ lds_swz(lr)) * 4;
@@ -577,7 +584,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int h = 0; h < NH; ++h)
-          av[i][h] = *reinterpret_cast<const s8_t*>(&Ws[ta][wr + MF * i + lr][slot[h]]);
+          av[i][h] = *reinterpret_cast<const s8_t*>(&Wsb[ab][ta][wr + MF * i + lr][slot[h]]);
 #pragma unroll
       for (int tb = NT - 1 - ta; tb >= 0; --tb)
 #pragma unroll
@@ -608,8 +615,11 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   load_w(0);
   load_b(0, bv0);
   __syncthreads();
+  // chunk c: its left operand goes to buffer c & 1, which the products of
+  // chunk c - 2 read before the previous barrier; its rank factors were
+  // written to alphaS[c & 1] before that barrier, and alphaS[(c + 1) & 1] was
+  // last read by the staging of chunk c - 1, also before it
   auto step = [&](int c, const BFrag& cur, BFrag& nxt) {
-    if (c > 0) __syncthreads();  // Ws of chunk c - 1 consumed
     store_w(c & 1);
     put_alpha((c + 1) & 1);
     __syncthreads();
@@ -621,7 +631,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
     // keep these loads ahead of the MFMAs (the scheduler would otherwise sink
     // them below, and the next chunk would wait for them)
     __builtin_amdgcn_sched_barrier(0);
-    products(cur);
+    products(cur, c & 1);
   };
   for (int c = 0; c < nch; c += 2) {
     step(c, bv0, bv1);
@@ -658,7 +668,8 @@ __device__ __forceinline__ void f16_tile(const BoxArg& a, int row0, int col0,
 // LS_F16X3, scaled FP16 terms (FMT = 1).
 template <typename T, int BM, int BN, int WM, int WN, int BK, int NT = 0, int MF = 16, int FMT = 0>
 __global__ __launch_bounds__(256, 2) void k_batch(BatchArg ba) {
-  constexpr int RB = NT ? split_smem_bytes<NT, BM, BN, 1>() : recon_smem_bytes<T, BM, BN, BK>();
+  constexpr int RB = FMT == 1 ? f16_smem_bytes<BM>()
+                   : NT ? split_smem_bytes<NT, BM, BN, 1>() : recon_smem_bytes<T, BM, BN, BK>();
   constexpr int VB = kVecSmem;
   __shared__ __attribute__((aligned(16))) char smem[RB > VB ? RB : VB];
   __shared__ int s_task, s_flag;
