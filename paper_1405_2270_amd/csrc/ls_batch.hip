@@ -491,8 +491,23 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   const auto a2row = gmem(a.A2 + mj);
   const auto a1 = gmem(a.A1);
   const auto cf = gmem(a.coef);
-  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-  const auto ypg = gmem(reinterpret_cast<const u32x4*>(yp));
+  // f1 (FAST) and the split right operand through buffer resources: a
+  // uniform (scalar) byte offset per rank row or chunk and a fixed 32-bit
+  // offset per lane, so no per-lane 64-bit address arithmetic; f1 rows past
+  // K read as 0
+  // (the base addresses and sizes are uniform: taken through readfirstlane so
+  // that the compiler keeps the resources in scalar registers)
+  auto urs = [](const void* p, int bytes) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo), (short)0,
+        __builtin_amdgcn_readfirstlane(bytes), kBufferFlags);
+  };
+  const __amdgpu_buffer_rsrc_t a2buf = urs(a.A2, a.K * a.len1 * 8);
+  const __amdgpu_buffer_rsrc_t ybuf = urs(yp, NT * nch * a.e2 * 64);
+  const int woff = mj * 8;
   // this lane's B rows (output columns), clamped into the sub-box (columns
   // beyond it are computed from the last one and not stored)
   const int lr = lane & (MF - 1), lg = lane / MF;
@@ -502,12 +517,16 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
 
   double w[KW];
   double cr = 0.0, ca = 1.0;
-  // FAST: f1 values of ranks k0 + kbw + kk, loaded at clamped ranks (rank
-  // factors past K are 0, rows past M are never stored); otherwise f1 f0
+  // FAST: f1 values of ranks k0 + kbw + kk, without conditions (ranks past
+  // K read as 0, rows past M are never stored); otherwise f1 f0
   auto load_w = [&](int k0) {
     if constexpr (FAST) {
+      const int rs = __builtin_amdgcn_readfirstlane(a.len1 * 8);  // bytes per rank row
+      const int s0 = __builtin_amdgcn_readfirstlane((k0 + kbw) * a.len1 * 8);
 #pragma unroll
-      for (int kk = 0; kk < KW; ++kk) w[kk] = a2row[(size_t)min(k0 + kbw + kk, a.K - 1) * a.len1];
+      for (int kk = 0; kk < KW; ++kk)
+        w[kk] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(a2buf, woff, s0 + kk * rs, 0));
       return;
     }
 #pragma unroll
@@ -557,12 +576,15 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   typedef uint4 BFrag[NT][FN][NH];
   auto load_b = [&](int c, BFrag& bv) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t) {
+      const int soff = __builtin_amdgcn_readfirstlane((t * nch + c) * a.e2 * 64);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
         for (int h = 0; h < NH; ++h)
-          bv[t][j][h] = __builtin_bit_cast(uint4, ypg[(((size_t)t * nch + c) * a.e2 + brow[j]) * 4 + NH * h + lg]);
+          bv[t][j][h] = __builtin_bit_cast(
+              uint4, __builtin_amdgcn_raw_buffer_load_b128(ybuf, (brow[j] * 4 + NH * h + lg) * 16, soff, 0));
+    }
   };
 
   typename Mma::acc_t acc[FM][FN];

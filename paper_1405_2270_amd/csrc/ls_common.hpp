@@ -18,6 +18,9 @@ namespace ls {
 // Largest quadrature rank handled; the node table travels as a kernel
 // argument (no device allocation).
 constexpr int kMaxR = 160;
+// word 3 of a raw buffer resource on gfx9-family chips (32-bit data format);
+// loads past the resource's byte count return 0
+constexpr int kBufferFlags = 0x00020000;
 // Largest density rank in the Gram kernels (per-lane accumulators).
 constexpr int kMaxRho = 16;
 

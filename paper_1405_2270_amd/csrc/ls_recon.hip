@@ -88,8 +88,6 @@ __global__ __launch_bounds__(256) void k_recon32(BoxSet bs, float* __restrict__ 
 // ---------------------------------------------------------------------------
 // split-bf16 kernels (helpers and the in-kernel split tile: ls_split_tile.hpp)
 // ---------------------------------------------------------------------------
-// word 3 of a raw buffer resource on gfx9-family chips (32-bit data format)
-constexpr int kBufferFlags = 0x00020000;
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
 template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
