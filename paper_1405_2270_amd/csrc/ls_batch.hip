@@ -142,6 +142,28 @@ __device__ int signal_counter(int* counter) {
   return prev;
 }
 
+// A pointer into device memory as a global-address-space pointer: its loads
+// become global loads, which count only in the vector-memory counter (a flat
+// load also counts in the LDS counter, so every wait for an LDS read would
+// wait for the loads still in flight as well).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// A raw buffer resource over `bytes` bytes at p, both uniform across the
+// workgroup (taken through readfirstlane, so that the compiler keeps the
+// resource in scalar registers): loads take a 32-bit lane offset and read 0
+// past the end.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo),
+                                           (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           kBufferFlags);
+}
+
 // Phi_l[s][i + X] = sum_{k=0}^{L-1} D_l[s][i + k n], i in [-X, X + n), D = 0 outside [0, N).
 // For i = rho + c n: c >= 0 -> suffix sum of the residue column from c, c < 0 ->
 // prefix sum up to c + L - 1.
@@ -233,7 +255,13 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
   int p;
   double delta;
   node_offset(S.pos[c], S.b, S.h, n, &p, &delta);
-  const double* ph = S.Phi + (size_t)l * Krho * W + p + X;  // ph[s*W + j] = Phi_l[s][j + p]
+  // the folded density of axis l, Krho rows of W, through a buffer resource:
+  // Phi_l[s][j + p] at byte offset (s W + j + p + X) 8; the Gram loads need no
+  // conditions (rows s >= Krho and offsets past the block read 0, and cells past
+  // the group's support have value 0)
+  const __amdgpu_buffer_rsrc_t phbuf = uniform_rsrc(S.Phi + (size_t)l * Krho * W, Krho * W * 8);
+  const int qoff = S.qoff;
+  const double hcell = S.h;
   // master cells that land on the sub-box: g = j + p + k n in [o, o+e), k in [0, L)
   const int jlo = o - p - (L - 1) * n, jhi = o + e - 1 - p;
   double* bq = sbuf;                          // [kVecQ][kVecRow] cell values
@@ -253,7 +281,7 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
     // support of the group: the union of the points' supports
     int jbeg = X, jend = -X;
     for (int g = 0; g < ng; ++g) {
-      const double hw = ba.qhw[S.qoff + q0 + g];
+      const double hw = ba.qhw[qoff + q0 + g];
       jbeg = min(jbeg, (int)fmax((double)-X, floor(delta - hw)));
       jend = max(jend, (int)fmin((double)X, ceil(delta + hw) + 1.0));
     }
@@ -265,17 +293,15 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
     for (int j0 = jbeg; j0 < jend; j0 += CH) {
       const int j = j0 + ci;
       const bool cell_ok = lane < 63 && j < jend;
-      vec_chunk_cells(ba, S.qoff + q0, ng, j, delta, S.h, cell_ok, lane < 63 ? bq + ci : nullptr);
+      vec_chunk_cells(ba, qoff + q0, ng, j, delta, hcell, cell_ok, lane < 63 ? bq + ci : nullptr);
       // Gram: wave wv takes cells 64 wv .. 64 wv + 63 of the chunk, 4 per
       // MFMA; the density values are requested before the barrier, whose
       // wait for the other waves' cells covers their latency
       double bvv[16];
+      const int pb = (gq * W + p + X + j0 + 64 * wv + ck) * 8;
 #pragma unroll
-      for (int k4 = 0; k4 < 16; ++k4) {
-        const int i = 64 * wv + 4 * k4 + ck;
-        const int jj = j0 + i;
-        bvv[k4] = (gq < Krho && i < CH && jj < jend) ? ph[(size_t)gq * W + jj] : 0.0;
-      }
+      for (int k4 = 0; k4 < 16; ++k4)
+        bvv[k4] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(phbuf, pb + 32 * k4, 0, 0));
       __syncthreads();
 #pragma unroll
       for (int k4 = 0; k4 < 16; ++k4) {
@@ -424,15 +450,6 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
   if (tid == 0) S.fsc[K] = ldexp(1.0, T - 24);
 }
 
-// A pointer into device memory as a global-address-space pointer: its loads
-// become global loads, which count only in the vector-memory counter (a flat
-// load also counts in the LDS counter, so every wait for an LDS read would
-// wait for the loads still in flight as well).
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
-  return (const __attribute__((address_space(1))) T*)p;
-}
-
 // One BM x BN tile of a sub-box for LS_F16X3: the left operand
 // a.coef[r] f0[r][i] f1[r][j] is rounded to FP32 and split into two FP16
 // terms in the tile (LDS, as split_tile), the right operand comes split from
@@ -495,18 +512,8 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   // uniform (scalar) byte offset per rank row or chunk and a fixed 32-bit
   // offset per lane, so no per-lane 64-bit address arithmetic; f1 rows past
   // K read as 0
-  // (the base addresses and sizes are uniform: taken through readfirstlane so
-  // that the compiler keeps the resources in scalar registers)
-  auto urs = [](const void* p, int bytes) {
-    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return __builtin_amdgcn_make_buffer_rsrc(
-        reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo), (short)0,
-        __builtin_amdgcn_readfirstlane(bytes), kBufferFlags);
-  };
-  const __amdgpu_buffer_rsrc_t a2buf = urs(a.A2, a.K * a.len1 * 8);
-  const __amdgpu_buffer_rsrc_t ybuf = urs(yp, NT * nch * a.e2 * 64);
+  const __amdgpu_buffer_rsrc_t a2buf = uniform_rsrc(a.A2, a.K * a.len1 * 8);
+  const __amdgpu_buffer_rsrc_t ybuf = uniform_rsrc(yp, NT * nch * a.e2 * 64);
   const int woff = mj * 8;
   // this lane's B rows (output columns), clamped into the sub-box (columns
   // beyond it are computed from the last one and not stored)
