@@ -207,9 +207,11 @@ __device__ __attribute__((noinline)) void vec_chunk_cells(const BatchArg& ba, in
                                                           int j, double delta, double h,
                                                           bool cell_ok, double* col) {
   const double y0 = (double)j - delta;
-  // the node tables' addresses are uniform: read through scalar registers,
-  // their loads become scalar loads
-  typedef const __attribute__((address_space(1))) double* gptr;
+  // the node tables' addresses are uniform and the tables are not written
+  // during the launch: read through the constant address space, their loads
+  // are scalar loads (scalar cache) instead of vector loads that each point
+  // would wait for at the full vector-memory latency
+  typedef const __attribute__((address_space(4))) double* gptr;
   auto uptr = [](const double* p) {
     const unsigned long long v = reinterpret_cast<unsigned long long>(p);
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
