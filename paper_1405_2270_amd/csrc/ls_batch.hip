@@ -151,6 +151,17 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const
   return (const __attribute__((address_space(1))) T*)p;
 }
 
+// A uniform pointer to data that no task writes during the launch, as a
+// constant-address-space pointer (through readfirstlane): its loads become
+// scalar loads (scalar cache), not vector loads waited for at full latency.
+typedef const __attribute__((address_space(4))) double* cdptr;
+__device__ __forceinline__ cdptr cmem(const double* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (cdptr)(((unsigned long long)hi << 32) | lo);
+}
+
 // A raw buffer resource over `bytes` bytes at p, both uniform across the
 // workgroup (taken through readfirstlane, so that the compiler keeps the
 // resource in scalar registers): loads take a 32-bit lane offset and read 0
@@ -207,20 +218,10 @@ __device__ __attribute__((noinline)) void vec_chunk_cells(const BatchArg& ba, in
                                                           int j, double delta, double h,
                                                           bool cell_ok, double* col) {
   const double y0 = (double)j - delta;
-  // the node tables' addresses are uniform and the tables are not written
-  // during the launch: read through the constant address space, their loads
-  // are scalar loads (scalar cache) instead of vector loads that each point
-  // would wait for at the full vector-memory latency
-  typedef const __attribute__((address_space(4))) double* gptr;
-  auto uptr = [](const double* p) {
-    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-    return (gptr)(((unsigned long long)hi << 32) | lo);
-  };
-  const gptr ttau = uptr(ba.tau + q0);
-  const gptr thw = uptr(ba.qhw + q0);
-  const gptr tk = uptr(ba.qk + q0);
+  // the node tables through the constant address space (scalar loads)
+  const cdptr ttau = cmem(ba.tau + q0);
+  const cdptr thw = cmem(ba.qhw + q0);
+  const cdptr tk = cmem(ba.qk + q0);
   ng = __builtin_amdgcn_readfirstlane(ng);
 #pragma unroll 1
   for (int g = 0; g < kVecQ; ++g) {
@@ -281,9 +282,13 @@ __device__ void vec_task(const SysDev& S, const BatchArg& ba, int c, double* sbu
   for (int q0 = 0; q0 < S.R; q0 += kVecQ) {
     const int ng = min(kVecQ, S.R - q0);
     // support of the group: the union of the points' supports
+    // (half-widths by scalar loads, all requested together; the indices past
+    // the group repeat its last point, which leaves the union unchanged)
     int jbeg = X, jend = -X;
-    for (int g = 0; g < ng; ++g) {
-      const double hw = ba.qhw[qoff + q0 + g];
+    const cdptr ghw = cmem(ba.qhw + qoff + q0);
+#pragma unroll
+    for (int g = 0; g < kVecQ; ++g) {
+      const double hw = ghw[min(g, ng - 1)];
       jbeg = min(jbeg, (int)fmax((double)-X, floor(delta - hw)));
       jend = max(jend, (int)fmin((double)X, ceil(delta + hw) + 1.0));
     }
