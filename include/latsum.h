@@ -242,7 +242,8 @@ ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad,
  * every other precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
  * LS_EUNSUPPORTED (tile id not valid for the precision; LS_F16X3 with over
- * 2^31 tiles in a group of boxes or an operand of 2 GB or more), LS_EWORKSPACE
+ * 2^31 tiles in a group of boxes or an operand of 2 GB or more; tiles 1..5 of
+ * a bf16 split precision with f1 or f2 of 2 GB or more), LS_EWORKSPACE
  * (tile 6 or above of a bf16 split precision, or LS_F16X3, with a missing or
  * short workspace).
  */

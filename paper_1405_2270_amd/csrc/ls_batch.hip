@@ -162,19 +162,6 @@ __device__ __forceinline__ cdptr cmem(const double* p) {
   return (cdptr)(((unsigned long long)hi << 32) | lo);
 }
 
-// A raw buffer resource over `bytes` bytes at p, both uniform across the
-// workgroup (taken through readfirstlane, so that the compiler keeps the
-// resource in scalar registers): loads take a 32-bit lane offset and read 0
-// past the end.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
-  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo),
-                                           (short)0, __builtin_amdgcn_readfirstlane(bytes),
-                                           kBufferFlags);
-}
-
 // Phi_l[s][i + X] = sum_{k=0}^{L-1} D_l[s][i + k n], i in [-X, X + n), D = 0 outside [0, N).
 // For i = rho + c n: c >= 0 -> suffix sum of the residue column from c, c < 0 ->
 // prefix sum up to c + L - 1.
@@ -474,7 +461,6 @@ __device__ void f16_scales(const SysDev& S, int* ibuf) {
 // through the chunk's MFMAs; otherwise (narrow boxes) each element also loads
 // its f0 value. The two cases are separate loops, so that the waits the
 // compiler places in the first do not follow the second's.
-constexpr int kTileNI = 4;
 
 template <int BM>
 constexpr int f16_smem_bytes() {

@@ -187,6 +187,19 @@ __device__ __forceinline__ double cell_from_edges(double tau, double y0, double 
   return cell_from_edges(tau, y0, eL, eR, cell_half_norm(tau));
 }
 
+// A raw buffer resource over `bytes` bytes at p, both uniform across the
+// workgroup (taken through readfirstlane, so that the compiler keeps the
+// resource in scalar registers): loads take a 32-bit lane offset and read 0
+// past the end.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const void* p, int bytes) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo),
+                                           (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           kBufferFlags);
+}
+
 // sinh(x) for |x| <= 1/4 (Taylor series to x^11: truncation below 1e-17 relative)
 __device__ __forceinline__ double sinh_small(double x) {
   const double x2 = x * x;

@@ -1227,9 +1227,14 @@ static bool launch_fp(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) 
 template <int NT>
 static bool launch_bf(int tile, hipStream_t s, BoxSet& bs, void* out, bool dry) {
   dim3 block(256);
+  // the in-kernel split tiles address f1 and f2 with 32-bit buffer offsets
+  auto split_fits = [&]() {
+    return (long long)bs.box[0].K * std::max(bs.box[0].len1, bs.box[0].len2) * 8 < (1LL << 31);
+  };
 #define LS_T(ID, BM_, BN_, WM_, WN_, NB_, MF_)                                                \
   if (tile == ID) {                                                                          \
     if (!dry) {                                                                              \
+      if (!split_fits()) return false;                                                       \
       fill_tiles(&bs, BM_, BN_);                                                             \
       dim3 grid((unsigned)(8 * bs.per_xcd));                                                 \
       hipLaunchKernelGGL((k_recon_split<NT, BM_, BN_, WM_, WN_, NB_, MF_>), grid, block, 0, s, \

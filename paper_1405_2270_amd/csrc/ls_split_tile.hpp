@@ -169,18 +169,26 @@ __device__ __forceinline__ void split_products(typename SplitMma<MF>::acc_t (&ac
   }
 }
 
+// A tile's rows (i, j) lie in the values i0 .. ilast of i. With at most
+// kTileNI of them (FAST; with 128-row tiles, every tile of a box with 43 or
+// more values of j) the rank factors coef_r f0[r][i] of each of them are
+// formed once per rank chunk in LDS and each row reads its own, so staging
+// loads only f1, without conditions; otherwise (narrow boxes) each element
+// also loads its f0 value, in a loop of its own.
+constexpr int kTileNI = 4;
+
 template <int NT, int BM, int BN, int NBUF>
 constexpr int split_smem_bytes() {
-  return NBUF * NT * (BM + BN) * 16 * 4 + 2 * SPLIT_BK * 8;
+  return NBUF * NT * (BM + BN) * 16 * 4 + 2 * kTileNI * (SPLIT_BK + 1) * 8;
 }
 
 // One BM x BN tile (rows row0.., columns col0..) of the box GEMM with both
 // operands split in the kernel; out is the box's output, smem holds
 // split_smem_bytes<NT, BM, BN, NBUF>() bytes (16-byte aligned). All 256
 // threads of the workgroup call it; it ends with the tile stored.
-template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
-__device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
-                                           float* __restrict__ out, char* smem) {
+template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF, bool FAST>
+__device__ __forceinline__ void split_tile_run(const BoxArg& a, int row0, int col0,
+                                               float* __restrict__ out, char* smem) {
   constexpr int BK = SPLIT_BK;
   constexpr int KW = BK * BM / 256, KY = BK * BN / 256;
   static_assert(BM >= 64 && BN >= 64 && 256 % BM == 0 && 256 % BN == 0, "staging map");
@@ -191,7 +199,9 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
   typedef unsigned YsT[NT][BN][16];
   WsT* Ws = reinterpret_cast<WsT*>(smem);
   YsT* Ys = reinterpret_cast<YsT*>(smem + NBUF * sizeof(WsT));
-  double (*alphaS)[BK] = reinterpret_cast<double (*)[BK]>(smem + NBUF * (sizeof(WsT) + sizeof(YsT)));
+  constexpr int NI = kTileNI, AST = BK + 1;  // alphaS row stride: rows of i in other banks
+  double (*alphaS)[NI][AST] =
+      reinterpret_cast<double (*)[NI][AST]>(smem + NBUF * (sizeof(WsT) + sizeof(YsT)));
 
   const int M = a.e0 * a.e1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -202,48 +212,64 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
   const int kbw = __builtin_amdgcn_readfirstlane(tid / BM) * KW;
   const int kby = __builtin_amdgcn_readfirstlane(tid / BN) * KY;
   const int i0 = row0 / a.e1;
-  const bool wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
+  const int ilast = (min(row0 + BM, M) - 1) / a.e1;
   const int m = row0 + mw;
   const bool mok = m < M;
-  const int mi = mok ? m / a.e1 : 0;
+  const int mi = mok ? m / a.e1 : i0;
   const int mj = mok ? m - mi * a.e1 : 0;
-  const bool nok = col0 + ny < a.e2;
+  const int islot = FAST ? mi - i0 : 0;  // this row's factors in alphaS
   const double* __restrict__ a1row = a.A1 + a.o0 + mi;
   const double* __restrict__ a2row = a.A2 + a.o1 + mj;
-  const double* __restrict__ a3row = a.A3 + a.o2 + col0 + ny;
   const int nchunk = (a.K + BK - 1) / BK;
+  // f1 (FAST) and f2 through buffer resources: a uniform (scalar) byte offset
+  // per rank row and a fixed 32-bit lane offset; rows past K read 0. Columns
+  // past the box read its last column (computed, never stored).
+  const __amdgpu_buffer_rsrc_t a2buf = uniform_rsrc(a.A2, a.K * a.len1 * 8);
+  const __amdgpu_buffer_rsrc_t a3buf = uniform_rsrc(a.A3, a.K * a.len2 * 8);
+  const int woff = (a.o1 + mj) * 8;
+  const int yoff = (a.o2 + min(col0 + ny, a.e2 - 1)) * 8;
+  const int rs1 = __builtin_amdgcn_readfirstlane(a.len1 * 8);  // bytes per rank row
+  const int rs2 = __builtin_amdgcn_readfirstlane(a.len2 * 8);
 
   double w[KW], y[KY];
-  double cr = 0.0, ca = 1.0;  // raw parts of one alpha_r (threads tid < BK)
+  double cr = 0.0, ca = 1.0;  // raw parts of one alpha_r (threads tid < NI BK)
 
   auto load_ops = [&](int k0) {
+    if constexpr (FAST) {
+      const int s0 = __builtin_amdgcn_readfirstlane((k0 + kbw) * a.len1 * 8);
 #pragma unroll
-    for (int kk = 0; kk < KW; ++kk) {
-      const int r = k0 + kbw + kk;
-      double v = 0.0;
-      if (r < a.K && mok) {
-        v = a2row[(size_t)r * a.len1];
-        if (!wfast) v *= a1row[(size_t)r * a.len0];
+      for (int kk = 0; kk < KW; ++kk)
+        w[kk] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(a2buf, woff, s0 + kk * rs1, 0));
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KW; ++kk) {
+        const int r = k0 + kbw + kk;
+        double v = 0.0;
+        if (r < a.K && mok) v = a2row[(size_t)r * a.len1] * a1row[(size_t)r * a.len0];
+        w[kk] = v;
       }
-      w[kk] = v;
     }
+    const int s0 = __builtin_amdgcn_readfirstlane((k0 + kby) * a.len2 * 8);
 #pragma unroll
-    for (int kk = 0; kk < KY; ++kk) {
-      const int r = k0 + kby + kk;
-      y[kk] = (r < a.K && nok) ? a3row[(size_t)r * a.len2] : 0.0;
-    }
+    for (int kk = 0; kk < KY; ++kk)
+      y[kk] = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(a3buf, yoff, s0 + kk * rs2, 0));
   };
+  // thread tid < NI BK: rank k0 + tid % BK and value i0 + tid / BK of i,
+  // loaded at clamped indices without conditions; aval says whether the
+  // factor is used (else it is written as 0)
+  const int ai = tid / BK, ar = tid % BK;
+  bool aval = false;
   auto load_alpha = [&](int k0) {
-    const int r = k0 + tid;
-    cr = 0.0;
-    ca = 1.0;
-    if (tid < BK && r < a.K) {
-      cr = a.coef[r];
-      if (wfast) ca = a.A1[(size_t)r * a.len0 + a.o0 + i0];
-    }
+    const int r = k0 + ar;
+    aval = ai < NI && r < a.K && (FAST ? i0 + ai <= ilast : ai == 0);
+    const int rc = min(r, a.K - 1);
+    cr = a.coef[rc];
+    if constexpr (FAST) ca = a.A1[(size_t)rc * a.len0 + a.o0 + min(i0 + min(ai, NI - 1), ilast)];
   };
   auto put_alpha = [&](int ab) {
-    if (tid < BK) alphaS[ab][tid] = cr * ca;
+    if (ai < NI) alphaS[ab][ai][ar] = aval ? cr * ca : 0.0;
   };
   auto store = [&](int sb, int ab) {
 #pragma unroll
@@ -253,8 +279,8 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
       for (int q = 0; q < 4; ++q) {
         const int kk = g * 8 + 2 * q;
         unsigned u0[NT], u1[NT];
-        split_fp32<NT>((float)(alphaS[ab][kbw + kk] * w[kk]), u0);
-        split_fp32<NT>((float)(alphaS[ab][kbw + kk + 1] * w[kk + 1]), u1);
+        split_fp32<NT>((float)(alphaS[ab][islot][kbw + kk] * w[kk]), u0);
+        split_fp32<NT>((float)(alphaS[ab][islot][kbw + kk + 1] * w[kk + 1]), u1);
 #pragma unroll
         for (int t = 0; t < NT; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
       }
@@ -304,7 +330,7 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
     store(sb, c & 1);
     put_alpha((c + 1) & 1);
     __syncthreads();
-    if (c + 1 < nchunk) load_ops((c + 1) * BK);
+    if (FAST || c + 1 < nchunk) load_ops((c + 1) * BK);
     load_alpha((c + 2) * BK);
     split_products<NT, MF, FM, FN>(acc, &Ws[sb][0][0][0], BM * 16, &Ys[sb][0][0][0], BN * 16, wr,
                                    wc, lane);
@@ -321,6 +347,17 @@ __device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
         const int col = col0 + wc + j * MF + Mma::dcol(lane);
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
       }
+}
+
+template <int NT, int BM, int BN, int WM, int WN, int NBUF, int MF>
+__device__ __forceinline__ void split_tile(const BoxArg& a, int row0, int col0,
+                                           float* __restrict__ out, char* smem) {
+  const int M = a.e0 * a.e1;
+  const int i0 = row0 / a.e1, ilast = (min(row0 + BM, M) - 1) / a.e1;
+  if (ilast - i0 < kTileNI)
+    split_tile_run<NT, BM, BN, WM, WN, NBUF, MF, true>(a, row0, col0, out, smem);
+  else
+    split_tile_run<NT, BM, BN, WM, WN, NBUF, MF, false>(a, row0, col0, out, smem);
 }
 
 }  // namespace ls
