@@ -67,15 +67,18 @@ __device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
 // staged per step; lane t of the workgroup owns rank row kk = t / TPR and
 // rows m = q + TPR*e (q = t % TPR, e = 0..EPT-1) of the W operand, so every
 // load instruction of a 16-lane group reads 16 consecutive doubles.
-// Fast path (uniform per workgroup): the BM rows of the tile share one i,
-// so W[r][m] = alpha_r * f1[r][o1 + j0 + m - row0] with alpha_r = coef[r] f0[r][o0 + i]
-// (two scalar loads per rank row); otherwise every element does its own
-// index arithmetic.
+// ONEI (the BM rows of the tile share one i, uniform per workgroup):
+// W[r][m] = alpha_r * f1[r][o1 + j0 + m - row0] with alpha_r = coef[r] f0[r][o0 + i]
+// (two loads per rank row); otherwise every element loads its own f0 and f1
+// values, at clamped ranks and rows without conditions (rank rows past K give
+// 0 through w_value, rows past the box are never stored). The two cases are
+// separate instantiations, so that the waits the compiler places for one do
+// not follow the other's loads.
 // load() only issues loads: the products are formed by w_value() when the
 // chunk is written to LDS one step later, so the loads of chunk c+1 stay in
 // flight while the MFMAs consume chunk c (a use right after the load would
 // make the wave wait for memory there).
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool ONEI>
 struct Stager {
   static constexpr int EPT_W = BK * BM / 256;
   static constexpr int TPR_W = BM / EPT_W;
@@ -85,9 +88,11 @@ struct Stager {
 
   int wk, wq, yk, yq;
   int row0, col0, M, i0, j0;
-  bool wfast, yfast;
-  double cr, a1;  // fast path: alpha = cr * a1 (1, 1 on the other paths)
+  bool yfast;
+  bool rv;        // !ONEI: the rank row of this chunk is below K
+  double cr, a1;  // ONEI: alpha = cr * a1
   double w[EPT_W];
+  double w0[ONEI ? 1 : EPT_W];  // !ONEI: each row's f0 value
   double y[EPT_Y];
 
   __device__ __forceinline__ void init(const BoxArg& a, int r0, int c0) {
@@ -101,18 +106,23 @@ struct Stager {
     M = a.e0 * a.e1;
     i0 = row0 / a.e1;
     j0 = row0 - i0 * a.e1;
-    wfast = (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
     yfast = col0 + BN <= a.e2;
   }
 
-  __device__ __forceinline__ double w_value(int e) const { return (cr * a1) * w[e]; }
+  // (coef f0) f1 in this order on both paths
+  __device__ __forceinline__ double w_value(int e) const {
+    if constexpr (ONEI)
+      return (cr * a1) * w[e];
+    else
+      return rv ? (cr * w0[e]) * w[e] : 0.0;
+  }
 
   __device__ __forceinline__ void load(const BoxArg& a, int k0) {
     const int r = k0 + wk;
-    cr = 1.0;
-    a1 = 1.0;
-    if (r < a.K) {
-      if (wfast) {
+    if constexpr (ONEI) {
+      cr = 1.0;
+      a1 = 1.0;
+      if (r < a.K) {
         cr = a.coef[r];
         a1 = a.A1[(size_t)r * a.len0 + a.o0 + i0];
         const double* src = a.A2 + (size_t)r * a.len1 + a.o1 + j0 + wq;
@@ -120,19 +130,20 @@ struct Stager {
         for (int e = 0; e < EPT_W; ++e) w[e] = src[e * TPR_W];
       } else {
 #pragma unroll
-        for (int e = 0; e < EPT_W; ++e) {
-          const int m = row0 + wq + e * TPR_W;
-          double v = 0.0;
-          if (m < M) {
-            const int i = m / a.e1, j = m - i * a.e1;
-            v = a.coef[r] * a.A1[(size_t)r * a.len0 + a.o0 + i] * a.A2[(size_t)r * a.len1 + a.o1 + j];
-          }
-          w[e] = v;
-        }
+        for (int e = 0; e < EPT_W; ++e) w[e] = 0.0;
       }
     } else {
+      rv = r < a.K;
+      const int rc = min(r, a.K - 1);
+      cr = a.coef[rc];
 #pragma unroll
-      for (int e = 0; e < EPT_W; ++e) w[e] = 0.0;
+      for (int e = 0; e < EPT_W; ++e) {
+        const int m = row0 + wq + e * TPR_W;
+        const int mc = m < M ? m : row0;  // rows past the box: never stored
+        const int i = mc / a.e1, j = mc - i * a.e1;
+        w[e] = a.A2[(size_t)rc * a.len1 + a.o1 + j];
+        w0[e] = a.A1[(size_t)rc * a.len0 + a.o0 + i];
+      }
     }
     const int ry = k0 + yk;
     if (ry < a.K) {
@@ -151,6 +162,13 @@ struct Stager {
   }
 };
 
+// rows of the tile in one value of i
+template <int BM>
+__device__ __forceinline__ bool tile_one_i(const BoxArg& a, int row0) {
+  const int M = a.e0 * a.e1, i0 = row0 / a.e1;
+  return (row0 + BM <= M) && ((row0 + BM - 1) / a.e1 == i0);
+}
+
 // FP64 / FP32 tile. T = operand type. Two LDS buffers: the global loads of
 // chunk c+1 are in flight while the MFMAs consume chunk c. `smem` holds
 // recon_smem_bytes<T, BM, BN, BK>() bytes.
@@ -159,9 +177,9 @@ constexpr int recon_smem_bytes() {
   return 2 * BK * (BM + BN + 2 * ((sizeof(T) == 8) ? 2 : 16)) * (int)sizeof(T);
 }
 
-template <typename T, int BM, int BN, int WM, int WN, int BK>
-__device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, T* __restrict__ out,
-                                           char* smem) {
+template <typename T, int BM, int BN, int WM, int WN, int BK, bool ONEI>
+__device__ __forceinline__ void recon_tile_run(const BoxArg& a, int row0, int col0,
+                                               T* __restrict__ out, char* smem) {
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   typedef typename Acc<T>::type acc_t;
   constexpr int FM = WM / 16, FN = WN / 16;
@@ -188,18 +206,17 @@ __device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, 
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  Stager<BM, BN, BK> st;
+  typedef Stager<BM, BN, BK, ONEI> St;
+  St st;
   st.init(a, row0, col0);
   st.load(a, 0);
   const int nchunk = (a.K + BK - 1) / BK;
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
 #pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
-      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (T)st.w_value(e);
+    for (int e = 0; e < St::EPT_W; ++e) Ws[buf][st.wk][st.wq + e * St::TPR_W] = (T)st.w_value(e);
 #pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
-      Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (T)st.y[e];
+    for (int e = 0; e < St::EPT_Y; ++e) Ys[buf][st.yk][st.yq + e * St::TPR_Y] = (T)st.y[e];
     __syncthreads();
     if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
 #pragma unroll
@@ -230,6 +247,15 @@ __device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, 
       }
 }
 
+template <typename T, int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ void recon_tile(const BoxArg& a, int row0, int col0, T* __restrict__ out,
+                                           char* smem) {
+  if (tile_one_i<BM>(a, row0))
+    recon_tile_run<T, BM, BN, WM, WN, BK, true>(a, row0, col0, out, smem);
+  else
+    recon_tile_run<T, BM, BN, WM, WN, BK, false>(a, row0, col0, out, smem);
+}
+
 typedef float f16v_t __attribute__((ext_vector_type(16)));
 
 // FP32 tile on v_mfma_f32_32x32x2f32: each wave owns a WM x WN sub-tile of
@@ -242,9 +268,9 @@ constexpr int recon32_smem_bytes() {
   return 2 * BK * (BM + BN + 2 * 32) * (int)sizeof(float);
 }
 
-template <int BM, int BN, int WM, int WN, int BK>
-__device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0,
-                                             float* __restrict__ out, char* smem) {
+template <int BM, int BN, int WM, int WN, int BK, bool ONEI>
+__device__ __forceinline__ void recon_tile32_run(const BoxArg& a, int row0, int col0,
+                                                 float* __restrict__ out, char* smem) {
   static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int PAD = 32;
@@ -270,18 +296,17 @@ __device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-  Stager<BM, BN, BK> st;
+  typedef Stager<BM, BN, BK, ONEI> St;
+  St st;
   st.init(a, row0, col0);
   st.load(a, 0);
   const int nchunk = (a.K + BK - 1) / BK;
   for (int c = 0; c < nchunk; ++c) {
     const int buf = c & 1;
 #pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_W; ++e)
-      Ws[buf][st.wk][st.wq + e * Stager<BM, BN, BK>::TPR_W] = (float)st.w_value(e);
+    for (int e = 0; e < St::EPT_W; ++e) Ws[buf][st.wk][st.wq + e * St::TPR_W] = (float)st.w_value(e);
 #pragma unroll
-    for (int e = 0; e < Stager<BM, BN, BK>::EPT_Y; ++e)
-      Ys[buf][st.yk][st.yq + e * Stager<BM, BN, BK>::TPR_Y] = (float)st.y[e];
+    for (int e = 0; e < St::EPT_Y; ++e) Ys[buf][st.yk][st.yq + e * St::TPR_Y] = (float)st.y[e];
     __syncthreads();
     if (c + 1 < nchunk) st.load(a, (c + 1) * BK);
 #pragma unroll
@@ -310,6 +335,15 @@ __device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0
         const int col = col0 + wc + j * 32 + lr;
         if (row < M && col < a.e2) out[(size_t)row * a.e2 + col] = sc * acc[i][j][v];
       }
+}
+
+template <int BM, int BN, int WM, int WN, int BK>
+__device__ __forceinline__ void recon_tile32(const BoxArg& a, int row0, int col0,
+                                             float* __restrict__ out, char* smem) {
+  if (tile_one_i<BM>(a, row0))
+    recon_tile32_run<BM, BN, WM, WN, BK, true>(a, row0, col0, out, smem);
+  else
+    recon_tile32_run<BM, BN, WM, WN, BK, false>(a, row0, col0, out, smem);
 }
 
 }  // namespace ls
