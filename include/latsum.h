@@ -487,7 +487,9 @@ typedef struct ls_batch* ls_batch_t;
  * FP32 accumulation and output; LS_F16X3 scales every rank of both operands
  * by powers of two from the largest value of each sub-box factor column, as
  * the LS_F16X3 reconstruction does); everything else is FP64.
- * Errors: LS_EINVAL (system index in the message), LS_EUNSUPPORTED. */
+ * Errors: LS_EINVAL (system index in the message; among others a system with
+ * M0 R >= 2^20 ranks, or a folded density of 2 GB or more, which the kernel's
+ * 32-bit buffer offsets cannot address), LS_EUNSUPPORTED. */
 ls_status ls_batch_create(const ls_system* systems, int32_t count, int32_t precision,
                           ls_batch_t* batch, size_t* ws_bytes);
 /* Number of tile variants of the batch kernel (tile ids 1..n). */

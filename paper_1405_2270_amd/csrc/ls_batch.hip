@@ -1226,6 +1226,10 @@ extern "C" ls_status ls_batch_create(const ls_system* systems, int32_t count, in
     d.qoff = (int)nq;
     d.X = master_halfwidth(L);
     d.W = 2 * d.X + L.n;
+    // the tiles and the vector tasks address the factor columns and the folded
+    // density through buffer resources with 32-bit byte offsets
+    if ((long long)d.K * 256 * 8 >= (1LL << 31) || (long long)d.Krho * d.W * 8 >= (1LL << 31))
+      return fail("factor columns or folded density of 2 GB or more");
     d.nvec = 3 * S.M0;
     d.pos = S.pos_dev;
     d.Z = S.Z_dev;

@@ -123,6 +123,18 @@ def test_invalid_host_arguments(lib):
                                          None) == _lib.LS_EINVAL
     assert lib.ls_reconstruct_tuned_tile(ctypes.byref(P), B1, 0, 0, None, 0, ctypes.byref(tile),
                                          None) == _lib.LS_EINVAL
+    # a batch system whose factor columns the kernel's 32-bit buffer offsets
+    # cannot address (M0 R >= 2^20 ranks) is refused on the host, by index
+    tq, wq = np.linspace(0.1, 2.0, 60), np.full(60, 0.01)
+    quad60 = _lib.Quad(60, tq.ctypes.data_as(_lib.c_double_p), wq.ctypes.data_as(_lib.c_double_p))
+    rho8 = _lib.Canon(8, (ctypes.c_int32 * 3)(24, 24, 24), (ctypes.c_void_p * 3)(16, 16, 16), 16)
+    sysd = (_lib.System * 1)()
+    sysd[0] = _lib.System(box, quad60, 20000, 16, 16, rho8,
+                          _lib.Box((ctypes.c_int32 * 3)(0, 0, 0), (ctypes.c_int32 * 3)(4, 4, 4)), 16, 16)
+    handle, nws = ctypes.c_void_p(), ctypes.c_size_t(0)
+    st = lib.ls_batch_create(sysd, 1, 4, ctypes.byref(handle), ctypes.byref(nws))
+    assert st == _lib.LS_EINVAL and b"system 0" in lib.ls_last_error() and b"2 GB" in lib.ls_last_error(), \
+        lib.ls_last_error()
     assert lib.ls_reconstruct_tiles(0) >= 1 and lib.ls_reconstruct_tiles(9) == 0
     assert lib.ls_reconstruct_tiles(4) == 8 and lib.ls_reconstruct_workspace(None, 4) == 0
     assert lib.ls_reconstruct_workspace(None, 2) == 0
