@@ -125,7 +125,7 @@ def test_batch_rejects_bad_systems():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("precision", ["f32", "f16x3"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "f16x3"])
 def test_config4_smallest_systems_against_oracle(precision):
     # the batched workload's own systems: the six cheapest (oracle cost) in a
     # batch with six mid-size ones; sampled sub-box values and energies

@@ -216,6 +216,29 @@ def test_reconstruct(L, name, maker, precision):
                 assert rel_inf < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16x6", "bf16x3", "f16x3"])
+def test_reconstruct_tiles_over_several_i(L, precision):
+    # boxes whose 43 or more values of j put a 128-row tile's rows in up to
+    # four values of i (the tiles' per-i rank factors), one with 42 (five
+    # values: each element loads its own f0), and the whole grid, every tile
+    # id against the oracle (Appendix, eq. CP_form)
+    sysm = small_box(141, n=12, L=(3, 5, 2), M0=3)
+    t, w, qt = _quads(sysm, L)
+    F, coef = _gpu_factors(L, sysm, qt)
+    Fo, co = direct_factors(_geom(sysm), t, w, sysm.pos, sysm.Z)
+    h3 = sysm.h ** 3
+    N = [f.shape[1] for f in F]
+    boxes = [(0, 0, 0, N[0], N[1], N[2]), (2, 7, 3, 5, 43, 20), (0, 3, 0, 3, 42, N[2]), (1, 1, 1, 4, 59, 7)]
+    for tile in range(L.reconstruct_tiles(precision) + 1):
+        outs = L.reconstruct(F, coef, boxes, 1.0 / h3, precision, tile)
+        torch.cuda.synchronize()
+        for b, out in zip(boxes, outs):
+            ref = o_reconstruct(Fo, co, b[:3], b[3:]) / h3
+            ref_abs = o_reconstruct(Fo, np.abs(co), b[:3], b[3:]) / h3
+            rel_inf, rel_mag = _errors(out.double().cpu().numpy(), ref, ref_abs)
+            assert rel_mag < _gate(precision, coef.numel()), (precision, tile, b, rel_inf, rel_mag)
+
+
 @pytest.mark.parametrize("precision", ["f64", "bf16x6", "bf16x3", "f16x3"])
 def test_prepared_matches_reconstruct(L, precision):
     # the preparation as a call of its own (on another stream, joined by an
