@@ -277,6 +277,23 @@ __global__ __launch_bounds__(256, 3) void k_force_grams(const double* __restrict
     // across the loop
     double tq = tau, dq = delta, kq = knorm, eq = ec;
     asm volatile("" : "+v"(tq), "+v"(dq), "+v"(kq), "+v"(eq));
+    // the cell's RHO densities (zero past Krho), 16 bytes per load; with FP32
+    // Grams of 8 densities requested before the edge is evaluated, so that the
+    // evaluation covers their latency (cells past the support read the last
+    // one's and are not used); otherwise that would exceed the register budget
+    // of three waves per SIMD (spills), so they are requested where used
+    constexpr bool kEarly = sizeof(T) == 4 && RHO == 8;
+    double fv[RHO];
+    auto load_rho = [&](int jc) {
+      const double2* c2 = reinterpret_cast<const double2*>(ph + (ptrdiff_t)jc * RHO);
+#pragma unroll
+      for (int q2 = 0; q2 < RHO / 2; ++q2) {
+        const double2 v = c2[q2];
+        fv[2 * q2] = v.x;
+        fv[2 * q2 + 1] = v.y;
+      }
+    };
+    if constexpr (kEarly) load_rho(min(j, jend - 1));
     double ev = 0.0, gv = 0.0;
     if (edge_needed(tq, j, dq)) ev = edge_value(tq, (double)j - dq, &gv);
     eb[threadIdx.x] = ev;
@@ -288,15 +305,7 @@ __global__ __launch_bounds__(256, 3) void k_force_grams(const double* __restrict
       const double bv = lat.h * cell_value_deriv(tq, y0, eb[threadIdx.x], eb[threadIdx.x + 1],
                                                  gb[threadIdx.x], gb[threadIdx.x + 1], kq, eq, &bd);
       if (bv != 0.0 || bd != 0.0) {
-        // the cell's RHO densities (zero past Krho), 16 bytes per load
-        const double2* c2 = reinterpret_cast<const double2*>(ph + (ptrdiff_t)j * RHO);
-        double fv[RHO];
-#pragma unroll
-        for (int q2 = 0; q2 < RHO / 2; ++q2) {
-          const double2 v = c2[q2];
-          fv[2 * q2] = v.x;
-          fv[2 * q2 + 1] = v.y;
-        }
+        if constexpr (!kEarly) load_rho(j);
 #pragma unroll
         for (int s = 0; s < RHO; ++s) {
           av[s] += (T)bv * (T)fv[s];
