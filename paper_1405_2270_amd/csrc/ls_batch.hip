@@ -487,6 +487,10 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   const int M = a.e0 * a.e1, nch = (a.K + BK - 1) / BK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave / (BN / WN)) * WM, wc = (wave % (BN / WN)) * WN;
+  // a wave whose columns all lie past the sub-box (narrow boxes, the last
+  // column tile) stages the left operand with the others but issues no
+  // right-operand loads and no MFMAs (uniform per wave)
+  const bool wlive = __builtin_amdgcn_readfirstlane(col0 + wc) < a.e2;
   const int mw = tid % BM;
   const int kbw = __builtin_amdgcn_readfirstlane(tid / BM) * KW;
   const int i0 = row0 / a.e1;
@@ -635,7 +639,7 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
   put_alpha(0);
   load_alpha(BK);
   load_w(0);
-  load_b(0, bv0);
+  if (wlive) load_b(0, bv0);
   __syncthreads();
   // chunk c: its left operand goes to buffer c & 1, which the products of
   // chunk c - 2 read before the previous barrier; its rank factors were
@@ -649,11 +653,11 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
     // reason as the rank factors
     if (FAST || c + 1 < nch) load_w((c + 1) * BK);
     load_alpha((c + 2) * BK);
-    load_b(min(c + 1, nch - 1), nxt);
+    if (wlive) load_b(min(c + 1, nch - 1), nxt);
     // keep these loads ahead of the MFMAs (the scheduler would otherwise sink
     // them below, and the next chunk would wait for them)
     __builtin_amdgcn_sched_barrier(0);
-    products(cur, c & 1);
+    if (wlive) products(cur, c & 1);
   };
   for (int c = 0; c < nch; c += 2) {
     step(c, bv0, bv1);
