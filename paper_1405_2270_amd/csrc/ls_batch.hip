@@ -649,8 +649,8 @@ __device__ __forceinline__ void f16_tile_run(const BoxArg& a, int row0, int col0
     store_w(c & 1);
     put_alpha((c + 1) & 1);
     __syncthreads();
-    // FAST: unconditional (clamped ranks past the last chunk), for the same
-    // reason as the rank factors
+    // FAST: unconditional (past the last chunk the buffer reads 0), for the
+    // same reason as the rank factors
     if (FAST || c + 1 < nch) load_w((c + 1) * BK);
     load_alpha((c + 2) * BK);
     if (wlive) load_b(min(c + 1, nch - 1), nxt);
