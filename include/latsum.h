@@ -238,8 +238,16 @@ ls_status ls_assemble_tensor(const ls_tensor_lattice* tlat, const ls_quad* quad,
  * 2^-g (results below the FP32 range then flush to zero, as they would in any
  * FP32 output). The rank factors coef_r f0 2^(g - 13 + e_r) are formed in
  * FP64, so factor rows whose largest entries differ by more than about 10^290
- * between the axes of one rank are outside its range. NULL / 0 is valid for
- * every other precision and tile.
+ * between the axes of one rank are outside its range. The ranks are taken in
+ * an order of the library's (with K <= 1024: decreasing max|f0[r]|, ties by
+ * index, so that terms of similar width share a chunk of 32 ranks; otherwise
+ * as given), and for each plane i of axis 0 the chunks whose rank factors
+ * times the scaled f2 round to zero in both FP16 terms (|coef_r f0[r][i]
+ * 2^(g - 13 + e_r + e2_r)| <= 2^-27, e2_r = floor(log2 max|f2[r]|)) are
+ * marked absent and skipped: they would add only zeros, so the result is bit
+ * for bit that of the full sum in the same order (ls_reconstruct_f16_plan
+ * reports the order, the marks and the work). NULL / 0 is valid for every
+ * other precision and tile.
  * Errors: LS_EINVAL (box outside the factors, nbox < 1, K < 1),
  * LS_EUNSUPPORTED (tile id not valid for the precision; LS_F16X3 with over
  * 2^31 tiles in a group of boxes or an operand of 2 GB or more; tiles 1..5 of
@@ -312,6 +320,26 @@ ls_status ls_reconstruct_autotune(const ls_canon* P, const ls_box* boxes, int32_
 ls_status ls_reconstruct_tuned_tile(const ls_canon* P, const ls_box* boxes, int32_t nbox,
                                     int32_t precision, const void* ws_dev, size_t ws_bytes,
                                     int32_t* tile, double* ms);
+/* The LS_F16X3 preparation that ws_dev holds (ls_reconstruct_prepare or an
+ * earlier ls_reconstruct of the same factors, complete before this call:
+ * it copies from the device synchronously, on the null stream), and the
+ * work of reconstructing `boxes` from it (Appendix, eq. CP_form; the chunk
+ * skipping is a project addition). perm_host (host, nullable, K entries):
+ * perm_host[s] = the caller's rank in slot s of the library's order.
+ * masks_host (host, nullable, len[0] entries): bit c set when rank chunk c
+ * (slots 32c .. 32c+31) has a nonzero FP16 term on that plane of axis 0;
+ * when the ranks fill more than 32 chunks none is skipped, every entry is
+ * 0xFFFFFFFF and chunk_values counts every chunk. chunk_values (host, nullable): the sum over the boxes'
+ * values of the chunks their plane runs (a plane with no marked chunk runs
+ * chunk 0, whose terms are all zero), so that 2 x 32 x chunk_values is the
+ * multiply-adds of one FP16 product of the persistent tiles, against
+ * 2 x 32 x ceil(K/32) x values without skipping.
+ * Errors: LS_EINVAL (null factors, nbox < 1, a box outside the factors),
+ * LS_EWORKSPACE (missing or short workspace), LS_EHIP (copy failure).
+ */
+ls_status ls_reconstruct_f16_plan(const ls_canon* P, const ls_box* boxes, int32_t nbox,
+                                  const void* ws_dev, size_t ws_bytes, int32_t* perm_host,
+                                  uint32_t* masks_host, int64_t* chunk_values);
 
 /*
  * Energy as a canonical scalar product (Appendix, eq. scal) with a density

@@ -8,13 +8,13 @@ package only marshals torch tensors into its C ABI.
 from .api import (LatticeSpec, TensorLatticeSpec, QuadTable, quadrature, master_halfwidth,
                   kernel_vectors, assemble, assemble_into, assemble_tensor,
                   reconstruct, reconstruct_into, reconstruct_prepare, reconstruct_tiles,
-                  reconstruct_autotune, reconstruct_tuned_tile, energy, forces,
+                  reconstruct_autotune, reconstruct_tuned_tile, reconstruct_f16_plan, energy, forces,
                   LatticeEnergy,
                   lattice_energy, Batch, batch_cache_file, combine, richardson,
                   nuclear_matrix, qtt_compress, qtt_expand, probe_copy, probe_mfma)
 
 __all__ = ["LatticeSpec", "TensorLatticeSpec", "QuadTable", "quadrature", "master_halfwidth",
            "kernel_vectors", "assemble", "assemble_into", "assemble_tensor", "reconstruct", "reconstruct_into", "reconstruct_prepare",
-           "reconstruct_tiles", "reconstruct_autotune", "reconstruct_tuned_tile", "energy", "forces",
+           "reconstruct_tiles", "reconstruct_autotune", "reconstruct_tuned_tile", "reconstruct_f16_plan", "energy", "forces",
            "LatticeEnergy", "lattice_energy", "Batch", "batch_cache_file", "combine", "richardson",
            "nuclear_matrix", "qtt_compress", "qtt_expand", "probe_copy", "probe_mfma"]

@@ -95,6 +95,10 @@ _SIGNATURES = {
                                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                                  ctypes.POINTER(ctypes.c_int32),
                                                  ctypes.POINTER(ctypes.c_double)]),
+    "ls_reconstruct_f16_plan": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Box), ctypes.c_int32,
+                                               ctypes.c_void_p, ctypes.c_size_t, c_int32_p,
+                                               ctypes.POINTER(ctypes.c_uint32),
+                                               ctypes.POINTER(ctypes.c_int64)]),
     "ls_energy_workspace": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "ls_energy": (ctypes.c_int, [ctypes.POINTER(Canon), ctypes.POINTER(Canon), ctypes.c_int32,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),

@@ -397,6 +397,33 @@ def reconstruct_tuned_tile(F, coef, boxes, precision="f64", ws_bytes=None):
     return int(t.value), float(ms.value)
 
 
+
+def reconstruct_f16_plan(F, coef, boxes, ws):
+    """The FP16x3 preparation held in ``ws`` (made by ``reconstruct_prepare``
+    on the same factors) and the work of reconstructing ``boxes`` from it:
+    dict with ``perm`` (int32, slot s -> the caller's rank), ``masks``
+    (uint32 per plane of axis 0, bit c: rank chunk c runs there) and
+    ``chunk_values`` (sum over the boxes' values of the chunks their plane
+    runs). Synchronizes the device."""
+    import numpy as np
+    boxes, cb = _boxes_c(boxes)
+    canon = _canon(F, coef)
+    ws = _ws_tensor(ws, F[0].device)
+    if ws is None:
+        raise ValueError("the workspace of reconstruct_prepare is required")
+    torch.cuda.synchronize(F[0].device)
+    K, n0 = int(F[0].shape[0]), int(F[0].shape[1])
+    perm = np.zeros(K, np.int32)
+    masks = np.zeros(n0, np.uint32)
+    cv = ctypes.c_int64(0)
+    check("ls_reconstruct_f16_plan",
+          lib().ls_reconstruct_f16_plan(ctypes.byref(canon), cb, len(boxes), _ptr(ws),
+                                        ws.numel() * ws.element_size(),
+                                        perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                        masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                        ctypes.byref(cv)))
+    return {"perm": perm, "masks": masks, "chunk_values": int(cv.value)}
+
 def energy(F, coef, D, d, precision="f64", ws=None):
     """E = <P, rho> (eq. scal) as a device scalar tensor."""
     cP, cR = _canon(F, coef), _canon(D, d, "density")

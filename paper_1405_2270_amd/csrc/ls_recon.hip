@@ -22,6 +22,7 @@
 // A[l%16][k-group l/16] and B[k-group l/16][l%16]. It receives D[4*(l/16) + v][l%16]
 // (v = 0..3) from the f32 and bf16 instructions, and D[l/16 + 4v][l%16] from the
 // f64 one (checked on gfx950).
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -52,6 +53,11 @@ struct BoxSet {
   const int* gexp;                            // LS_F16X3: g
   const double* coefS32;                      // LS_F16X3: coefS_r 2^(e2_r)
   const float* f2f;                           // LS_F16X3: f2 2^(-e2_r) rounded to FP32
+  // LS_F16X3: rank slot s holds rank perm[s] of the caller's factors (P2,
+  // f2f, coefS and coefS32 are in slot order); cmask[x] bit c set when chunk
+  // c has a nonzero FP16 term on plane x of axis 0 (null: every chunk runs)
+  const int* perm;
+  const unsigned* cmask;
 };
 
 __device__ __forceinline__ bool locate(const BoxSet& bs, int* b, int* tm, int* tn) {
@@ -195,68 +201,134 @@ ls_status launch_rank_max(const double* f0, const double* f1, const double* f2, 
 // floor(log2 m) for a row maximum m, 0 for a zero or non-finite row
 __device__ __forceinline__ int row_exp(double m) { return (m > 0.0 && isfinite(m)) ? ilogb(m) : 0; }
 
-// With e_r = row_exp(max|f1[r]|) and e2_r = row_exp(max|f2[r]|) from rmax:
-// blockIdx.y < nch: as k_presplit<2>, with rank r of f1 scaled by
-// 2^(13 - e_r) and FP16 terms; nch <= y < nch + n8: ranks 8 (y - nch) .. +7 of
-// f2 scaled by 2^-e2_r and rounded to FP32 (the FP16 split of the other
-// operand keeps 22 bits; f2 in FP32 halves the bytes the kernel loads for it);
-// y = nch + n8, x = 0 (one wave): g from the largest bound b_r = |coef_r|
-// max|f0[r]| max|f2[r]| 2^(e_r - 13), coefS[r] = coef[r] 2^(g - 13 + e_r) and,
-// for the FP32 copy of f2, coefS32[r] = coefS[r] 2^(e2_r).
+// Rank order and scales of LS_F16X3 (one workgroup of 512 threads, which fits
+// beside other work on a CU), from the
+// row maxima rmax = [max|f0[r]|, max|f1[r]|, max|f2[r]|], e_r = row_exp of the
+// f1 maximum, e2_r of the f2 maximum. Slot s of the reordered ranks holds rank
+// perm[s]: with K <= kOrderRanks the ranks in decreasing max|f0[r]| (ties by
+// index), so that terms of similar width, whose f0 vanishes on the same planes,
+// share a chunk of 32; otherwise the given order. g from the largest bound
+// b_r = |coef_r| max|f0[r]| max|f2[r]| 2^(e_r - 13), then in slot order
+// coefS[s] = coef_r 2^(g - 13 + e_r) and coefS32[s] = coefS[s] 2^(e2_r),
+// r = perm[s]. Clears the chunk masks (len0 words) when cmask is given.
+constexpr int kOrderRanks = 1024;
+__global__ __launch_bounds__(512) void k_f16_order(const double* __restrict__ coef,
+                                                   const double* __restrict__ rmax, int K,
+                                                   int len0, int* __restrict__ perm,
+                                                   double* __restrict__ coefS,
+                                                   double* __restrict__ coefS32,
+                                                   int* __restrict__ gexp,
+                                                   unsigned* __restrict__ cmask) {
+  __shared__ double key[kOrderRanks];
+  __shared__ double red[8];
+  const int t = threadIdx.x;
+  const double* __restrict__ m1 = rmax + K;
+  const double* __restrict__ m2 = rmax + 2 * (size_t)K;
+  const bool order = K <= kOrderRanks;
+  if (order)
+    for (int r = t; r < K; r += 512) key[r] = isfinite(rmax[r]) ? rmax[r] : 0.0;
+  double m = 0.0;
+  for (int r = t; r < K; r += 512)
+    m = fmax(m, fabs(coef[r]) * rmax[r] * m2[r] * ldexp(1.0, row_exp(m1[r]) - 13));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((t & 63) == 0) red[t >> 6] = m;
+  __syncthreads();
+  m = red[0];
+  for (int w = 1; w < 8; ++w) m = fmax(m, red[w]);
+  const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
+  for (int r = t; r < K; r += 512) {
+    int s = r;
+    if (order) {
+      // the rank's place in the order: the ranks before it
+      // (eight LDS reads in flight per step, and the tests combined with
+      // bitwise operators: short-circuit ones become a branch per test)
+      const double k = key[r];
+      s = 0;
+      int q = 0;
+      for (; q + 8 <= K; q += 8) {
+        double kq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kq[u] = key[q + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += (int)(kq[u] > k) | ((int)(kq[u] == k) & (int)(q + u < r));
+      }
+      for (; q < K; ++q) s += (int)(key[q] > k) | ((int)(key[q] == k) & (int)(q < r));
+    }
+    const double cs = coef[r] * ldexp(1.0, g - 13 + row_exp(m1[r]));
+    perm[s] = r;
+    coefS[s] = cs;
+    coefS32[s] = ldexp(cs, row_exp(m2[r]));
+  }
+  if (t == 0) *gexp = g;
+  if (cmask != nullptr)
+    for (int x = t; x < len0; x += 512) cmask[x] = 0u;
+}
+
+// After k_f16_order, in slot order (r = perm[s]): blockIdx.y < nch: as
+// k_presplit<2>, with rank r of f1 scaled by 2^(13 - e_r) and FP16 terms;
+// nch <= y < nch + n8: slots 8 (y - nch) .. +7 of f2 scaled by 2^-e2_r and
+// rounded to FP32 (the FP16 split of the other operand keeps 22 bits; f2 in
+// FP32 halves the bytes the kernel loads for it); nch + n8 <= y (with cmask):
+// the chunk c = y - nch - n8 of every plane x of axis 0 is marked in cmask[x]
+// unless |coefS32[s] f0[r][x]| <= 2^-27 for each of its 32 slots. The
+// reconstruction forms the same FP64 product as its rank factor; a rank
+// factor of at most 2^-27 times the scaled f2 (below 2 in magnitude) gives a
+// value of at most 2^-26 (2^-25 in the FP64-f2 tiles), which rounds to zero
+// in both FP16 terms, so an unmarked chunk adds only zeros to the plane's
+// outputs and is skipped without changing a bit.
 __global__ __launch_bounds__(64) void k_prep_f16(const double* __restrict__ f,
                                                  const double* __restrict__ f2,
-                                                 const double* __restrict__ coef,
-                                                 const double* __restrict__ rmax, int K, int len,
-                                                 int len2, int nch, int n8,
+                                                 const double* __restrict__ f0,
+                                                 const double* __restrict__ rmax,
+                                                 const int* __restrict__ perm,
+                                                 const double* __restrict__ coefS32, int K,
+                                                 int len0, int len, int len2, int nch, int n8,
                                                  unsigned* __restrict__ P, float* __restrict__ f2f,
-                                                 double* __restrict__ coefS,
-                                                 double* __restrict__ coefS32,
-                                                 int* __restrict__ gexp) {
+                                                 unsigned* __restrict__ cmask) {
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int c = blockIdx.y;
   const double* __restrict__ m1 = rmax + K;
   const double* __restrict__ m2 = rmax + 2 * (size_t)K;
-  if (c == nch + n8) {
-    if (blockIdx.x != 0) return;
-    double m = 0.0;
-    for (int r = threadIdx.x; r < K; r += 64)
-      m = fmax(m, fabs(coef[r]) * rmax[r] * m2[r] * ldexp(1.0, row_exp(m1[r]) - 13));
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
-    const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
-    for (int r = threadIdx.x; r < K; r += 64) {
-      const double cs = coef[r] * ldexp(1.0, g - 13 + row_exp(m1[r]));
-      coefS[r] = cs;
-      coefS32[r] = ldexp(cs, row_exp(m2[r]));
+  if (c >= nch + n8) {
+    if (x >= len0) return;
+    const int cc = c - nch - n8;
+    // all 32 loads in flight, then the tests
+    double a[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int sl = min(32 * cc + q, K - 1);
+      a[q] = f0[(size_t)perm[sl] * len0 + x];
     }
-    if (threadIdx.x == 0) *gexp = g;
+    int act = 0;
+#pragma unroll
+    for (int q = 0; q < 32; ++q)
+      act |= (int)(32 * cc + q < K) & (int)!(fabs(coefS32[min(32 * cc + q, K - 1)] * a[q]) <= 0x1p-27);
+    if (act) atomicOr(&cmask[x], 1u << cc);
     return;
   }
   if (c >= nch) {
     if (x >= len2) return;
     double v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = f2[(size_t)min(8 * (c - nch) + q, K - 1) * len2 + x];
+    for (int q = 0; q < 8; ++q) v[q] = f2[(size_t)perm[min(8 * (c - nch) + q, K - 1)] * len2 + x];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int r = 8 * (c - nch) + q;
-      if (r < K) f2f[(size_t)r * len2 + x] = (float)ldexp(v[q], -row_exp(m2[r]));
+      const int sl = 8 * (c - nch) + q;
+      if (sl < K) f2f[(size_t)sl * len2 + x] = (float)ldexp(v[q], -row_exp(m2[perm[sl]]));
     }
     return;
   }
   if (x >= len) return;
   double v[32];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    const int r = min(32 * c + q, K - 1);
-    v[q] = f[(size_t)r * len + x];
-  }
+  for (int q = 0; q < 32; ++q) v[q] = f[(size_t)perm[min(32 * c + q, K - 1)] * len + x];
   unsigned pk[2][16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int r0 = 32 * c + 2 * q;
+    const int s0 = 32 * c + 2 * q;
     unsigned u0[2], u1[2];
-    split_f16(r0 < K ? (float)ldexp(v[2 * q], 13 - row_exp(m1[min(r0, K - 1)])) : 0.0f, u0);
-    split_f16(r0 + 1 < K ? (float)ldexp(v[2 * q + 1], 13 - row_exp(m1[min(r0 + 1, K - 1)])) : 0.0f, u1);
+    split_f16(s0 < K ? (float)ldexp(v[2 * q], 13 - row_exp(m1[perm[min(s0, K - 1)]])) : 0.0f, u0);
+    split_f16(s0 + 1 < K ? (float)ldexp(v[2 * q + 1], 13 - row_exp(m1[perm[min(s0 + 1, K - 1)]])) : 0.0f, u1);
 #pragma unroll
     for (int t = 0; t < 2; ++t) pk[t][q] = pack_hi(u0[t], u1[t]);
   }
@@ -690,14 +762,17 @@ __global__ __launch_bounds__(256, 2) void k_recon_direct(BoxSet bs, float* __res
 // workgroup l of nbx takes tiles l, l + nbx, l + 2 nbx, ... of the range, so
 // at any time the XCD works on neighbouring tiles, which read the same f1 and
 // f2 slices from its L2. A workgroup walks its tiles as one stream of steps,
-// step s being rank chunk s % nchunk of its tile s / nchunk, and runs the
-// pipeline of the direct kernel (PIPE = 1) over the whole stream: the split
+// step s being rank chunk s % nchunk of its tile s / nchunk (with chunk
+// masks, only the chunks marked for the tile's plane of axis 0, in order),
+// and runs the pipeline of the direct kernel (PIPE = 1) over the whole
+// stream: the split
 // of step s+1 and the loads of steps s+2 and s+3 overlap the MFMAs of step s
 // also across tile boundaries, so a tile starts without waiting for memory,
 // and its results are stored (non-temporal) while the stream goes on.
 struct StreamPos {
-  int c;  // rank chunk
-  int g;  // tile number
+  int c;       // rank chunk
+  unsigned m;  // with chunk masks: the chunks of the tile's plane
+  int g;       // tile number
   int ib, j0, col0;
   int o0, o1, o2, e1, e2;
   long long ooff;  // element offset of the tile's box in the output
@@ -723,11 +798,32 @@ __device__ __forceinline__ void stream_tile(const BoxSet& bs, int g, StreamPos& 
   p.e1 = rfl(a.e1);
   p.e2 = rfl(a.e2);
   p.ooff = bs.out_off[i];
+  // the chunks marked for the plane, or chunk 0 alone when none is (its terms
+  // are then all zero, and so are the tile's outputs)
+  if (bs.cmask != nullptr) {
+    const unsigned m = (unsigned)rfl((int)bs.cmask[p.o0 + p.ib]);
+    p.m = m ? m : 1u;
+  }
+}
+
+// chunks of p's tile after chunk p.c (with chunk masks)
+__device__ __forceinline__ unsigned chunks_after(const StreamPos& p) {
+  return p.m & ~((2u << p.c) - 1u);
 }
 
 // position of the step after p (the caller keeps p at the stream's last step)
 template <int BN>
 __device__ __forceinline__ void stream_next(const BoxSet& bs, StreamPos& p, int nchunk, int nbx) {
+  if (bs.cmask != nullptr) {
+    const unsigned rest = chunks_after(p);
+    if (rest != 0u) {
+      p.c = __builtin_ctz(rest);
+    } else {
+      stream_tile<BN>(bs, p.g + nbx, p);
+      p.c = __builtin_ctz(p.m);
+    }
+    return;
+  }
   if (p.c + 1 < nchunk) {
     p.c += 1;
   } else {
@@ -784,7 +880,16 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   const BoxArg a = uniform_box(bs.box[0]);  // factor pointers, K and lengths are common
   const int K = a.K, len0 = a.len0, len2 = a.len2;
   const int nchunk = (K + BK - 1) / BK;
-  const int S = ntile * nchunk;
+  // steps of the stream: every chunk of every tile, or the marked ones
+  int S = ntile * nchunk;
+  if (bs.cmask != nullptr) {
+    S = 0;
+    for (int t = 0; t < ntile; ++t) {
+      StreamPos q;
+      stream_tile<BN>(bs, xcd * per + l + t * nbx, q);
+      S += __builtin_popcount(q.m);
+    }
+  }
   const int nch = rfl(bs.nch);
   const int plane = a.len1 * 64;  // bytes per rank chunk of one term
   // f2 and the pre-split f1 are read through buffer resources: a uniform
@@ -798,6 +903,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       const_cast<unsigned*>(bs.P2), (short)0, (int)(NT * nch * plane), kBufferFlags);
   const double* __restrict__ A1 = a.A1;
   const double* __restrict__ coef = FMT ? (YV == 3 ? bs.coefS32 : bs.coefS) : a.coef;
+  // LS_F16X3: the caller's rank of each slot, for the reads of f0 and the FP64 f2
+  const int* __restrict__ perm = bs.perm;
   const float sc = FMT ? (float)(a.scale * ldexp(1.0, -rfl(*bs.gexp))) : (float)a.scale;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -851,7 +958,8 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       const int cb = (p.o2 + min(p.col0 + 2 * yp, p.e2 - 1)) * 8;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int r = min(p.c * BK + kby + 4 * yh + kk, K - 1);
+        const int r = FMT ? perm[min(p.c * BK + kby + 4 * yh + kk, K - 1)]
+                          : min(p.c * BK + kby + 4 * yh + kk, K - 1);
         const d2_t v = __builtin_bit_cast(d2_t, __builtin_amdgcn_raw_buffer_load_b128(ybuf, r * len2 * 8 + cb, 0, 0));
         yv[2 * kk] = v[0];
         yv[2 * kk + 1] = v[1];
@@ -860,7 +968,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
       const int yoff = (p.o2 + min(p.col0 + ny, p.e2 - 1)) * 8;
 #pragma unroll
       for (int kk = 0; kk < KY; ++kk) {
-        const int r = min(p.c * BK + kby + kk, K - 1);
+        const int r = FMT ? perm[min(p.c * BK + kby + kk, K - 1)] : min(p.c * BK + kby + kk, K - 1);
         yv[kk] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ybuf, yoff, r * len2 * 8, 0));
       }
     }
@@ -870,7 +978,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
     if (!(OPT & 1) || wave0) {
       const int r = min(p.c * BK + min(tid, BK - 1), K - 1);
       v[0] = coef[r];
-      v[1] = A1[(size_t)(p.o0 + p.ib) + (size_t)r * len0];
+      v[1] = A1[(size_t)(p.o0 + p.ib) + (size_t)(FMT ? perm[r] : r) * len0];
     }
   };
   auto pt_al = [&](int ab, const double (&v)[2], const StreamPos& p) {
@@ -997,6 +1105,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
   StreamPos p0, p1, p2, p3;
   p0.c = 0;
   stream_tile<BN>(bs, xcd * per + l, p0);
+  if (bs.cmask != nullptr) p0.c = __builtin_ctz(p0.m);
   p1 = p0;
   if (S > 1) stream_next<BN>(bs, p1, nchunk, nbx);
   p2 = p1;
@@ -1097,7 +1206,7 @@ __global__ __launch_bounds__(256, 2) void k_recon_stream(BoxSet bs, int nbx,
     else
       store_y(ys, yb ^ 1, yb ^ 1);
     pt_al(yb, as, p2);
-    if (p0.c == nchunk - 1) epilogue(p0);
+    if (bs.cmask != nullptr ? chunks_after(p0) == 0u : p0.c == nchunk - 1) epilogue(p0);
     __syncthreads();
     p0 = p1;
     p1 = p2;
@@ -1328,11 +1437,13 @@ static size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
 // LS_F16X3 workspace: pre-split f1 (two FP16 terms) | row maxima of f0, f1,
 // f2 (3 x K double) | coefS (double) | g (int) | coefS32 (double) | f2
-// 2^(-e2_r) rounded to FP32 (K x len2)
+// 2^(-e2_r) rounded to FP32 (K x len2) | rank order (K int) | chunk masks of
+// the planes of axis 0 (len0 words, when the ranks fill at most 32 chunks)
 struct F16Layout {
-  size_t p, rmax, coefS, gexp, coefS32, f2f, total;
+  size_t p, rmax, coefS, gexp, coefS32, f2f, perm, cmask, total;
 };
-static F16Layout f16_layout(int K, int len1, int len2) {
+static bool f16_masks(int K) { return (K + SPLIT_BK - 1) / SPLIT_BK <= 32; }
+static F16Layout f16_layout(int K, int len0, int len1, int len2) {
   F16Layout L;
   const size_t nch = (size_t)((K + SPLIT_BK - 1) / SPLIT_BK);
   L.p = 0;
@@ -1341,12 +1452,15 @@ static F16Layout f16_layout(int K, int len1, int len2) {
   L.gexp = L.coefS + align256((size_t)K * 8);
   L.coefS32 = L.gexp + 256;
   L.f2f = L.coefS32 + align256((size_t)K * 8);
-  L.total = L.f2f + align256((size_t)K * len2 * 4);
+  L.perm = L.f2f + align256((size_t)K * len2 * 4);
+  L.cmask = L.perm + align256((size_t)K * 4);
+  L.total = L.cmask + (f16_masks(K) ? align256((size_t)len0 * 4) : 0);
   return L;
 }
 
-static size_t presplit_bytes(int precision, int K, int len1, int len2) {
-  if (precision == LS_F16X3) return f16_layout(K, len1, len2).total;
+static size_t presplit_bytes(int precision, const ls_canon* P) {
+  const int K = P->K, len1 = P->len[1];
+  if (precision == LS_F16X3) return f16_layout(K, P->len[0], len1, P->len[2]).total;
   if (precision != LS_BF16X3 && precision != LS_BF16X6) return 0;
   const size_t nt = precision == LS_BF16X6 ? 3 : 2;
   return nt * (size_t)((K + SPLIT_BK - 1) / SPLIT_BK) * (size_t)len1 * 64;
@@ -1410,7 +1524,7 @@ extern "C" int32_t ls_reconstruct_tiles(int32_t precision) {
 
 extern "C" size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision) {
   if (P == nullptr || P->K < 1 || P->len[1] < 1) return 0;
-  return presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  return presplit_bytes(precision, P);
 }
 
 // What a call with a workspace forms there before its reconstruction
@@ -1418,7 +1532,7 @@ extern "C" size_t ls_reconstruct_workspace(const ls_canon* P, int32_t precision)
 // and the scaled rank factors; for the split-bf16 precisions the pre-split f1.
 static ls_status prepare_ws(const ls_canon* P, int precision, void* ws_dev, hipStream_t stream) {
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
-  const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
+  const F16Layout fl = f16_layout(P->K, P->len[0], P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
   if (precision == LS_F16X3) {
     // the row maxima: those the assembly wrote, if the descriptor carries
@@ -1430,10 +1544,15 @@ static ls_status prepare_ws(const ls_canon* P, int precision, void* ws_dev, hipS
       rmax = (const double*)(wsb + fl.rmax);
     }
     const int n8 = (P->K + 7) / 8;
-    hipLaunchKernelGGL(k_prep_f16, dim3((std::max(P->len[1], P->len[2]) + 63) / 64, nch + n8 + 1), dim3(64),
-                       0, stream, P->f[1], P->f[2], P->coef, rmax, P->K,
-                       P->len[1], P->len[2], nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f),
-                       (double*)(wsb + fl.coefS), (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp));
+    unsigned* cmask = f16_masks(P->K) ? (unsigned*)(wsb + fl.cmask) : nullptr;
+    hipLaunchKernelGGL(k_f16_order, dim3(1), dim3(512), 0, stream, P->coef, rmax, P->K, P->len[0],
+                       (int*)(wsb + fl.perm), (double*)(wsb + fl.coefS),
+                       (double*)(wsb + fl.coefS32), (int*)(wsb + fl.gexp), cmask);
+    const int lx = std::max(std::max(P->len[1], P->len[2]), cmask ? P->len[0] : 1);
+    hipLaunchKernelGGL(k_prep_f16, dim3((lx + 63) / 64, nch + n8 + (cmask ? nch : 0)), dim3(64), 0,
+                       stream, P->f[1], P->f[2], P->f[0], rmax, (const int*)(wsb + fl.perm),
+                       (const double*)(wsb + fl.coefS32), P->K, P->len[0], P->len[1], P->len[2],
+                       nch, n8, (unsigned*)ws_dev, (float*)(wsb + fl.f2f), cmask);
     return launch_status("ls_reconstruct (scales and pre-split)");
   }
   dim3 grid((P->len[1] + 63) / 64, nch);
@@ -1514,7 +1633,7 @@ static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int3
     }
     LS_REQUIRE((long long)boxes[b].e[0] * boxes[b].e[1] < (1LL << 31), "box %d too large", b);
   }
-  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const size_t need = presplit_bytes(precision, P);
   const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
   int t = tile ? tile : tuned_tile(P, boxes, nbox, precision, have_ws, nullptr);
   if (t == 0)
@@ -1532,7 +1651,7 @@ static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int3
   }
   LS_REQUIRE(!pre || ws_aligned(ws_dev), "the workspace must be 256-byte aligned");
   const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
-  const F16Layout fl = f16_layout(P->K, P->len[1], P->len[2]);
+  const F16Layout fl = f16_layout(P->K, P->len[0], P->len[1], P->len[2]);
   char* wsb = (char*)ws_dev;
   if (pre && !prepared) {
     ls_status st = prepare_ws(P, precision, ws_dev, stream);
@@ -1548,6 +1667,8 @@ static ls_status reconstruct_common(const ls_canon* P, const ls_box* boxes, int3
     bs.gexp = precision == LS_F16X3 ? (const int*)(wsb + fl.gexp) : nullptr;
     bs.coefS32 = precision == LS_F16X3 ? (const double*)(wsb + fl.coefS32) : nullptr;
     bs.f2f = precision == LS_F16X3 ? (const float*)(wsb + fl.f2f) : nullptr;
+    bs.perm = precision == LS_F16X3 ? (const int*)(wsb + fl.perm) : nullptr;
+    bs.cmask = precision == LS_F16X3 && f16_masks(P->K) ? (const unsigned*)(wsb + fl.cmask) : nullptr;
     long long local = 0;
     for (int i = 0; i < bs.nbox; ++i) {
       const ls_box& bx = boxes[b0 + i];
@@ -1611,7 +1732,7 @@ extern "C" ls_status ls_reconstruct_autotune(const ls_canon* P, const ls_box* bo
   ls_status st = reconstruct_common(P, boxes, nbox, scale, precision, 0, out_dev, ws_dev,
                                     ws_bytes, stream, false);
   if (st != LS_OK) return st;
-  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const size_t need = presplit_bytes(precision, P);
   const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) {
@@ -1680,10 +1801,58 @@ extern "C" ls_status ls_reconstruct_tuned_tile(const ls_canon* P, const ls_box* 
   LS_REQUIRE(P != nullptr && boxes != nullptr && tile != nullptr, "null pointer");
   LS_REQUIRE(nbox >= 1, "nbox must be >= 1");
   LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
-  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const size_t need = presplit_bytes(precision, P);
   const bool have_ws = need > 0 && ws_dev != nullptr && ws_bytes >= need;
   if (ms) *ms = 0.0;
   *tile = tuned_tile(P, boxes, nbox, precision, have_ws, ms);
+  return LS_OK;
+}
+
+extern "C" ls_status ls_reconstruct_f16_plan(const ls_canon* P, const ls_box* boxes,
+                                             int32_t nbox, const void* ws_dev, size_t ws_bytes,
+                                             int32_t* perm_host, uint32_t* masks_host,
+                                             int64_t* chunk_values) {
+  clear_error();
+  ls_status cs = check_canon(P);
+  if (cs != LS_OK) return cs;
+  LS_REQUIRE(boxes != nullptr && nbox >= 1, "nbox must be >= 1");
+  for (int b = 0; b < nbox; ++b)
+    for (int l = 0; l < 3; ++l)
+      LS_REQUIRE(boxes[b].e[l] >= 1 && boxes[b].o[l] >= 0 &&
+                     (long long)boxes[b].o[l] + boxes[b].e[l] <= P->len[l],
+                 "box %d outside the factors on axis %d", b, l);
+  const size_t need = presplit_bytes(LS_F16X3, P);
+  if (ws_dev == nullptr || ws_bytes < need) {
+    set_error("a workspace of %zu bytes is required", need);
+    return LS_EWORKSPACE;
+  }
+  const F16Layout fl = f16_layout(P->K, P->len[0], P->len[1], P->len[2]);
+  const char* wsb = (const char*)ws_dev;
+  const int nch = (P->K + SPLIT_BK - 1) / SPLIT_BK;
+  const bool masked = f16_masks(P->K);
+  std::vector<uint32_t> m((size_t)P->len[0], masked ? 0u : ~0u);
+  if (masked && hipMemcpy(m.data(), wsb + fl.cmask, m.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("copy of the chunk masks failed");
+    return LS_EHIP;
+  }
+  if (perm_host != nullptr &&
+      hipMemcpy(perm_host, wsb + fl.perm, (size_t)P->K * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("copy of the rank order failed");
+    return LS_EHIP;
+  }
+  if (masks_host != nullptr) std::copy(m.begin(), m.end(), masks_host);
+  if (chunk_values != nullptr) {
+    long long cv = 0;
+    for (int b = 0; b < nbox; ++b) {
+      long long per_plane = 0;
+      for (int i = 0; i < boxes[b].e[0]; ++i) {
+        const uint32_t mi = m[(size_t)boxes[b].o[0] + i];
+        per_plane += masked ? (mi ? __builtin_popcount(mi) : 1) : nch;
+      }
+      cv += per_plane * boxes[b].e[1] * boxes[b].e[2];
+    }
+    *chunk_values = cv;
+  }
   return LS_OK;
 }
 
@@ -1693,7 +1862,7 @@ extern "C" ls_status ls_reconstruct_prepare(const ls_canon* P, int32_t precision
   ls_status cs = check_canon(P);
   if (cs != LS_OK) return cs;
   LS_REQUIRE(precision >= LS_F64 && precision <= LS_F16X3, "unknown precision %d", precision);
-  const size_t need = presplit_bytes(precision, P->K, P->len[1], P->len[2]);
+  const size_t need = presplit_bytes(precision, P);
   if (need == 0) return LS_OK;  // FP64 and FP32 use no workspace
   if (ws_dev == nullptr || ws_bytes < need) {
     set_error("a workspace of %zu bytes is required", need);

@@ -123,6 +123,23 @@ def test_invalid_host_arguments(lib):
                                          None) == _lib.LS_EINVAL
     assert lib.ls_reconstruct_tuned_tile(ctypes.byref(P), B1, 0, 0, None, 0, ctypes.byref(tile),
                                          None) == _lib.LS_EINVAL
+    # the FP16x3 plan query checks its boxes and workspace on the host before
+    # any copy; the FP16x3 workspace also holds the rank order (K words) and
+    # one chunk mask per plane of axis 0
+    cv = ctypes.c_int64(-1)
+    B9 = (_lib.Box * 1)(_lib.Box((ctypes.c_int32 * 3)(0, 0, 21), (ctypes.c_int32 * 3)(4, 4, 4)))
+    assert lib.ls_reconstruct_f16_plan(ctypes.byref(P), B9, 1, dummy, 1 << 40, None, None,
+                                       ctypes.byref(cv)) == _lib.LS_EINVAL
+    assert lib.ls_reconstruct_f16_plan(ctypes.byref(P), B1, 0, dummy, 1 << 40, None, None,
+                                       ctypes.byref(cv)) == _lib.LS_EINVAL
+    need = lib.ls_reconstruct_workspace(ctypes.byref(P), 4)
+    assert lib.ls_reconstruct_f16_plan(ctypes.byref(P), B1, 1, dummy, need - 1, None, None,
+                                       ctypes.byref(cv)) == _lib.LS_EWORKSPACE
+    assert lib.ls_reconstruct_f16_plan(ctypes.byref(P), B1, 1, None, need, None, None,
+                                       ctypes.byref(cv)) == _lib.LS_EWORKSPACE
+    assert cv.value == -1
+    P2 = _lib.Canon(4, (ctypes.c_int32 * 3)(1024, 24, 24), (ctypes.c_void_p * 3)(16, 16, 16), 16)
+    assert lib.ls_reconstruct_workspace(ctypes.byref(P2), 4) >= need + 1000 * 4 - 256
     # a batch system whose factor columns the kernel's 32-bit buffer offsets
     # cannot address (M0 R >= 2^20 ranks) is refused on the host, by index
     tq, wq = np.linspace(0.1, 2.0, 60), np.full(60, 0.01)
