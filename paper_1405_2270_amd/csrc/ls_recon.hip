@@ -237,27 +237,29 @@ __global__ __launch_bounds__(512) void k_f16_order(const double* __restrict__ co
   for (int w = 1; w < 8; ++w) m = fmax(m, red[w]);
   const int g = (m > 0.0 && isfinite(m)) ? 13 - ilogb(m) : 0;
   for (int r = t; r < K; r += 512) {
+    // the rank's values, requested before the ranking runs
+    const double cr = coef[r], mr1 = m1[r], mr2 = m2[r];
     int s = r;
     if (order) {
       // the rank's place in the order: the ranks before it
-      // (eight LDS reads in flight per step, and the tests combined with
+      // (sixteen LDS reads in flight per step, and the tests combined with
       // bitwise operators: short-circuit ones become a branch per test)
       const double k = key[r];
       s = 0;
       int q = 0;
-      for (; q + 8 <= K; q += 8) {
-        double kq[8];
+      for (; q + 16 <= K; q += 16) {
+        double kq[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) kq[u] = key[q + u];
+        for (int u = 0; u < 16; ++u) kq[u] = key[q + u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s += (int)(kq[u] > k) | ((int)(kq[u] == k) & (int)(q + u < r));
+        for (int u = 0; u < 16; ++u) s += (int)(kq[u] > k) | ((int)(kq[u] == k) & (int)(q + u < r));
       }
       for (; q < K; ++q) s += (int)(key[q] > k) | ((int)(key[q] == k) & (int)(q < r));
     }
-    const double cs = coef[r] * ldexp(1.0, g - 13 + row_exp(m1[r]));
+    const double cs = cr * ldexp(1.0, g - 13 + row_exp(mr1));
     perm[s] = r;
     coefS[s] = cs;
-    coefS32[s] = ldexp(cs, row_exp(m2[r]));
+    coefS32[s] = ldexp(cs, row_exp(mr2));
   }
   if (t == 0) *gexp = g;
   if (cmask != nullptr)
