@@ -273,11 +273,12 @@ __global__ __launch_bounds__(512) void k_f16_order(const double* __restrict__ co
 // FP32 halves the bytes the kernel loads for it); nch + n8 <= y (with cmask):
 // the chunk c = y - nch - n8 of every plane x of axis 0 is marked in cmask[x]
 // unless |coefS32[s] f0[r][x]| <= 2^-27 for each of its 32 slots. The
-// reconstruction forms the same FP64 product as its rank factor; a rank
-// factor of at most 2^-27 times the scaled f2 (below 2 in magnitude) gives a
-// value of at most 2^-26 (2^-25 in the FP64-f2 tiles), which rounds to zero
-// in both FP16 terms, so an unmarked chunk adds only zeros to the plane's
-// outputs and is skipped without changing a bit.
+// reconstruction forms the same FP64 product as its rank factor; times the
+// FP32 copy of f2 (below 2 in magnitude) it gives at most 2^-26, and so does
+// the FP64-f2 tiles' product (their rank factor carries 2^-e2_r, their f2 is
+// below 2^(e2_r + 1)); that is under half the smallest FP16 subnormal, so both
+// FP16 terms round to zero, an unmarked chunk adds only zeros to the plane's
+// outputs, and it is skipped without changing a bit.
 __global__ __launch_bounds__(64) void k_prep_f16(const double* __restrict__ f,
                                                  const double* __restrict__ f2,
                                                  const double* __restrict__ f0,
