@@ -101,3 +101,29 @@ def test_skipping_tiles_against_oracle(L):
                 first = cat.clone()
             else:
                 assert torch.equal(cat, first), tile
+
+
+def test_many_ranks_keep_their_order(L):
+    # K > 1024: the given order, no chunk skipped; the result against the
+    # oracle's einsum on random factors
+    rng = np.random.default_rng(1405)
+    K, N = 1100, (20, 36, 70)
+    Fh = [rng.standard_normal((K, n)) for n in N]
+    ch = rng.standard_normal(K)
+    dev = torch.device("cuda:0")
+    F = [torch.as_tensor(f, device=dev) for f in Fh]
+    coef = torch.as_tensor(ch, device=dev)
+    boxes = [(0, 0, 0, N[0], N[1], N[2]), (3, 5, 9, 11, 17, 33)]
+    ws = L.reconstruct_prepare(F, coef, "f16x3")
+    plan = L.reconstruct_f16_plan(F, coef, boxes, ws)
+    nch = (K + 31) // 32
+    assert np.array_equal(plan["perm"], np.arange(K))
+    assert np.all(plan["masks"] == np.uint32(0xFFFFFFFF))
+    assert plan["chunk_values"] == nch * sum(b[3] * b[4] * b[5] for b in boxes)
+    outs = L.reconstruct(F, coef, boxes, 1.0, "f16x3", 0, ws)
+    torch.cuda.synchronize()
+    for b, out in zip(boxes, outs):
+        ref = o_reconstruct(Fh, ch, b[:3], b[3:])
+        ref_abs = o_reconstruct([np.abs(f) for f in Fh], np.abs(ch), b[:3], b[3:])
+        rel_mag = np.abs(out.double().cpu().numpy() - ref).max() / np.abs(ref_abs).max()
+        assert rel_mag < gate("f16x3", K), (b, rel_mag)
